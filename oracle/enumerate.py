@@ -84,6 +84,36 @@ def segment_law(p: dict[int, Fraction], qcol: dict[int, Fraction], a: int, b: in
     return out
 
 
+def segment_proposals(p: dict[int, Fraction], qcol: dict[int, Fraction], a: int, b: int,
+                      q_start: Fraction) -> dict[int, Fraction]:
+    """Law of the number of candidates the chain evaluates in [a, b).
+
+    Distinguishes chains with the same edge law but different proposal rules
+    (the paper moves q to the evaluated column's probability whether or not
+    the candidate was accepted)."""
+    out: dict[int, Fraction] = {}
+
+    def walk(pos: int, q: Fraction, cnt: int, w: Fraction):
+        if w == 0:
+            return
+        room = b - 1 - pos
+        if q == 0 or room <= 0:
+            out[cnt] = out.get(cnt, Fraction(0)) + w
+            return
+        stay = (1 - q) ** room
+        if stay:
+            out[cnt] = out.get(cnt, Fraction(0)) + w * stay
+        for L in range(room):
+            j = pos + 1 + L
+            walk(j, qcol[j], cnt + 1, w * (1 - q) ** L * q)
+
+    if a < b:
+        walk(a - 1, q_start, 0, Fraction(1))
+    else:
+        out[0] = Fraction(1)
+    return out
+
+
 def combine(d1: dict, d2: dict) -> dict:
     """Law of the union of two independent accepted sets on disjoint columns."""
     out: dict[frozenset, Fraction] = {}

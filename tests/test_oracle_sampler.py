@@ -95,6 +95,28 @@ def test_uecm_joint_law_and_weights(seg_work):
         assert stats.chi2.sf(chi, max(keep.sum() - 1, 1)) > 1e-6
 
 
+def test_proposal_count_matches_exact_law():
+    # Expected candidates per sample from the exact path law (q moves to the
+    # evaluated column's probability after every candidate, Sec. 2.3).
+    from oracle import enumerate as en
+
+    rng = np.random.default_rng(23)
+    n = 7
+    x = np.exp(rng.normal(0.3, 1.0, n))
+    perm, zs, _, _ = oracle.sorted_params(x)
+    mean, var = 0.0, 0.0
+    for r in range(n - 1):
+        p = {j: en.ubcm_p(zs[r] * zs[j]) for j in range(r, n)}
+        law = en.segment_proposals(p, p, r + 1, n, p[r])
+        m1 = sum(k * w for k, w in law.items())
+        m2 = sum(k * k * w for k, w in law.items())
+        mean += float(m1)
+        var += float(m2 - m1 * m1)
+    R = 20_000
+    props = [oracle.sample_mh(x, None, seed=12, replica=rep, capacity=64).stats["proposals"] for rep in range(R)]
+    assert abs(np.mean(props) - mean) <= 4 * np.sqrt(var / R)
+
+
 def test_ubcm_mean_degree_4sigma_n2000():
     from workloads import cfg1_small
 
