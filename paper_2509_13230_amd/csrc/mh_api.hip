@@ -1,0 +1,39 @@
+// C-ABI entry points for the individual steps (order, bound) and status text.
+// The samplers live in mh_sweep.hip and mh_bf.hip, the expected-degree calls
+// in mh_degree.hip.
+#include "mh_common.hpp"
+#include "mh_internal.hpp"
+
+extern "C" {
+
+mh_status mh_order(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
+                   int32_t* status_dev, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0 || n > 0x7FFFFFFFll) return MH_EINVAL;
+    if (n == 0) return MH_OK;
+    if (!x || !perm || !zs || (y && !ys)) return MH_EINVAL;
+    if (!workspace || ws_bytes < mh::order_workspace_bytes(n)) return MH_EWORKSPACE;
+    return mh::order_nodes(x, y, n, perm, zs, ys, status_dev, nullptr, workspace, ws_bytes, stream);
+}
+
+size_t mh_bound_workspace_bytes(int64_t n) { return mh::bound_workspace_bytes(n); }
+
+mh_status mh_bound(const double* ys, int64_t n, double* c, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0) return MH_EINVAL;
+    if (n == 0) return MH_OK;
+    if (!ys || !c) return MH_EINVAL;
+    if (!workspace || ws_bytes < mh::bound_workspace_bytes(n)) return MH_EWORKSPACE;
+    return mh::bound_suffix_top2(ys, n, c, nullptr, workspace, ws_bytes, stream);
+}
+
+const char* mh_status_string(mh_status s) {
+    switch (s) {
+        case MH_OK: return "ok";
+        case MH_EINVAL: return "invalid argument or parameters";
+        case MH_ECAPACITY: return "output capacity too small";
+        case MH_EHIP: return "HIP runtime error";
+        case MH_EWORKSPACE: return "workspace missing or too small";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Host-side internal interfaces between the translation units of libmh.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "mh.h"
+
+namespace mh {
+
+// Bump allocator over a caller-provided workspace (256-byte aligned pieces).
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0;
+    size_t used = 0;
+    bool overflow = false;
+
+    Arena(void* p, size_t n) : base(static_cast<char*>(p)), size(n) {}
+
+    template <typename T>
+    T* take(size_t count) {
+        size_t off = (used + 255) & ~size_t(255);
+        size_t bytes = count * sizeof(T);
+        used = off + bytes;
+        if (used > size || base == nullptr) {
+            overflow = true;
+            return nullptr;
+        }
+        return reinterpret_cast<T*>(base + off);
+    }
+};
+
+// Counting pass: same sequence of take() calls with no memory behind it.
+struct Sizer {
+    size_t used = 0;
+    template <typename T>
+    void take(size_t count) {
+        used = ((used + 255) & ~size_t(255)) + count * sizeof(T);
+    }
+};
+
+#define MH_HIP_TRY(expr)                              \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return MH_EHIP;         \
+    } while (0)
+
+// ---- exclusive scans: out[0..n] with out[n] = total (in may alias out) ----
+size_t scan_workspace_bytes(int64_t n);
+mh_status scan_exclusive_u64(const uint64_t* in, uint64_t* out, int64_t n, void* ws, size_t ws_bytes,
+                             hipStream_t stream);
+mh_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void* ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+// ---- radix sort of (key, value) pairs ascending by key, stable ----
+size_t radix_workspace_bytes(int64_t n);
+// Sorts keys[0..n) / vals[0..n) using alt buffers of the same size; the result
+// ends in keys/vals (8 passes of 8 bits).
+mh_status radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                         void* ws, size_t ws_bytes, hipStream_t stream);
+
+// ---- sampler pieces ----
+struct SortedView {
+    int32_t* perm = nullptr;
+    double* zs = nullptr;
+    double* ys = nullptr;  // weighted only
+    double* c = nullptr;   // weighted only
+};
+
+size_t order_workspace_bytes(int64_t n);
+mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
+                      int32_t* status, uint64_t* mass_out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+size_t bound_workspace_bytes(int64_t n);
+mh_status bound_suffix_top2(const double* ys, int64_t n, double* c, int32_t* status, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+}  // namespace mh

@@ -1,0 +1,226 @@
+// Node order (ascending alpha, or alpha + beta, i.e. descending x or x*y:
+// Sec. 2.4 step (i), first line of Alg. 1) and the bound of Sec. 2.5
+// (product of the two largest y among the ranks not yet processed).
+#include "mh_common.hpp"
+#include "mh_internal.hpp"
+
+namespace mh {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict__ x, const double* __restrict__ y,
+                                                        int64_t n, uint64_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ vals, int32_t* status) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const double xi = x[i];
+    bool ok = (xi >= 0.0) && isfinite(xi);
+    double z = xi;
+    if (y) {
+        const double yi = y[i];
+        ok = ok && (yi >= 0.0) && isfinite(yi);
+        z = xi * yi;
+        ok = ok && isfinite(z);
+    }
+    if (!ok) raise_status(status, MH_EINVAL);
+    keys[i] = desc_key(ok ? z : 0.0);
+    vals[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(kThreads) void k_finish_order(const uint64_t* __restrict__ keys,
+                                                           const uint32_t* __restrict__ vals, int64_t n,
+                                                           int32_t* __restrict__ perm, double* __restrict__ zs,
+                                                           const double* __restrict__ y, double* __restrict__ ys,
+                                                           uint64_t* __restrict__ mass, int32_t* status) {
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t id = vals[r];
+    const double z = key_value(keys[r]);
+    perm[r] = (int32_t)id;
+    zs[r] = z;
+    if (ys) ys[r] = y[id];
+    if (mass) mass[r] = mass_q(z);
+    if (r == 0 && !isfinite(z * z)) raise_status(status, MH_EINVAL);
+}
+
+// ---- suffix top-2 of ys: the monoid keeps the two largest values (multiset) ----
+struct Top2 {
+    double a, b;  // a >= b; -1 marks "none" (inputs are >= 0)
+};
+
+__device__ __forceinline__ Top2 top2_combine(Top2 p, Top2 q) {
+    Top2 r;
+    if (p.a >= q.a) {
+        r.a = p.a;
+        r.b = fmax(p.b, q.a);
+    } else {
+        r.a = q.a;
+        r.b = fmax(q.b, p.a);
+    }
+    return r;
+}
+
+__device__ __forceinline__ Top2 top2_shfl_down(Top2 v, int off) {
+    Top2 r;
+    r.a = __shfl_down(v.a, off, kWave);
+    r.b = __shfl_down(v.b, off, kWave);
+    return r;
+}
+
+constexpr int kBoundItems = 8;
+constexpr int kBoundTile = kThreads * kBoundItems;
+
+// Suffix (towards higher ranks) inclusive scan of per-thread values over the block.
+__device__ __forceinline__ Top2 block_suffix_exclusive(Top2 v, Top2* lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    Top2 inc = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        Top2 u = top2_shfl_down(inc, off);
+        if (lane + off < kWave) inc = top2_combine(inc, u);
+    }
+    if (lane == 0) lds[wave] = inc;  // wave's total
+    __syncthreads();
+    Top2 after = {-1.0, -1.0};
+    for (int w = kThreads / kWave - 1; w > wave; --w) after = top2_combine(after, lds[w]);
+    // exclusive within the wave: the value of the next lane's inclusive
+    Top2 nxt = top2_shfl_down(inc, 1);
+    Top2 excl = (lane + 1 < kWave) ? top2_combine(nxt, after) : after;
+    __syncthreads();
+    return excl;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bound_tile_aggr(const double* __restrict__ ys, int64_t n,
+                                                              Top2* __restrict__ aggr) {
+    __shared__ Top2 lds[kThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kBoundTile;
+    Top2 v = {-1.0, -1.0};
+    for (int k = 0; k < kBoundItems; ++k) {
+        const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+        if (i < n) v = top2_combine(v, Top2{ys[i], -1.0});
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        Top2 u;
+        u.a = __shfl_xor(v.a, off, kWave);
+        u.b = __shfl_xor(v.b, off, kWave);
+        v = top2_combine(v, u);
+    }
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Top2 t = lds[0];
+        for (int w = 1; w < kThreads / kWave; ++w) t = top2_combine(t, lds[w]);
+        aggr[blockIdx.x] = t;
+    }
+}
+
+// One block: exclusive suffix combine of the tile aggregates, in place.
+__global__ __launch_bounds__(kThreads) void k_bound_aggr_scan(Top2* aggr, int64_t nb) {
+    __shared__ Top2 lds[kThreads / kWave];
+    Top2 carry = {-1.0, -1.0};
+    const int64_t nchunks = (nb + kThreads - 1) / kThreads;
+    for (int64_t ch = nchunks - 1; ch >= 0; --ch) {
+        const int64_t i = ch * kThreads + threadIdx.x;
+        Top2 v = (i < nb) ? aggr[i] : Top2{-1.0, -1.0};
+        Top2 excl = block_suffix_exclusive(v, lds);
+        Top2 out = top2_combine(excl, carry);
+        // chunk total = combine of everything in the chunk (thread 0's inclusive)
+        Top2 tot0 = top2_combine(v, excl);
+        __shared__ Top2 chunk_total;
+        if (threadIdx.x == 0) chunk_total = tot0;
+        __syncthreads();
+        if (i < nb) aggr[i] = out;
+        carry = top2_combine(carry, chunk_total);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_bound_tile_scan(const double* __restrict__ ys, int64_t n,
+                                                              const Top2* __restrict__ aggr_excl,
+                                                              double* __restrict__ c, int32_t* status) {
+    __shared__ Top2 lds[kThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kBoundTile + (int64_t)threadIdx.x * kBoundItems;
+    double vals[kBoundItems];
+    Top2 v = {-1.0, -1.0};
+#pragma unroll
+    for (int k = 0; k < kBoundItems; ++k) {
+        const int64_t i = base + k;
+        vals[k] = (i < n) ? ys[i] : -1.0;
+        v = top2_combine(v, Top2{vals[k], -1.0});
+    }
+    Top2 after = block_suffix_exclusive(v, lds);
+    after = top2_combine(after, aggr_excl[blockIdx.x]);
+    bool bad = false;
+#pragma unroll
+    for (int k = kBoundItems - 1; k >= 0; --k) {
+        const int64_t r = base + k;
+        after = top2_combine(Top2{vals[k], -1.0}, after);
+        if (r < n) {
+            const double Y = (after.b < 0.0) ? 0.0 : after.a * after.b;
+            c[r] = 1.0 - Y;
+            if (r < n - 1 && !(Y < 1.0)) bad = true;
+        }
+    }
+    if (bad) raise_status(status, MH_EINVAL);
+}
+
+}  // namespace
+
+size_t order_workspace_bytes(int64_t n) {
+    Sizer s;
+    s.take<uint64_t>(n);  // keys
+    s.take<uint64_t>(n);  // keys alt
+    s.take<uint32_t>(n);  // vals
+    s.take<uint32_t>(n);  // vals alt
+    return s.used + radix_workspace_bytes(n) + 256;
+}
+
+mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
+                      int32_t* status, uint64_t* mass_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n <= 0) return MH_OK;
+    Arena ar(ws, ws_bytes);
+    uint64_t* keys = ar.take<uint64_t>(n);
+    uint64_t* keys_alt = ar.take<uint64_t>(n);
+    uint32_t* vals = ar.take<uint32_t>(n);
+    uint32_t* vals_alt = ar.take<uint32_t>(n);
+    if (ar.overflow) return MH_EWORKSPACE;
+    const size_t off = (ar.used + 255) & ~size_t(255);
+    const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_prep_keys, dim3(grid), dim3(kThreads), 0, stream, x, y, n, keys, vals, status);
+    MH_HIP_TRY(hipGetLastError());
+    mh_status st = radix_sort_u64(keys, vals, keys_alt, vals_alt, n, ar.base + off, ws_bytes > off ? ws_bytes - off : 0,
+                                  stream);
+    if (st != MH_OK) return st;
+    hipLaunchKernelGGL(k_finish_order, dim3(grid), dim3(kThreads), 0, stream, keys, vals, n, perm, zs, y, y ? ys : nullptr,
+                       mass_out, status);
+    MH_HIP_TRY(hipGetLastError());
+    return MH_OK;
+}
+
+size_t bound_workspace_bytes(int64_t n) {
+    const int64_t nb = (n + kBoundTile - 1) / kBoundTile;
+    Sizer s;
+    s.take<Top2>(nb + 1);
+    return s.used + 256;
+}
+
+mh_status bound_suffix_top2(const double* ys, int64_t n, double* c, int32_t* status, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+    if (n <= 0) return MH_OK;
+    const int64_t nb = (n + kBoundTile - 1) / kBoundTile;
+    Arena ar(ws, ws_bytes);
+    Top2* aggr = ar.take<Top2>(nb + 1);
+    if (!aggr) return MH_EWORKSPACE;
+    hipLaunchKernelGGL(k_bound_tile_aggr, dim3((unsigned)nb), dim3(kThreads), 0, stream, ys, n, aggr);
+    MH_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_bound_aggr_scan, dim3(1), dim3(kThreads), 0, stream, aggr, nb);
+    MH_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_bound_tile_scan, dim3((unsigned)nb), dim3(kThreads), 0, stream, ys, n, aggr, c, status);
+    MH_HIP_TRY(hipGetLastError());
+    return MH_OK;
+}
+
+}  // namespace mh

@@ -1,0 +1,87 @@
+"""Host-side checks of the C-ABI library: it loads, exports every symbol that
+include/mh.h declares, and its argument checks fail before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mh.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mh_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2509_13230_amd as mh
+
+    if not os.path.exists(mh.library_path()):
+        mh_build = pytest.importorskip("paper_2509_13230_amd.build")
+        mh_build.build(verbose=False)
+    return mh.lib()
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ("mh_sample_unweighted", "mh_sample_weighted", "mh_sample_bruteforce", "mh_expected_degree_fwd",
+                 "mh_expected_degree_bwd", "mh_order", "mh_bound", "mh_plan_counts", "mh_workspace_bytes"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_workspace_sizes_grow_with_n(L):
+    import paper_2509_13230_amd as mh
+
+    p = mh.PlanParams(32, 0)
+    a = L.mh_workspace_bytes(1000, 0, ctypes.byref(p))
+    b = L.mh_workspace_bytes(1_000_000, 0, ctypes.byref(p))
+    c = L.mh_workspace_bytes(1_000_000, 1, ctypes.byref(p))
+    assert 0 < a < b < c
+    # roughly linear: a few tens of bytes per node
+    assert b < 200 * 1_000_000
+    assert L.mh_bruteforce_workspace_bytes(50_000) > 0
+
+
+def test_argument_errors_return_before_device_work(L):
+    n = ctypes.c_int64(0)
+    # missing n_edges_host
+    assert L.mh_sample_unweighted(None, 10, 1, 0, None, None, None, 0, None, None, 0, None, None) == -1
+    # negative n
+    assert L.mh_sample_unweighted(None, -1, 1, 0, None, None, None, 0, ctypes.byref(n), None, 0, None, None) == -1
+    # n = 0 is an empty sample
+    assert L.mh_sample_unweighted(None, 0, 1, 0, None, None, None, 0, ctypes.byref(n), None, 0, None, None) == 0
+    assert n.value == 0
+    # capacity > 0 needs output pointers
+    assert L.mh_sample_unweighted(ctypes.c_void_p(16), 10, 1, 0, None, None, None, 5, ctypes.byref(n), None, 0,
+                                  None, None) == -1
+    # workspace too small
+    assert L.mh_sample_unweighted(ctypes.c_void_p(16), 10, 1, 0, None, ctypes.c_void_p(16), ctypes.c_void_p(16), 5,
+                                  ctypes.byref(n), None, 0, None, None) == -4
+    # negative plan parameter
+    import paper_2509_13230_amd as mh
+
+    bad = mh.PlanParams(-3, 0)
+    assert L.mh_sample_unweighted(ctypes.c_void_p(16), 10, 1, 0, ctypes.byref(bad), ctypes.c_void_p(16),
+                                  ctypes.c_void_p(16), 5, ctypes.byref(n), ctypes.c_void_p(256), 1 << 20, None,
+                                  None) == -1
+    assert L.mh_status_string(-2) == b"output capacity too small"
+
+
+def test_binding_fails_loudly_without_device():
+    import torch
+
+    import paper_2509_13230_amd as mh
+
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    with pytest.raises(TypeError):
+        mh.sample_unweighted(torch.zeros(10, dtype=torch.float64))
