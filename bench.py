@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X sampler on the N = 1,000,000 unweighted workload.
+
+One step = one full sample: node order (radix sort), plan, segmented sweep
+with edge compaction, and the edge-count readback, on parameters already
+resident in HBM.  Target degrees follow a discrete power law (exponent 2.1,
+k in [1, 10^4]) and x is fitted to them on the device (untimed).  Every step
+draws a new replica (a new sample).
+
+Prints one JSON line (rank 0, one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sampled edges/s (unweighted, N=1M) + replicas/s batched vs plain, same GPU"
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes per cycle at 2.4 GHz (one VALU instruction
+# of a 64-wide wave issues over 4 cycles): 39.3e12 lane-operations/s for
+# full-rate 32-bit integer and binary64 vector instructions.
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+
+# VALU instructions of one step of the sweep on its common path (Philox block,
+# the two uniforms, log and log1p, the skip division, the candidate load and
+# the acceptance test), counted in the gfx950 code of k_sweep<false,false>;
+# loop, refill and staging instructions are not counted as work.
+SWEEP_VALU_PER_STEP = 313
+
+
+class HipEvents:
+    def __init__(self, n: int):
+        self.rt = ctypes.CDLL("libamdhip64.so")
+        self.rt.hipEventCreate.argtypes = [ctypes.c_void_p]
+        self.rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.rt.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.arr = (ctypes.c_void_p * n)()
+        for i in range(n):
+            ev = ctypes.c_void_p()
+            rc = self.rt.hipEventCreate(ctypes.byref(ev))
+            if rc != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.arr[i] = ev.value
+
+    @property
+    def address(self) -> int:
+        return ctypes.addressof(self.arr)
+
+    def elapsed_ms(self, a: int, b: int) -> float:
+        self.rt.hipEventSynchronize(self.arr[b])
+        out = ctypes.c_float(0)
+        rc = self.rt.hipEventElapsedTime(ctypes.byref(out), self.arr[a], self.arr[b])
+        if rc != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(out.value)
+
+
+def cpu_baseline(x: np.ndarray, seed: int, seg_work: int, budget_s: float) -> dict:
+    """The CPU oracle (sequential, one thread) on whole samples of the same workload."""
+    import oracle
+
+    oracle.build()
+    t_total = 0.0
+    edges = 0
+    reps = 0
+    while reps < 1 or (t_total < budget_s and reps < 20):
+        t0 = time.perf_counter()
+        s = oracle.sample_mh(x, None, seed=seed, replica=10_000 + reps, seg_work=seg_work, capacity=int(2.5e6))
+        t_total += time.perf_counter() - t0
+        edges += s.n_edges
+        reps += 1
+    return {"value": edges / t_total, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} whole samples of the N=1M workload (order + plan + sequential sweep), "
+                      f"{t_total:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seg-work", type=int, default=32)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(a sample's rows, or a batch's samples, would be sharded across GPUs with no "
+              "communication; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2509_13230_amd as mh
+    import workloads
+    from paper_2509_13230_amd.fit import fit_ubcm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    k_target = workloads.cfg2_degrees(seed=2, n=args.n)
+    t0 = time.perf_counter()
+    fit = fit_ubcm(k_target, tol=1e-10)
+    t_fit = time.perf_counter() - t0
+    x_np = fit.x
+    x = torch.as_tensor(x_np, device=dev)
+    n = x.numel()
+    print(f"# fit: {fit.iterations} iterations, residual {fit.residual:.2e}, {t_fit:.2f} s", file=sys.stderr,
+          flush=True)
+
+    L = mh.lib()
+    plan = mh.PlanParams(args.seg_work, 0, None)
+    ws = torch.empty(L.mh_workspace_bytes(n, 0, ctypes.byref(plan)), dtype=torch.uint8, device=dev)
+    s0, d0, st0 = mh.sample_unweighted(x, seed=args.seed, replica=0, seg_work=args.seg_work, stats=True,
+                                       workspace=ws)
+    cap = int(len(s0) * 1.05) + 65536
+    src = torch.empty(cap, dtype=torch.int32, device=dev)
+    dst = torch.empty(cap, dtype=torch.int32, device=dev)
+    ev = HipEvents(4)
+
+    def step(replica, events=None):
+        s, _ = mh.sample_unweighted(x, seed=args.seed, replica=replica, seg_work=args.seg_work, out=(src, dst),
+                                    workspace=ws, stage_events=events)
+        return s.numel()
+
+    for w in range(args.warmup):
+        step(1 + w)
+    torch.cuda.synchronize()
+    replicas = [1000 + i for i in range(args.steps)]
+    edges = 0
+    stage = np.zeros(3)
+    t0 = time.perf_counter()
+    for r in replicas:
+        edges += step(r, ev.address)
+        stage += [ev.elapsed_ms(0, 1), ev.elapsed_ms(1, 2), ev.elapsed_ms(2, 3)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    value = edges / elapsed
+
+    # algorithmic work of the timed samples (same seeds/replicas, counted untimed)
+    steps_total = 0
+    for r in replicas:
+        _, _, st = mh.sample_unweighted(x, seed=args.seed, replica=r, seg_work=args.seg_work, stats=True,
+                                        out=(src, dst), workspace=ws)
+        steps_total += st["steps"]
+    sweep_ms = stage[2] / args.steps
+    achieved_lane_ops = steps_total / args.steps * SWEEP_VALU_PER_STEP / (sweep_ms * 1e-3)
+    roof = {"bound": "alu", "kernel": "k_sweep (unweighted)",
+            "achieved": achieved_lane_ops / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
+            "frac": achieved_lane_ops / PEAK_LANE_OPS, "traffic": None,
+            "work_per_launch": f"{steps_total / args.steps:.0f} steps x {SWEEP_VALU_PER_STEP} VALU lane-ops",
+            "avg_launch_ms": sweep_ms}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "UBCM, N=1,000,000, power-law target degrees (exponent 2.1, k in [1, 10^4]), "
+                               "x fitted (class-compressed fixed point), one sample per step",
+                   "n": n, "seg_work": args.seg_work, "mean_edges_per_sample": edges / args.steps,
+                   "fit_residual": fit.residual},
+        "stages_ms": {"order": stage[0] / args.steps, "bound_plan": stage[1] / args.steps,
+                      "sweep": stage[2] / args.steps},
+        "sweep_steps_per_sample": steps_total / args.steps,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x_np, args.seed, args.seg_work, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -59,7 +59,14 @@ typedef enum {
 typedef struct {
     int32_t seg_work;
     uint32_t flags; /* reserved, must be 0 */
+    /* Optional stage timing: NULL, or an array of MH_STAGE_EVENTS events made
+     * by the caller (hipEventCreate).  The samplers record them on `stream` at
+     * the start, after the order step, after the bound and plan steps, and after
+     * the sweep.  Recording adds no synchronisation. */
+    hipEvent_t* stage_events;
 } mh_plan_params;
+
+#define MH_STAGE_EVENTS 4
 
 typedef struct {
     int64_t steps;       /* skip draws, including the draw that ends each segment */

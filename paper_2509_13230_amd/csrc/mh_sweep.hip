@@ -377,11 +377,14 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
     void* scratch = ar.base + off;
     const size_t scratch_bytes = ws_bytes - off;
 
+    hipEvent_t* ev = plan ? plan->stage_events : nullptr;
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[0], stream));
     hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, L.ctr);
     MH_HIP_TRY(hipGetLastError());
     int32_t* status = &L.ctr->status;
     mh_status st = order_nodes(x, y, n, L.perm, L.zs, L.ys, status, L.P, scratch, scratch_bytes, stream);
     if (st != MH_OK) return st;
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[1], stream));
     if (weighted) {
         st = bound_suffix_top2(L.ys, n, L.c, status, scratch, scratch_bytes, stream);
         if (st != MH_OK) return st;
@@ -399,6 +402,7 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
         if (st != MH_OK) return st;
     }
 
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[2], stream));
     SweepArgs A;
     A.zs = L.zs;
     A.ys = L.ys;
@@ -425,6 +429,7 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
         else hipLaunchKernelGGL((k_sweep<false, false>), grid, dim3(kThreads), 0, stream, A);
     }
     MH_HIP_TRY(hipGetLastError());
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[3], stream));
 
     Counters hc;
     MH_HIP_TRY(hipMemcpyAsync(&hc, L.ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
