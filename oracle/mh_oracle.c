@@ -260,7 +260,7 @@ static int32_t draw_weight(double u, double b, int64_t* saturated, int* tie) {
      stops once j passes the end of the segment;
      it accepts j with probability p_rj / q, then sets q to the probability at j
      (the true p for UBCM, the bound p^ for UECM) whether or not j was accepted.
-   Randomness: one Philox block per step, counter (step, id of r, replica,
+   Randomness: one Philox block per step, counter (step, rank r, replica,
    2*segment + 0); U1 drives the skip, U2 the acceptance; a second block with
    kind 1 gives the weight.  Key = seed.
    Floating point:  L = floor(-log U1 / log1p(t_q))          (UBCM, 1-q = 1/(1+t_q))
@@ -324,7 +324,7 @@ int64_t mho_sample_mh(const double* x, const double* y, int64_t n, uint64_t seed
             uint32_t step = 0;
             for (;;) {
                 if (tq == 0.0) break;
-                uint32_t ctr[4] = {step, (uint32_t)id_r, replica, (uint32_t)(g << 1)};
+                uint32_t ctr[4] = {step, (uint32_t)r, replica, (uint32_t)(g << 1)};
                 uint32_t u[4];
                 mho_philox4x32_10(ctr, key, u);
                 ++st.steps;
@@ -351,7 +351,7 @@ int64_t mho_sample_mh(const double* x, const double* y, int64_t n, uint64_t seed
                 if (lhs < rhs) {
                     int32_t wt = 0;
                     if (y) {
-                        uint32_t ctr2[4] = {step, (uint32_t)id_r, replica, (uint32_t)((g << 1) | 1)};
+                        uint32_t ctr2[4] = {step, (uint32_t)r, replica, (uint32_t)((g << 1) | 1)};
                         uint32_t v[4];
                         mho_philox4x32_10(ctr2, key, v);
                         double U3 = mho_u53(v[0], v[1]);

@@ -86,6 +86,10 @@ __global__ __launch_bounds__(kThreads) void k_row_plan(const double* __restrict_
     if (hn) hn[r] = total >= 2 ? (uint64_t)total : 0ull;
 }
 
+struct HeavyRec {
+    int32_t r, g, a, b;
+};
+
 struct SweepArgs {
     const double* zs;
     const double* ys;
@@ -96,6 +100,8 @@ struct SweepArgs {
     const uint64_t* mq;
     const uint64_t* P;
     const uint64_t* hoff;  // null when unsegmented
+    const HeavyRec* rec;   // records of the first rec_cap heavy items
+    int64_t rec_cap;
     int64_t n;
     int32_t T;
     uint32_t key0, key1;
@@ -112,60 +118,48 @@ __device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* __restrict__ 
     return lo;
 }
 
-struct Chain {
-    int64_t pos, end;
-    double s, cr, ysr, tq;
-    uint32_t id, step, tag;
-};
-
-// Locate item `it` and set up its chain.  Returns false for items that draw nothing.
-template <bool WEIGHTED>
-__device__ __forceinline__ bool setup_item(const SweepArgs& A, int64_t it, int64_t H, Chain& ch, uint32_t& segs) {
-    int64_t r, g, a, b;
+// Row, segment index and column range of heavy item `it` (it < H).
+__device__ HeavyRec heavy_record(const SweepArgs& A, int64_t it) {
     const int64_t n = A.n;
-    if (it < H) {
-        int64_t lo = 0, hi = n;  // first row index with hoff > it, minus one
-        while (lo < hi) {
-            const int64_t mid = lo + (hi - lo) / 2;
-            if (A.hoff[mid] > (uint64_t)it) hi = mid; else lo = mid + 1;
-        }
-        r = lo - 1;
-        g = it - (int64_t)A.hoff[r];
-        const int64_t nsg = (int64_t)(A.hoff[r + 1] - A.hoff[r]);
-        const int64_t J = A.jend[r];
-        const int64_t T = A.T;
-        const int64_t nd = (J - r - 1 + T - 1) / T;
-        if (g < nd) {
-            a = r + 1 + g * T;
-            b = a + T < J ? a + T : J;
-        } else {
-            const int64_t kk = g - nd;
-            const int64_t ns = nsg - nd;
-            const uint64_t base = A.P[J];
-            const uint64_t m = A.mq[r];
-            a = (kk == 0) ? J : lower_bound_u64(A.P, J, n, base + (uint64_t)kk * m);
-            b = (kk == ns - 1) ? n : lower_bound_u64(A.P, J, n, base + (uint64_t)(kk + 1) * m);
-        }
-    } else {
-        r = it - H;
-        if (A.nseg[r] != 1) return false;
-        g = 0;
-        a = r + 1;
-        b = n;
+    int64_t lo = 0, hi = n;  // first row index with hoff > it, minus one
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (A.hoff[mid] > (uint64_t)it) hi = mid; else lo = mid + 1;
     }
-    if (a >= b) return false;
-    ++segs;
-    ch.s = A.zs[r];
-    ch.id = (uint32_t)A.perm[r];
-    ch.cr = WEIGHTED ? A.c[r] : 1.0;
-    ch.ysr = WEIGHTED ? A.ys[r] : 0.0;
-    ch.pos = a - 1;
-    ch.end = b;
-    ch.tq = ch.s * A.zs[a - 1];
-    ch.step = 0;
-    ch.tag = (uint32_t)(g << 1);
-    return ch.tq != 0.0;
+    const int64_t r = lo - 1;
+    const int64_t g = it - (int64_t)A.hoff[r];
+    const int64_t nsg = (int64_t)(A.hoff[r + 1] - A.hoff[r]);
+    const int64_t J = A.jend[r];
+    const int64_t T = A.T;
+    const int64_t nd = (J - r - 1 + T - 1) / T;
+    int64_t a, b;
+    if (g < nd) {
+        a = r + 1 + g * T;
+        b = a + T < J ? a + T : J;
+    } else {
+        const int64_t kk = g - nd;
+        const int64_t ns = nsg - nd;
+        const uint64_t base = A.P[J];
+        const uint64_t m = A.mq[r];
+        a = (kk == 0) ? J : lower_bound_u64(A.P, J, n, base + (uint64_t)kk * m);
+        b = (kk == ns - 1) ? n : lower_bound_u64(A.P, J, n, base + (uint64_t)(kk + 1) * m);
+    }
+    return HeavyRec{(int32_t)r, (int32_t)g, (int32_t)a, (int32_t)b};
 }
+
+__global__ __launch_bounds__(kThreads) void k_heavy_records(SweepArgs A, HeavyRec* __restrict__ rec) {
+    if (A.ctr->status != 0) return;
+    const int64_t H = (int64_t)A.hoff[A.n];
+    const int64_t lim = H < A.rec_cap ? H : A.rec_cap;
+    for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < lim; it += (int64_t)gridDim.x * kThreads)
+        rec[it] = heavy_record(A, it);
+}
+
+// Lane states of the sweep.  Every loop iteration a lane consumes the global
+// loads it issued in the previous iteration and issues the next ones, so one
+// memory round trip per iteration is overlapped with the Philox block and the
+// logarithm of the next draw, which need no loaded data.
+enum : uint32_t { S_IDLE = 0, S_REC, S_LOAD, S_STEP, S_DONE };
 
 template <bool WEIGHTED, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs A) {
@@ -179,84 +173,158 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs A) {
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t H = A.hoff ? (int64_t)A.hoff[A.n] : 0;
     const int64_t total = H + (A.n > 1 ? A.n - 1 : 0);
+    const int32_t n32 = (int32_t)A.n;
     const uint64_t lt = lanemask_lt();
 
     WaveStage<WEIGHTED> stage{s_src[wave], s_dst[wave], WEIGHTED ? s_w[wave] : nullptr, 0u};
 
     uint32_t st_steps = 0, st_props = 0, st_acc = 0, st_segs = 0, st_sat = 0;
-    Chain ch;
-    ch.pos = ch.end = 0;
-    ch.s = ch.cr = ch.ysr = ch.tq = 0.0;
-    ch.id = ch.step = ch.tag = 0;
-    bool active = false;
+    uint32_t state = S_IDLE;
+    bool check_light = false;
+    int32_t r = 0, pos = 0, end = 0, jc = 0;
+    uint32_t step = 0, tag = 0, scand = 0;
+    int32_t id = 0;
+    double s = 0.0, cr = 1.0, ysr = 0.0, tq = 0.0, U2 = 0.0;
+    // values in flight from the previous iteration's loads
+    double ld_s = 0.0, ld_z = 0.0, ld_c = 1.0, ld_y = 0.0;
+    int32_t ld_id = 0, ld_n = 1;
+    HeavyRec ld_rec{0, 0, 0, 0};
     int64_t kbase = 0;
 
     for (;;) {
-        const uint64_t idle = __ballot(!active);
-        if (idle) {
-            if (!active) {
-                const int64_t it = gwave + (kbase + __popcll(idle & lt)) * nwaves;
-                if (it < total) active = setup_item<WEIGHTED>(A, it, H, ch, st_segs);
-            }
-            kbase += __popcll(idle);
+        // 1. the next draw of every lane that will draw this iteration (no loaded data needed)
+        const bool draws = (state == S_STEP) || (state == S_LOAD);
+        double E = 0.0, U2n = 0.0;
+        if (draws) {
+            const u32x4 R = philox4x32_10(step, (uint32_t)r, A.replica, tag, A.key0, A.key1);
+            E = -log(uniform53(R.v0, R.v1));
+            U2n = uniform53(R.v2, R.v3);
         }
-        if (__ballot(active) == 0) {
-            if (gwave + kbase * nwaves >= total) break;
-            continue;
-        }
-        bool acc = false;
+        // 2. consume the loads of the previous iteration
+        bool acc = false, go = false;
         int32_t dst_id = 0, wt = 0;
-        if (active) {
-            const u32x4 R = philox4x32_10(ch.step, ch.id, A.replica, ch.tag, A.key0, A.key1);
-            ++st_steps;
-            const double U1 = uniform53(R.v0, R.v1);
-            const double U2 = uniform53(R.v2, R.v3);
-            const double lq = WEIGHTED ? log1p(ch.tq / ch.cr) : log1p(ch.tq);
-            const double d = -log(U1) / lq;
-            const double room = (double)(ch.end - 1 - ch.pos);
-            if (d >= room) {
-                active = false;
+        if (state == S_STEP) {
+            const double t = s * ld_z;
+            double lhs, rhs;
+            if (WEIGHTED) {
+                const double e = 1.0 - ysr * ld_y;
+                lhs = (U2 * tq) * (e + t);
+                rhs = t * (cr + tq);
             } else {
-                const int64_t j = ch.pos + 1 + (int64_t)d;
-                const double t = ch.s * A.zs[j];
-                double lhs, rhs, ysj = 0.0;
+                lhs = (U2 * tq) * (1.0 + t);
+                rhs = t * (1.0 + tq);
+            }
+            ++st_props;
+            if (lhs < rhs) {
+                acc = true;
+                ++st_acc;
+                dst_id = ld_id;
                 if (WEIGHTED) {
-                    ysj = A.ys[j];
-                    const double e = 1.0 - ch.ysr * ysj;
-                    lhs = (U2 * ch.tq) * (e + t);
-                    rhs = t * (ch.cr + ch.tq);
-                } else {
-                    lhs = (U2 * ch.tq) * (1.0 + t);
-                    rhs = t * (1.0 + ch.tq);
-                }
-                ++st_props;
-                if (lhs < rhs) {
-                    acc = true;
-                    ++st_acc;
-                    dst_id = A.perm[j];
-                    if (WEIGHTED) {
-                        const u32x4 V = philox4x32_10(ch.step, ch.id, A.replica, ch.tag | 1u, A.key0, A.key1);
-                        const double U3 = uniform53(V.v0, V.v1);
-                        const double bb = ch.ysr * ysj;
-                        if (bb == 0.0) {
-                            wt = 1;
+                    const double bb = ysr * ld_y;
+                    if (bb == 0.0) {
+                        wt = 1;
+                    } else {
+                        const u32x4 V = philox4x32_10(scand, (uint32_t)r, A.replica, tag | 1u, A.key0, A.key1);
+                        const double ratio = log(uniform53(V.v0, V.v1)) / log(bb);
+                        if (ratio >= 2147483646.0) {
+                            wt = 0x7FFFFFFF;
+                            ++st_sat;
                         } else {
-                            const double ratio = log(U3) / log(bb);
-                            if (ratio >= 2147483646.0) {
-                                wt = 0x7FFFFFFF;
-                                ++st_sat;
-                            } else {
-                                wt = 1 + (int32_t)ratio;
-                            }
+                            wt = 1 + (int32_t)ratio;
                         }
                     }
                 }
-                ch.tq = t;
-                ch.pos = j;
-                ++ch.step;
+            }
+            tq = t;
+            pos = jc;
+            go = true;
+        } else if (state == S_LOAD) {
+            if (check_light && ld_n != 1) {
+                state = S_IDLE;
+            } else {
+                s = ld_s;
+                id = ld_id;
+                tq = s * ld_z;
+                cr = WEIGHTED ? ld_c : 1.0;
+                ysr = WEIGHTED ? ld_y : 0.0;
+                ++st_segs;
+                go = true;
+            }
+        } else if (state == S_REC) {
+            r = ld_rec.r;
+            pos = ld_rec.a - 1;
+            end = ld_rec.b;
+            tag = (uint32_t)ld_rec.g << 1;
+            step = 0;
+            check_light = false;
+            if (ld_rec.a >= ld_rec.b) {
+                state = S_IDLE;
+            } else {
+                ld_s = A.zs[r];
+                ld_z = A.zs[pos];
+                ld_id = A.perm[r];
+                if (WEIGHTED) {
+                    ld_c = A.c[r];
+                    ld_y = A.ys[r];
+                }
+                state = S_LOAD;
             }
         }
-        stage.push(acc, (int32_t)ch.id, dst_id, wt, A.out);
+        // 3. the skip: candidate pos + 1 + floor(-log U1 / -log(1 - q)), or the end of the segment
+        if (go) {
+            if (tq == 0.0) {
+                state = S_IDLE;
+            } else {
+                ++st_steps;
+                const double lq = WEIGHTED ? log1p(tq / cr) : log1p(tq);
+                const double d = E / lq;
+                const double room = (double)(end - 1 - pos);
+                if (d >= room) {
+                    state = S_IDLE;
+                } else {
+                    jc = pos + 1 + (int32_t)d;
+                    U2 = U2n;
+                    scand = step;
+                    ++step;
+                    ld_z = A.zs[jc];
+                    ld_id = A.perm[jc];
+                    if (WEIGHTED) ld_y = A.ys[jc];
+                    state = S_STEP;
+                }
+            }
+        }
+        // 4. idle lanes take the wave's next items and issue their loads
+        const uint64_t idle = __ballot(state == S_IDLE);
+        if (idle) {
+            if (state == S_IDLE) {
+                const int64_t it = gwave + (kbase + __popcll(idle & lt)) * nwaves;
+                if (it >= total) {
+                    state = S_DONE;
+                } else if (it < H) {
+                    ld_rec = (it < A.rec_cap) ? A.rec[it] : heavy_record(A, it);
+                    state = S_REC;
+                } else {
+                    r = (int32_t)(it - H);
+                    pos = r;
+                    end = n32;
+                    tag = 0;
+                    step = 0;
+                    check_light = true;
+                    ld_n = A.nseg[r];
+                    ld_s = A.zs[r];
+                    ld_z = ld_s;
+                    ld_id = A.perm[r];
+                    if (WEIGHTED) {
+                        ld_c = A.c[r];
+                        ld_y = A.ys[r];
+                    }
+                    state = S_LOAD;
+                }
+            }
+            kbase += __popcll(idle);
+        }
+        stage.push(acc, id, dst_id, wt, A.out);
+        if (__ballot(state != S_DONE) == 0) break;
     }
     stage.flush(A.out);
 
@@ -287,9 +355,15 @@ struct Layout {
     int32_t* jend;
     uint64_t* mq;
     uint64_t* hoff;
+    HeavyRec* rec;
+    int64_t rec_cap;
     char* scratch;
     size_t scratch_bytes;
 };
+
+// Records kept for up to this many heavy items; items beyond it are located
+// inside the sweep (slower, same result).
+int64_t heavy_record_capacity(int64_t n) { return n + 4096; }
 
 template <typename A>
 void carve(A& ar, int64_t n, bool weighted, bool segmented, Layout* L) {
@@ -303,6 +377,8 @@ void carve(A& ar, int64_t n, bool weighted, bool segmented, Layout* L) {
     auto jend = ar.template take<int32_t>(segmented ? n : 0);
     auto mq = ar.template take<uint64_t>(segmented ? n : 0);
     auto hoff = ar.template take<uint64_t>(segmented ? n + 1 : 0);
+    const int64_t rec_cap = segmented ? heavy_record_capacity(n) : 0;
+    auto rec = ar.template take<HeavyRec>(rec_cap);
     if (L) {
         L->ctr = (Counters*)c;
         L->perm = (int32_t*)perm;
@@ -314,6 +390,8 @@ void carve(A& ar, int64_t n, bool weighted, bool segmented, Layout* L) {
         L->jend = segmented ? (int32_t*)jend : nullptr;
         L->mq = segmented ? (uint64_t*)mq : nullptr;
         L->hoff = segmented ? (uint64_t*)hoff : nullptr;
+        L->rec = (HeavyRec*)rec;
+        L->rec_cap = rec_cap;
     }
 }
 
@@ -339,17 +417,19 @@ size_t sample_workspace_bytes(int64_t n, bool weighted, int32_t T) {
     return sz.s.used + scratch + 512;
 }
 
-int sweep_grid(int64_t n) {
-    int cus = 256;
-    int dev = 0;
+template <typename K>
+int resident_grid(K kernel, int64_t n) {
+    int cus = 256, dev = 0, per_cu = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
     }
-    // about one item per lane to start with; at most 8 blocks (32 waves) per CU
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 4;
+    // every block resident at once: the sweep's waves take their items in turn
     int64_t want = (n + kWave - 1) / kWave;
     if (want < 16) want = 16;
-    const int64_t cap = (int64_t)cus * 8;
+    const int64_t cap = (int64_t)cus * per_cu;
     return (int)(want < cap ? want : cap);
 }
 
@@ -402,7 +482,6 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
         if (st != MH_OK) return st;
     }
 
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[2], stream));
     SweepArgs A;
     A.zs = L.zs;
     A.ys = L.ys;
@@ -413,6 +492,8 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
     A.mq = L.mq;
     A.P = L.P;
     A.hoff = L.hoff;
+    A.rec = L.rec;
+    A.rec_cap = L.rec_cap;
     A.n = n;
     A.T = T;
     A.key0 = (uint32_t)seed;
@@ -420,13 +501,17 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
     A.replica = replica;
     A.out = EdgeOut{src, dst, w, capacity, &L.ctr->n_edges};
     A.ctr = L.ctr;
-    const dim3 grid(sweep_grid(n));
+    if (seg) {
+        hipLaunchKernelGGL(k_heavy_records, dim3(512), dim3(kThreads), 0, stream, A, L.rec);
+        MH_HIP_TRY(hipGetLastError());
+    }
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[2], stream));
     if (weighted) {
-        if (stats_host) hipLaunchKernelGGL((k_sweep<true, true>), grid, dim3(kThreads), 0, stream, A);
-        else hipLaunchKernelGGL((k_sweep<true, false>), grid, dim3(kThreads), 0, stream, A);
+        if (stats_host) hipLaunchKernelGGL((k_sweep<true, true>), dim3(resident_grid(k_sweep<true, true>, n)), dim3(kThreads), 0, stream, A);
+        else hipLaunchKernelGGL((k_sweep<true, false>), dim3(resident_grid(k_sweep<true, false>, n)), dim3(kThreads), 0, stream, A);
     } else {
-        if (stats_host) hipLaunchKernelGGL((k_sweep<false, true>), grid, dim3(kThreads), 0, stream, A);
-        else hipLaunchKernelGGL((k_sweep<false, false>), grid, dim3(kThreads), 0, stream, A);
+        if (stats_host) hipLaunchKernelGGL((k_sweep<false, true>), dim3(resident_grid(k_sweep<false, true>, n)), dim3(kThreads), 0, stream, A);
+        else hipLaunchKernelGGL((k_sweep<false, false>), dim3(resident_grid(k_sweep<false, false>, n)), dim3(kThreads), 0, stream, A);
     }
     MH_HIP_TRY(hipGetLastError());
     if (ev) MH_HIP_TRY(hipEventRecord(ev[3], stream));
