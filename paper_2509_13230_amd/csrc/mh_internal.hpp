@@ -55,10 +55,15 @@ mh_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void*
 
 // ---- radix sort of (key, value) pairs ascending by key, stable ----
 size_t radix_workspace_bytes(int64_t n);
+// Zeroes the sort's scratch (in ws) and returns its histogram array
+// (8 x 256 counts, digit d of pass p at [p * 256 + d]) for a fused counting kernel.
+mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream);
 // Sorts keys[0..n) / vals[0..n) using alt buffers of the same size; the result
-// ends in keys/vals (8 passes of 8 bits).
+// ends in keys/vals (8 passes of 8 bits).  hist_ready: the histogram returned
+// by radix_prepare already holds the counts.  err (optional, device) receives
+// MH_EHIP if a look-back ever stalls.
 mh_status radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                         void* ws, size_t ws_bytes, hipStream_t stream);
+                         void* ws, size_t ws_bytes, bool hist_ready, int32_t* err, hipStream_t stream);
 
 // ---- sampler pieces ----
 struct SortedView {

@@ -10,23 +10,42 @@ namespace {
 
 constexpr int kThreads = 256;
 
+constexpr int kPrepTile = 4096;
+
+// Sort keys (complemented bits of z = x or x*y) with ids as payload, checks of
+// the parameters, and the digit histograms of all 8 radix passes.
 __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict__ x, const double* __restrict__ y,
                                                         int64_t n, uint64_t* __restrict__ keys,
-                                                        uint32_t* __restrict__ vals, int32_t* status) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    const double xi = x[i];
-    bool ok = (xi >= 0.0) && isfinite(xi);
-    double z = xi;
-    if (y) {
-        const double yi = y[i];
-        ok = ok && (yi >= 0.0) && isfinite(yi);
-        z = xi * yi;
-        ok = ok && isfinite(z);
+                                                        uint32_t* __restrict__ vals, uint32_t* __restrict__ hist,
+                                                        int32_t* status) {
+    __shared__ uint32_t h[8 * 256];
+    for (int i = threadIdx.x; i < 8 * 256; i += kThreads) h[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kPrepTile;
+    bool bad = false;
+    for (int k = threadIdx.x; k < kPrepTile; k += kThreads) {
+        const int64_t i = base + k;
+        if (i >= n) break;
+        const double xi = x[i];
+        bool ok = (xi >= 0.0) && isfinite(xi);
+        double z = xi;
+        if (y) {
+            const double yi = y[i];
+            ok = ok && (yi >= 0.0) && isfinite(yi);
+            z = xi * yi;
+            ok = ok && isfinite(z);
+        }
+        bad = bad || !ok;
+        const uint64_t key = desc_key(ok ? z : 0.0);
+        keys[i] = key;
+        vals[i] = (uint32_t)i;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) atomicAdd(&h[p * 256 + ((key >> (8 * p)) & 255)], 1u);
     }
-    if (!ok) raise_status(status, MH_EINVAL);
-    keys[i] = desc_key(ok ? z : 0.0);
-    vals[i] = (uint32_t)i;
+    if (bad) raise_status(status, MH_EINVAL);
+    __syncthreads();
+    for (int i = threadIdx.x; i < 8 * 256; i += kThreads)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_finish_order(const uint64_t* __restrict__ keys,
@@ -188,12 +207,17 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
     uint32_t* vals_alt = ar.take<uint32_t>(n);
     if (ar.overflow) return MH_EWORKSPACE;
     const size_t off = (ar.used + 255) & ~size_t(255);
-    const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_prep_keys, dim3(grid), dim3(kThreads), 0, stream, x, y, n, keys, vals, status);
-    MH_HIP_TRY(hipGetLastError());
-    mh_status st = radix_sort_u64(keys, vals, keys_alt, vals_alt, n, ar.base + off, ws_bytes > off ? ws_bytes - off : 0,
-                                  stream);
+    void* sort_ws = ar.base + off;
+    const size_t sort_bytes = ws_bytes > off ? ws_bytes - off : 0;
+    uint32_t* hist = nullptr;
+    mh_status st = radix_prepare(sort_ws, sort_bytes, n, &hist, stream);
     if (st != MH_OK) return st;
+    const unsigned tiles = (unsigned)((n + kPrepTile - 1) / kPrepTile);
+    hipLaunchKernelGGL(k_prep_keys, dim3(tiles), dim3(kThreads), 0, stream, x, y, n, keys, vals, hist, status);
+    MH_HIP_TRY(hipGetLastError());
+    st = radix_sort_u64(keys, vals, keys_alt, vals_alt, n, sort_ws, sort_bytes, true, status, stream);
+    if (st != MH_OK) return st;
+    const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_finish_order, dim3(grid), dim3(kThreads), 0, stream, keys, vals, n, perm, zs, y, y ? ys : nullptr,
                        mass_out, status);
     MH_HIP_TRY(hipGetLastError());

@@ -1,9 +1,17 @@
-// Stable LSD radix sort of 64-bit keys with 32-bit payloads, 8 passes of 8
-// bits.  Per pass: a counting kernel (per-tile digit histograms, digit-major),
-// an exclusive scan of the histograms, and a scatter kernel.  Inside a wave,
-// keys with equal digits are grouped by 8 ballots (one per digit bit), which
-// gives each key its rank among equal digits without LDS atomics, so heavy
-// ties (many equal keys) cost nothing extra.
+// Stable LSD radix sort of 64-bit keys with 32-bit payloads: 8 passes of 8
+// bits, one kernel per pass ("one-sweep" with decoupled look-back).
+//
+// The digit histograms of all 8 passes come from one counting kernel (fused
+// into key preparation by the caller, or k_radix_hist).  In a pass, each block
+// takes a tile ticket, ranks its 4096 keys (keys with equal digits are grouped
+// by 8 ballots, one per digit bit, so ties cost nothing extra), publishes its
+// per-digit counts, and finds the counts of all earlier tiles by looking back
+// over their published words (a 64-bit word per tile and digit: a flag in the
+// high half -- 1 = this tile's count, 2 = inclusive prefix over tiles 0..t --
+// and the value in the low half).  A block waits only on tiles with smaller
+// tickets, which have started and publish without waiting, so the look-back
+// always ends; a spin limit turns a lost update into an error, never a hang.
+// Keys are then reordered by digit in LDS and written in coalesced runs.
 #include "mh_common.hpp"
 #include "mh_internal.hpp"
 
@@ -17,6 +25,10 @@ constexpr int kKeysPerLane = 16;
 constexpr int kWaveKeys = kWave * kKeysPerLane;     // 1024, contiguous per wave
 constexpr int kTileKeys = kWaveKeys * kSortWaves;  // 4096 per block
 constexpr int kRadix = 256;
+constexpr int kPasses = 8;
+constexpr uint64_t kFlagAggregate = 1ull << 32;
+constexpr uint64_t kFlagPrefix = 2ull << 32;
+constexpr uint32_t kSpinLimit = 1u << 24;
 
 // Lanes (among `valid`) whose digit equals this lane's.
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -30,43 +42,67 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
     return m;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_count(const uint64_t* __restrict__ keys, int64_t n, int shift,
-                                                              uint32_t* __restrict__ counts, int nblocks) {
-    __shared__ uint32_t cnt[kSortWaves][kRadix];
-    for (int i = threadIdx.x; i < kSortWaves * kRadix; i += kSortThreads) (&cnt[0][0])[i] = 0;
-    __syncthreads();
+// Exclusive scan of one value per thread (256 threads) through LDS.
+__device__ __forceinline__ uint32_t block_exclusive_256(uint32_t v, uint32_t* lds_wave) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kTileKeys + (int64_t)wave * kWaveKeys;
-    const uint64_t lt = lanemask_lt();
-    for (int r = 0; r < kKeysPerLane; ++r) {
-        const int64_t i = base + (int64_t)r * kWave + lane;
-        const bool valid = i < n;
-        if (__ballot(valid) == 0) break;
-        const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & (kRadix - 1) : 0u;
-        const uint64_t m = match_digit(d, valid);
-        if (valid && (m & lt) == 0) cnt[wave][d] += (uint32_t)__popcll(m);
-        __builtin_amdgcn_wave_barrier();
-    }
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == 63) lds_wave[wave] = inc;
     __syncthreads();
-    const int d = threadIdx.x;  // kSortThreads == kRadix
-    uint32_t total = 0;
+    uint32_t before = 0;
 #pragma unroll
-    for (int w = 0; w < kSortWaves; ++w) total += cnt[w][d];
-    counts[(int64_t)d * nblocks + blockIdx.x] = total;
+    for (int w = 0; w < kSortWaves; ++w)
+        if (w < wave) before += lds_wave[w];
+    __syncthreads();
+    return before + inc - v;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* __restrict__ kin,
-                                                                const uint32_t* __restrict__ vin,
-                                                                uint64_t* __restrict__ kout,
-                                                                uint32_t* __restrict__ vout, int64_t n, int shift,
-                                                                const uint32_t* __restrict__ offsets, int nblocks) {
+__global__ __launch_bounds__(kSortThreads) void k_zero_u64(uint64_t* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSortThreads)
+        p[i] = 0;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n,
+                                                             uint32_t* __restrict__ ghist) {
+    __shared__ uint32_t h[kPasses * kRadix];
+    for (int i = threadIdx.x; i < kPasses * kRadix; i += kSortThreads) h[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTileKeys;
+    for (int k = threadIdx.x; k < kTileKeys; k += kSortThreads) {
+        const int64_t i = base + k;
+        if (i < n) {
+            const uint64_t key = keys[i];
+#pragma unroll
+            for (int p = 0; p < kPasses; ++p) atomicAdd(&h[p * kRadix + ((key >> (8 * p)) & 255)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kPasses * kRadix; i += kSortThreads)
+        if (h[i]) atomicAdd(&ghist[i], h[i]);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __restrict__ kin,
+                                                           const uint32_t* __restrict__ vin,
+                                                           uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                           int64_t n, int shift, const uint32_t* __restrict__ ghist,
+                                                           uint64_t* status, uint32_t* ticket, int32_t* err) {
+    __shared__ uint64_t s_keys[kTileKeys];
+    __shared__ uint32_t s_vals[kTileKeys];
     __shared__ uint32_t cnt[kSortWaves][kRadix];
-    __shared__ uint32_t woff[kSortWaves][kRadix];
+    __shared__ uint32_t s_bstart[kRadix];
+    __shared__ uint32_t s_goff[kRadix];
+    __shared__ uint32_t s_scan[kSortWaves];
+    __shared__ uint32_t s_tile;
+
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     for (int i = threadIdx.x; i < kSortWaves * kRadix; i += kSortThreads) (&cnt[0][0])[i] = 0;
     __syncthreads();
+    const int64_t tile = s_tile;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kTileKeys + (int64_t)wave * kWaveKeys;
+    const int64_t tbase = tile * kTileKeys;
+    const int64_t base = tbase + (int64_t)wave * kWaveKeys;
     const uint64_t lt = lanemask_lt();
+
+    // rank every key among the wave's keys with the same digit
     uint64_t k[kKeysPerLane];
     uint32_t v[kKeysPerLane];
     uint32_t rank[kKeysPerLane];
@@ -85,65 +121,153 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    {
-        const int d = threadIdx.x;
-        uint32_t run = offsets[(int64_t)d * nblocks + blockIdx.x];
+
+    const int d = threadIdx.x;  // one digit per thread
+    uint32_t total = 0;
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) {
-            woff[w][d] = run;
-            run += cnt[w][d];
-        }
+    for (int w = 0; w < kSortWaves; ++w) {
+        const uint32_t c = cnt[w][d];
+        cnt[w][d] = total;  // becomes the wave's offset inside the block's digit run
+        total += c;
     }
+    uint64_t* st = status + tile * kRadix + d;
+    __hip_atomic_store(st, (tile == 0 ? kFlagPrefix : kFlagAggregate) | total, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t bstart = block_exclusive_256(total, s_scan);
+    const uint32_t dstart = block_exclusive_256(ghist[d], s_scan);
+    uint32_t excl = 0;
+    if (tile > 0) {
+        int64_t t = tile - 1;
+        uint32_t spins = 0;
+        while (t >= 0) {
+            const uint64_t w =
+                __hip_atomic_load(status + t * kRadix + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t flag = w & ~0xFFFFFFFFull;
+            if (flag == 0) {
+                if (++spins > kSpinLimit) {
+                    raise_status(err, MH_EHIP);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            excl += (uint32_t)w;
+            if (flag == kFlagPrefix) break;
+            --t;
+        }
+        __hip_atomic_store(st, kFlagPrefix | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_bstart[d] = bstart;
+    s_goff[d] = dstart + excl - bstart;
     __syncthreads();
+
+    // reorder the tile by digit in LDS, then write each digit's run contiguously
 #pragma unroll
     for (int r = 0; r < kKeysPerLane; ++r) {
         const int64_t i = base + (int64_t)r * kWave + lane;
         if (i < n) {
-            const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
-            const uint32_t pos = woff[wave][d] + rank[r];
-            kout[pos] = k[r];
-            vout[pos] = v[r];
+            const uint32_t dd = (uint32_t)(k[r] >> shift) & (kRadix - 1);
+            const uint32_t lp = s_bstart[dd] + cnt[wave][dd] + rank[r];
+            s_keys[lp] = k[r];
+            s_vals[lp] = v[r];
         }
     }
+    __syncthreads();
+    const int64_t cnt_tile = (n - tbase) < kTileKeys ? (n - tbase) : kTileKeys;
+    for (int i = threadIdx.x; i < cnt_tile; i += kSortThreads) {
+        const uint64_t key = s_keys[i];
+        const uint32_t dd = (uint32_t)(key >> shift) & (kRadix - 1);
+        const uint32_t pos = s_goff[dd] + (uint32_t)i;
+        kout[pos] = key;
+        vout[pos] = s_vals[i];
+    }
 }
+
+int64_t sort_blocks(int64_t n) { return (n + kTileKeys - 1) / kTileKeys; }
 
 }  // namespace
 
 size_t radix_workspace_bytes(int64_t n) {
-    const int64_t nblocks = (n + kTileKeys - 1) / kTileKeys;
+    const int64_t nb = sort_blocks(n);
     Sizer s;
-    s.take<uint32_t>((size_t)nblocks * kRadix + 1);
-    return s.used + scan_workspace_bytes(nblocks * kRadix + 1) + 256;
+    s.take<uint64_t>((size_t)kPasses * nb * kRadix + kPasses * kRadix / 2 + kPasses);  // status, hist, tickets
+    s.take<int32_t>(1);
+    return s.used + 256;
 }
 
-mh_status radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                         void* ws, size_t ws_bytes, hipStream_t stream) {
-    if (n <= 1) return MH_OK;
-    if (n > (int64_t)0xFFFFFFFFll) return MH_EINVAL;
-    const int64_t nblocks = (n + kTileKeys - 1) / kTileKeys;
-    Arena ar(ws, ws_bytes);
-    uint32_t* counts = ar.take<uint32_t>((size_t)nblocks * kRadix + 1);
-    if (!counts) return MH_EWORKSPACE;
-    void* scan_ws = ar.base + ((ar.used + 255) & ~size_t(255));
-    size_t scan_bytes = ws_bytes > ((ar.used + 255) & ~size_t(255)) ? ws_bytes - ((ar.used + 255) & ~size_t(255)) : 0;
+// Zeroes the look-back words, histograms and tickets (one kernel), counts all
+// passes' digits (unless the caller already did, hist_ready), then runs the
+// 8 passes.  The result ends in keys/vals.
+mh_status radix_sort_u64_hist(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                              uint32_t* hist, uint64_t* status, uint32_t* tickets, int32_t* err,
+                              bool hist_ready, hipStream_t stream) {
+    const int64_t nb = sort_blocks(n);
+    if (!hist_ready) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, keys, n, hist);
+        MH_HIP_TRY(hipGetLastError());
+    }
     uint64_t* kin = keys;
     uint32_t* vin = vals;
     uint64_t* kout = keys_alt;
     uint32_t* vout = vals_alt;
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = pass * 8;
-        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)nblocks), dim3(kSortThreads), 0, stream, kin, n, shift, counts,
-                           (int)nblocks);
-        MH_HIP_TRY(hipGetLastError());
-        mh_status st = scan_exclusive_u32(counts, counts, nblocks * kRadix, scan_ws, scan_bytes, stream);
-        if (st != MH_OK) return st;
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblocks), dim3(kSortThreads), 0, stream, kin, vin, kout, vout,
-                           n, shift, counts, (int)nblocks);
+    for (int pass = 0; pass < kPasses; ++pass) {
+        hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n,
+                           pass * 8, hist + pass * kRadix, status + (int64_t)pass * nb * kRadix, tickets + pass, err);
         MH_HIP_TRY(hipGetLastError());
         uint64_t* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
     }
-    return MH_OK;  // 8 passes: the result is back in keys/vals
+    return MH_OK;
+}
+
+// Layout of the sort's scratch: look-back words, then histograms and tickets.
+struct SortScratch {
+    uint64_t* status;
+    uint32_t* hist;
+    uint32_t* tickets;
+    int32_t* err;
+    int64_t words;  // u64 words to zero (status + hist + tickets)
+};
+
+static SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) {
+    const int64_t nb = sort_blocks(n);
+    Arena ar(ws, ws_bytes);
+    const int64_t status_words = (int64_t)kPasses * nb * kRadix;
+    const int64_t extra_words = kPasses * kRadix / 2 + kPasses;
+    uint64_t* block = ar.take<uint64_t>(status_words + extra_words);
+    int32_t* err = ar.take<int32_t>(1);
+    *ok = !ar.overflow;
+    SortScratch s{};
+    if (!*ok) return s;
+    s.status = block;
+    s.hist = reinterpret_cast<uint32_t*>(block + status_words);
+    s.tickets = s.hist + kPasses * kRadix;
+    s.err = err;
+    s.words = status_words + extra_words;
+    return s;
+}
+
+mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream) {
+    bool ok = false;
+    SortScratch s = sort_scratch(ws, ws_bytes, n, &ok);
+    if (!ok) return MH_EWORKSPACE;
+    int64_t blocks = (s.words + kSortThreads - 1) / kSortThreads;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), dim3(kSortThreads), 0, stream, s.status, s.words);
+    MH_HIP_TRY(hipGetLastError());
+    *hist = s.hist;
+    return MH_OK;
+}
+
+mh_status radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                         void* ws, size_t ws_bytes, bool hist_ready, int32_t* err, hipStream_t stream) {
+    if (n <= 1) return MH_OK;
+    if (n > (int64_t)0xFFFFFFFFll) return MH_EINVAL;
+    bool ok = false;
+    SortScratch s = sort_scratch(ws, ws_bytes, n, &ok);
+    if (!ok) return MH_EWORKSPACE;
+    return radix_sort_u64_hist(keys, vals, keys_alt, vals_alt, n, s.hist, s.status, s.tickets, err ? err : s.err,
+                               hist_ready, stream);
 }
 
 }  // namespace mh
