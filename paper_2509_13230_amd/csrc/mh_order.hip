@@ -22,25 +22,52 @@ __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict
     for (int i = threadIdx.x; i < 8 * 256; i += kThreads) h[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kPrepTile;
+    const int lane = threadIdx.x & 63;
     bool bad = false;
     for (int k = threadIdx.x; k < kPrepTile; k += kThreads) {
         const int64_t i = base + k;
-        if (i >= n) break;
-        const double xi = x[i];
-        bool ok = (xi >= 0.0) && isfinite(xi);
-        double z = xi;
-        if (y) {
-            const double yi = y[i];
-            ok = ok && (yi >= 0.0) && isfinite(yi);
-            z = xi * yi;
-            ok = ok && isfinite(z);
+        const bool valid = i < n;
+        if (__ballot(valid) == 0) break;
+        uint64_t key = 0;
+        if (valid) {
+            const double xi = x[i];
+            bool ok = (xi >= 0.0) && isfinite(xi);
+            double z = xi;
+            if (y) {
+                const double yi = y[i];
+                ok = ok && (yi >= 0.0) && isfinite(yi);
+                z = xi * yi;
+                ok = ok && isfinite(z);
+            }
+            bad = bad || !ok;
+            key = desc_key(ok ? z : 0.0);
+            keys[i] = key;
+            vals[i] = (uint32_t)i;
         }
-        bad = bad || !ok;
-        const uint64_t key = desc_key(ok ? z : 0.0);
-        keys[i] = key;
-        vals[i] = (uint32_t)i;
+        // Lanes holding the key of their group's first lane (groups by an 8-bit
+        // fold of the key) are counted once by that lane: tied parameters,
+        // common in fitted inputs, would otherwise all hit one LDS bin.
+        const uint32_t fold = (uint32_t)(key ^ (key >> 8) ^ (key >> 16) ^ (key >> 24) ^ (key >> 32) ^ (key >> 40) ^
+                                         (key >> 48) ^ (key >> 56)) & 255u;
+        uint64_t m = __ballot(valid);
 #pragma unroll
-        for (int p = 0; p < 8; ++p) atomicAdd(&h[p * 256 + ((key >> (8 * p)) & 255)], 1u);
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (fold >> b) & 1u;
+            const uint64_t vote = __ballot(bit);
+            m &= bit ? vote : ~vote;
+        }
+        const int leader = valid ? (int)__ffsll((unsigned long long)m) - 1 : lane;
+        const uint64_t lkey = __shfl(key, leader, kWave);
+        const uint64_t same = __ballot(valid && key == lkey);
+        if (valid) {
+            uint32_t add = 0;
+            if (lane == leader) add = (uint32_t)__popcll(same & m);
+            else if (!((same >> lane) & 1ull)) add = 1;
+            if (add) {
+#pragma unroll
+                for (int p = 0; p < 8; ++p) atomicAdd(&h[p * 256 + ((key >> (8 * p)) & 255)], add);
+            }
+        }
     }
     if (bad) raise_status(status, MH_EINVAL);
     __syncthreads();

@@ -29,6 +29,7 @@ constexpr int kPasses = 8;
 constexpr uint64_t kFlagAggregate = 1ull << 32;
 constexpr uint64_t kFlagPrefix = 2ull << 32;
 constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr int kLookWindow = 8;
 
 // Lanes (among `valid`) whose digit equals this lane's.
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -135,25 +136,38 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
                        __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t bstart = block_exclusive_256(total, s_scan);
     const uint32_t dstart = block_exclusive_256(ghist[d], s_scan);
+    // look back over the preceding tiles, kLookWindow words in flight at a time
     uint32_t excl = 0;
     if (tile > 0) {
         int64_t t = tile - 1;
         uint32_t spins = 0;
-        while (t >= 0) {
-            const uint64_t w =
-                __hip_atomic_load(status + t * kRadix + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t flag = w & ~0xFFFFFFFFull;
-            if (flag == 0) {
+        bool done = false;
+        while (!done) {
+            uint64_t w[kLookWindow];
+#pragma unroll
+            for (int q = 0; q < kLookWindow; ++q)
+                w[q] = (t - q >= 0) ? __hip_atomic_load(status + (t - q) * kRadix + d, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)
+                                    : kFlagPrefix;
+            int used = 0;
+#pragma unroll
+            for (int q = 0; q < kLookWindow; ++q) {
+                if (done || used < q) continue;  // stop at the first word still unpublished
+                const uint64_t flag = w[q] & ~0xFFFFFFFFull;
+                if (flag == 0) continue;
+                excl += (uint32_t)w[q];
+                used = q + 1;
+                if (flag == kFlagPrefix) done = true;
+            }
+            if (done) break;
+            t -= used;
+            if (used == 0) {
                 if (++spins > kSpinLimit) {
                     raise_status(err, MH_EHIP);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
-                continue;
             }
-            excl += (uint32_t)w;
-            if (flag == kFlagPrefix) break;
-            --t;
         }
         __hip_atomic_store(st, kFlagPrefix | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
