@@ -23,24 +23,37 @@ __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kPrepTile;
     const int lane = threadIdx.x & 63;
-    bool bad = false;
-    for (int k = threadIdx.x; k < kPrepTile; k += kThreads) {
-        const int64_t i = base + k;
-        const bool valid = i < n;
-        if (__ballot(valid) == 0) break;
-        uint64_t key = 0;
-        if (valid) {
+    constexpr int kPer = kPrepTile / kThreads;
+    // all loads first, then the keys and their counts
+    double zv[kPer];
+    bool okv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int64_t i = base + (int64_t)q * kThreads + threadIdx.x;
+        zv[q] = 0.0;
+        okv[q] = true;
+        if (i < n) {
             const double xi = x[i];
-            bool ok = (xi >= 0.0) && isfinite(xi);
-            double z = xi;
             if (y) {
                 const double yi = y[i];
-                ok = ok && (yi >= 0.0) && isfinite(yi);
-                z = xi * yi;
-                ok = ok && isfinite(z);
+                okv[q] = (yi >= 0.0) && isfinite(yi) && (xi >= 0.0) && isfinite(xi);
+                zv[q] = xi * yi;
+            } else {
+                okv[q] = (xi >= 0.0) && isfinite(xi);
+                zv[q] = xi;
             }
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int64_t i = base + (int64_t)q * kThreads + threadIdx.x;
+        const bool valid = i < n;
+        uint64_t key = 0;
+        if (valid) {
+            const bool ok = okv[q] && isfinite(zv[q]);
             bad = bad || !ok;
-            key = desc_key(ok ? z : 0.0);
+            key = desc_key(ok ? zv[q] : 0.0);
             keys[i] = key;
             vals[i] = (uint32_t)i;
         }

@@ -107,12 +107,19 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     uint64_t k[kKeysPerLane];
     uint32_t v[kKeysPerLane];
     uint32_t rank[kKeysPerLane];
+    // all loads first: the ranking below orders LDS accesses with wave barriers,
+    // which the compiler will not move loads across
 #pragma unroll
     for (int r = 0; r < kKeysPerLane; ++r) {
         const int64_t i = base + (int64_t)r * kWave + lane;
         const bool valid = i < n;
         k[r] = valid ? kin[i] : 0ull;
         v[r] = valid ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kKeysPerLane; ++r) {
+        const int64_t i = base + (int64_t)r * kWave + lane;
+        const bool valid = i < n;
         const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
         const uint64_t m = match_digit(d, valid);
         const uint32_t prior = cnt[wave][d];
