@@ -153,6 +153,86 @@ mh_status mh_expected_degree_bwd(const double* x, const double* y, const double*
                                  const double* gk, const double* gs, double* gx, double* gy,
                                  hipStream_t stream);
 
+/* ---- Batched ensembles: many networks x many replicas in one persistent launch ----
+ * Ensembles of hundreds or thousands of samples per null-model test motivate
+ * the method (Sec. 2.2); here every network is ordered, bounded and planned
+ * once, and all requested (network, replica) samples are swept by one resident
+ * grid.  A sample (network i, replica r) is identical, edge for edge, to
+ * mh_sample_unweighted/mh_sample_weighted(x_i[, y_i], seed, r) with the same
+ * seg_work. */
+typedef struct {
+    int64_t n;        /* nodes */
+    const double* x;  /* device float64[n] */
+    const double* y;  /* device float64[n]; NULL = unweighted (every network of a batch uses the same model) */
+    int32_t seg_work; /* plan parameter of this network (0 = one segment per row) */
+    int32_t pad;
+} mh_network;
+
+#define MH_BATCH_EDGES 0   /* edges (src, dst[, w]) and optionally the sample index per edge (sid) */
+#define MH_BATCH_DEGREES 1 /* per-sample degree sequences: degrees[deg_off[s] + node id] */
+
+typedef struct {
+    int32_t seg_work;    /* chosen plan parameter */
+    int32_t grid_blocks; /* chosen persistent grid (0 = all resident blocks) */
+    float ms;            /* median probe time */
+} mh_tuning;
+
+/* Workspace for a batch of these networks and at most max_samples samples per call. */
+size_t mh_batch_workspace_bytes(const mh_network* nets_host, int32_t n_networks, int32_t max_samples);
+
+/* Order, bound and plan every network into the workspace (synchronous; MH_EINVAL
+ * if any network's parameters are invalid).  Later calls on this workspace must
+ * pass the same nets_host array. */
+mh_status mh_batch_prepare(const mh_network* nets_host, int32_t n_networks, int32_t max_samples,
+                           void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Sample s = 0..n_samples-1 is (network sample_net[s], replica sample_rep[s])
+ * (device int32/uint32 arrays; a network index outside [0, n_networks) fails
+ * the call with MH_EINVAL, reported by mh_batch_result).  MH_BATCH_EDGES: up to `capacity` edges into
+ * src/dst (w for weighted networks; sid[k] = sample of edge k, may be NULL),
+ * order unspecified.  MH_BATCH_DEGREES: degrees[deg_off[s] + v] (device int32,
+ * offsets device int64; the caller's array must hold deg_off[s] + n of every
+ * listed sample) is overwritten with node v's degree in sample s.
+ * grid_blocks = 0 uses every resident block.  Asynchronous, kernels only: it
+ * may be captured in a hipGraph.  mh_batch_result reads the edge count back. */
+mh_status mh_batch_sample_async(const mh_network* nets_host, int32_t n_networks, int32_t max_samples,
+                                void* workspace, size_t ws_bytes, const int32_t* sample_net,
+                                const uint32_t* sample_rep, int32_t n_samples, uint64_t seed,
+                                int32_t mode, int32_t* src, int32_t* dst, int32_t* w, int32_t* sid,
+                                int64_t capacity, int32_t* degrees, const int64_t* deg_off,
+                                int32_t grid_blocks, hipStream_t stream);
+
+/* Edge count of the last batch call (synchronises the stream); MH_ECAPACITY if
+ * it exceeds capacity (pass capacity < 0 to skip that check). */
+mh_status mh_batch_result(const mh_network* nets_host, int32_t n_networks, int32_t max_samples,
+                          void* workspace, size_t ws_bytes, int64_t* n_edges_host, int64_t capacity,
+                          hipStream_t stream);
+
+/* Capture mh_batch_sample_async with these arguments into an executable graph
+ * (*exec_out, owned by the caller: hipGraphExecDestroy).  Replays sample the
+ * same (network, replica) list, read from the same device arrays. */
+mh_status mh_batch_capture(const mh_network* nets_host, int32_t n_networks, int32_t max_samples,
+                           void* workspace, size_t ws_bytes, const int32_t* sample_net,
+                           const uint32_t* sample_rep, int32_t n_samples, uint64_t seed, int32_t mode,
+                           int32_t* src, int32_t* dst, int32_t* w, int32_t* sid, int64_t capacity,
+                           int32_t* degrees, const int64_t* deg_off, int32_t grid_blocks,
+                           hipStream_t stream, hipGraphExec_t* exec_out);
+
+/* Time the degree-sink sweep of a probe batch for every (seg_work, grid) pair
+ * of the candidates (median of 3), set every network's seg_work to the
+ * fastest, prepare the workspace with it, and report it in *best.  The
+ * workspace must fit the layout of every candidate. */
+mh_status mh_batch_autotune(mh_network* nets_host, int32_t n_networks, int32_t max_samples,
+                            void* workspace, size_t ws_bytes, const int32_t* sample_net,
+                            const uint32_t* sample_rep, int32_t n_samples, int32_t* degrees,
+                            const int64_t* deg_off, const int32_t* seg_candidates, int32_t n_seg,
+                            const int32_t* grid_candidates, int32_t n_grid, mh_tuning* best,
+                            hipStream_t stream);
+
+/* Launch / destroy a graph made by mh_batch_capture (thin wrappers of the HIP calls). */
+mh_status mh_graph_launch(hipGraphExec_t exec, hipStream_t stream);
+mh_status mh_graph_destroy(hipGraphExec_t exec);
+
 const char* mh_status_string(mh_status s);
 
 #ifdef __cplusplus

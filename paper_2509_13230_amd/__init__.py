@@ -330,3 +330,188 @@ class ExpectedDegree(torch.autograd.Function):
             gs = torch.zeros_like(x)
         gx, gy = expected_degree_grad(x, y, mult, gk.contiguous(), gs.contiguous() if ctx.weighted else None)
         return gx, (gy if ctx.weighted else None), None
+
+
+# ---------------------------------------------------------------------------- batched ensembles
+MH_BATCH_EDGES, MH_BATCH_DEGREES = 0, 1
+
+
+class Network(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("seg_work", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("seg_work", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
+def _batch_sigs(L):
+    if getattr(L, "_batch_ready", False):
+        return
+    vp, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "mh_batch_workspace_bytes": ([vp, i32, i32], sz),
+        "mh_batch_prepare": ([vp, i32, i32, vp, sz, vp], ctypes.c_int),
+        "mh_batch_sample_async": ([vp, i32, i32, vp, sz, vp, vp, i32, u64, i32, vp, vp, vp, vp, i64, vp, vp, i32, vp],
+                                  ctypes.c_int),
+        "mh_batch_result": ([vp, i32, i32, vp, sz, P(i64), i64, vp], ctypes.c_int),
+        "mh_batch_capture": ([vp, i32, i32, vp, sz, vp, vp, i32, u64, i32, vp, vp, vp, vp, i64, vp, vp, i32, vp,
+                              P(vp)], ctypes.c_int),
+        "mh_batch_autotune": ([vp, i32, i32, vp, sz, vp, vp, i32, vp, vp, vp, i32, vp, i32, P(Tuning), vp],
+                              ctypes.c_int),
+        "mh_graph_launch": ([vp, vp], ctypes.c_int),
+        "mh_graph_destroy": ([vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    L._batch_ready = True
+
+
+class Batch:
+    """Prepared ensemble of networks (A1-A3 done once) sampled by one persistent launch.
+
+    xs: list of float64 CUDA tensors (one per network); ys: same-length list for
+    the weighted model, or None.  Sample (i, r) equals sample_unweighted(xs[i],
+    seed, r, seg_work) edge for edge."""
+
+    def __init__(self, xs, ys=None, seg_work: int | list = DEFAULT_SEG_WORK, max_samples: int = 4096):
+        L = lib()
+        _batch_sigs(L)
+        self.L = L
+        self.xs = [_dev_f64(x, "x") for x in xs]
+        self.ys = None if ys is None else [_dev_f64(y, "y") for y in ys]
+        self.device = self.xs[0].device
+        k = len(self.xs)
+        sw = [int(seg_work)] * k if not isinstance(seg_work, (list, tuple)) else [int(v) for v in seg_work]
+        self.nets = (Network * k)()
+        for i, x in enumerate(self.xs):
+            self.nets[i].n = x.numel()
+            self.nets[i].x = x.data_ptr()
+            self.nets[i].y = None if self.ys is None else self.ys[i].data_ptr()
+            self.nets[i].seg_work = sw[i]
+        self.k = k
+        self.max_samples = int(max_samples)
+        self.sizes = [x.numel() for x in self.xs]
+        self.ws = _workspace(self._ws_bytes(), self.device)
+        _check(L.mh_batch_prepare(self.nets, k, self.max_samples, _ptr(self.ws), self.ws.numel(),
+                                  _stream(self.device)), "mh_batch_prepare")
+
+    def _ws_bytes(self):
+        return self.L.mh_batch_workspace_bytes(self.nets, self.k, self.max_samples)
+
+    def _refs(self, sample_net, sample_rep):
+        net = torch.as_tensor(sample_net, dtype=torch.int32, device=self.device).contiguous()
+        rep = torch.as_tensor(sample_rep, dtype=torch.int64, device=self.device).to(torch.int32).contiguous()
+        if net.numel() != rep.numel() or net.numel() > self.max_samples:
+            raise ValueError("sample lists must have equal length <= max_samples")
+        return net, rep
+
+    def degree_offsets(self, sample_net):
+        # an index outside the batch sizes as 0 here; the library rejects it
+        sizes = torch.as_tensor([self.sizes[int(i)] if 0 <= int(i) < self.k else 0
+                                 for i in torch.as_tensor(sample_net).tolist()], dtype=torch.int64)
+        off = torch.zeros(len(sizes) + 1, dtype=torch.int64)
+        off[1:] = torch.cumsum(sizes, 0)
+        return off
+
+    def sample_edges_async(self, net, rep, seed, src, dst, w, sid, capacity, grid_blocks=0):
+        _check(self.L.mh_batch_sample_async(self.nets, self.k, self.max_samples, _ptr(self.ws), self.ws.numel(),
+                                            _ptr(net), _ptr(rep), net.numel(), seed, MH_BATCH_EDGES, _ptr(src),
+                                            _ptr(dst), _ptr(w), _ptr(sid), capacity, None, None, grid_blocks,
+                                            _stream(self.device)), "mh_batch_sample_async")
+
+    def result(self, capacity=-1) -> int:
+        m = ctypes.c_int64(0)
+        st = self.L.mh_batch_result(self.nets, self.k, self.max_samples, _ptr(self.ws), self.ws.numel(),
+                                    ctypes.byref(m), capacity, _stream(self.device))
+        if st not in (MH_OK, MH_ECAPACITY):
+            _check(st, "mh_batch_result")
+        return int(m.value) if st == MH_OK else -int(m.value)
+
+    def sample_edges(self, sample_net, sample_rep, seed: int = 1, capacity: int | None = None, grid_blocks=0):
+        """(src, dst, w|None, sid) of every listed sample, order unspecified."""
+        net, rep = self._refs(sample_net, sample_rep)
+        cap = int(capacity) if capacity is not None else max(
+            4096, 4 * sum(self.sizes[i] for i in net.tolist() if 0 <= i < self.k))
+        for _ in range(2):
+            src = torch.empty(cap, dtype=torch.int32, device=self.device)
+            dst = torch.empty(cap, dtype=torch.int32, device=self.device)
+            w = torch.empty(cap, dtype=torch.int32, device=self.device) if self.ys is not None else None
+            sid = torch.empty(cap, dtype=torch.int32, device=self.device)
+            self.sample_edges_async(net, rep, seed, src, dst, w, sid, cap, grid_blocks)
+            m = self.result(cap)
+            if m >= 0:
+                return src[:m], dst[:m], (None if w is None else w[:m]), sid[:m]
+            cap = -m
+        raise MHError(MH_ECAPACITY, "mh_batch_sample_async")
+
+    def sample_degrees(self, sample_net, sample_rep, seed: int = 1, out=None, grid_blocks=0):
+        """Concatenated per-sample degree sequences and their offsets (int64, len n_samples + 1)."""
+        net, rep = self._refs(sample_net, sample_rep)
+        off = self.degree_offsets(net.cpu())
+        deg = out if out is not None else torch.empty(int(off[-1]), dtype=torch.int32, device=self.device)
+        offd = off.to(self.device)
+        _check(self.L.mh_batch_sample_async(self.nets, self.k, self.max_samples, _ptr(self.ws), self.ws.numel(),
+                                            _ptr(net), _ptr(rep), net.numel(), seed, MH_BATCH_DEGREES, None, None,
+                                            None, None, 0, _ptr(deg), _ptr(offd), grid_blocks, _stream(self.device)),
+               "mh_batch_sample_async")
+        self.result(-1)
+        return deg, off
+
+    def capture_degrees(self, net, rep, seed, deg, offd, grid_blocks=0):
+        """hipGraph of one degree-sink batch launch; returns a BatchGraph (replay with .launch())."""
+        exe = ctypes.c_void_p()
+        _check(self.L.mh_batch_capture(self.nets, self.k, self.max_samples, _ptr(self.ws), self.ws.numel(), _ptr(net),
+                                       _ptr(rep), net.numel(), seed, MH_BATCH_DEGREES, None, None, None, None, 0,
+                                       _ptr(deg), _ptr(offd), grid_blocks, _stream(self.device), ctypes.byref(exe)),
+               "mh_batch_capture")
+        return BatchGraph(self.L, exe, self.device)
+
+    def capture_edges(self, net, rep, seed, src, dst, w, sid, capacity, grid_blocks=0):
+        exe = ctypes.c_void_p()
+        _check(self.L.mh_batch_capture(self.nets, self.k, self.max_samples, _ptr(self.ws), self.ws.numel(), _ptr(net),
+                                       _ptr(rep), net.numel(), seed, MH_BATCH_EDGES, _ptr(src), _ptr(dst), _ptr(w),
+                                       _ptr(sid), capacity, None, None, grid_blocks, _stream(self.device),
+                                       ctypes.byref(exe)), "mh_batch_capture")
+        return BatchGraph(self.L, exe, self.device)
+
+    def autotune(self, probe_net, probe_rep, seg_candidates=(4, 8, 16, 32), grid_candidates=(0,)):
+        """Pick seg_work and grid size on a probe batch (degree sink); re-prepares with the winner."""
+        net, rep = self._refs(probe_net, probe_rep)
+        off = self.degree_offsets(net.cpu())
+        deg = torch.empty(int(off[-1]), dtype=torch.int32, device=self.device)
+        offd = off.to(self.device)
+        segs = (ctypes.c_int32 * len(seg_candidates))(*seg_candidates)
+        grids = (ctypes.c_int32 * len(grid_candidates))(*grid_candidates)
+        best = Tuning()
+        # the workspace must fit every candidate's layout: size it for the largest
+        need = 0
+        for sw in seg_candidates:
+            for i in range(self.k):
+                self.nets[i].seg_work = int(sw)
+            need = max(need, self._ws_bytes())
+        if self.ws.numel() < need:
+            self.ws = _workspace(need, self.device)
+        _check(self.L.mh_batch_autotune(self.nets, self.k, self.max_samples, _ptr(self.ws), self.ws.numel(), _ptr(net),
+                                        _ptr(rep), net.numel(), _ptr(deg), _ptr(offd), segs, len(seg_candidates),
+                                        grids, len(grid_candidates), ctypes.byref(best), _stream(self.device)),
+               "mh_batch_autotune")
+        return {"seg_work": best.seg_work, "grid_blocks": best.grid_blocks, "ms": best.ms}
+
+
+class BatchGraph:
+    def __init__(self, L, exe, device):
+        self.L, self.exe, self.device = L, exe, device
+
+    def launch(self):
+        _check(self.L.mh_graph_launch(self.exe, _stream(self.device)), "mh_graph_launch")
+
+    def __del__(self):
+        try:
+            if self.exe:
+                self.L.mh_graph_destroy(self.exe)
+        except Exception:
+            pass

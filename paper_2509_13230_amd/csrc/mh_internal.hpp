@@ -55,8 +55,9 @@ mh_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void*
 
 // ---- radix sort of (key, value) pairs ascending by key, stable ----
 size_t radix_workspace_bytes(int64_t n);
-// Zeroes the sort's scratch (in ws) and returns its histogram array
-// (8 x 256 counts, digit d of pass p at [p * 256 + d]) for a fused counting kernel.
+// Zeroes the sort's scratch (in ws) and returns its histogram array for a fused
+// counting kernel: 32 copies of 8 x 256 counts (copy c, pass p, digit d at
+// [(c * 8 + p) * 256 + d]); a counting block adds into copy blockIdx % 32.
 mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream);
 // Sorts keys[0..n) / vals[0..n) using alt buffers of the same size; the result
 // ends in keys/vals (8 passes of 8 bits).  hist_ready: the histogram returned

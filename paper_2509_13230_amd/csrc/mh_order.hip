@@ -84,8 +84,10 @@ __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict
     }
     if (bad) raise_status(status, MH_EINVAL);
     __syncthreads();
+    // one of 32 histogram copies per block (the sort sums them)
+    uint32_t* copy = hist + (blockIdx.x % 32) * 8 * 256;
     for (int i = threadIdx.x; i < 8 * 256; i += kThreads)
-        if (h[i]) atomicAdd(&hist[i], h[i]);
+        if (h[i]) atomicAdd(&copy[i], h[i]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_finish_order(const uint64_t* __restrict__ keys,

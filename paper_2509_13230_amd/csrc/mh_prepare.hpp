@@ -1,0 +1,50 @@
+// Host-side preparation of a network (order, bound, plan) shared by the
+// single-sample and batched entry points.
+#pragma once
+
+#include "mh_internal.hpp"
+#include "mh_sweep_core.hpp"
+
+namespace mh {
+
+// Device buffers of one prepared network (writable views of a NetDesc).
+struct NetBuffers {
+    int32_t* perm;
+    double* zs;
+    double* ys;
+    double* c;
+    uint64_t* P;
+    int32_t* nseg;
+    int32_t* jend;
+    uint64_t* mq;
+    uint64_t* hoff;
+    HeavyRec* rec;
+    int64_t rec_cap;
+    int64_t n;
+    int32_t T;
+    bool weighted;
+};
+
+size_t network_bytes(int64_t n, bool weighted, int32_t T);
+NetBuffers carve_network(Arena& ar, int64_t n, bool weighted, int32_t T);
+size_t prepare_scratch_bytes(int64_t n);
+NetDesc net_desc(const NetBuffers& B);
+mh_status init_counters(Counters* c, hipStream_t stream);
+// Records ev[1] after the order step when ev is non-null.
+mh_status prepare_network(const double* x, const double* y, const NetBuffers& B, int32_t* status, void* scratch,
+                          size_t scratch_bytes, hipStream_t stream, hipEvent_t* ev);
+
+// Blocks of `kernel` (with `threads` threads) that fit on the device at once.
+template <typename K>
+int64_t resident_blocks(K kernel, int threads) {
+    int cus = 256, dev = 0, per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return (int64_t)cus * per_cu;
+}
+
+}  // namespace mh

@@ -28,8 +28,12 @@ constexpr int kRadix = 256;
 constexpr int kPasses = 8;
 constexpr uint64_t kFlagAggregate = 1ull << 32;
 constexpr uint64_t kFlagPrefix = 2ull << 32;
-constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr uint32_t kSpinLimit = 1u << 20;
 constexpr int kLookWindow = 8;
+// The counting kernel adds its block histograms into kHistCopies copies (block
+// b into copy b % kHistCopies), so that no address sees more than a few of the
+// device-scope atomics; readers sum the copies.
+constexpr int kHistCopies = 32;
 
 // Lanes (among `valid`) whose digit equals this lane's.
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -77,15 +81,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
         }
     }
     __syncthreads();
+    uint32_t* copy = ghist + (blockIdx.x % kHistCopies) * kPasses * kRadix;
     for (int i = threadIdx.x; i < kPasses * kRadix; i += kSortThreads)
-        if (h[i]) atomicAdd(&ghist[i], h[i]);
+        if (h[i]) atomicAdd(&copy[i], h[i]);
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __restrict__ kin,
                                                            const uint32_t* __restrict__ vin,
                                                            uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                            int64_t n, int shift, const uint32_t* __restrict__ ghist,
-                                                           uint64_t* status, uint32_t* ticket, int32_t* err) {
+                                                           uint64_t* status, uint32_t* ticket, bool use_ticket,
+                                                           int32_t* err) {
     __shared__ uint64_t s_keys[kTileKeys];
     __shared__ uint32_t s_vals[kTileKeys];
     __shared__ uint32_t cnt[kSortWaves][kRadix];
@@ -94,7 +100,10 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     __shared__ uint32_t s_scan[kSortWaves];
     __shared__ uint32_t s_tile;
 
-    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    // Tiles are taken in ticket order unless the whole grid is resident at once
+    // (then every block runs concurrently and its index serves, sparing 1 atomic
+    // per block on one address).
+    if (threadIdx.x == 0) s_tile = use_ticket ? atomicAdd(ticket, 1u) : blockIdx.x;
     for (int i = threadIdx.x; i < kSortWaves * kRadix; i += kSortThreads) (&cnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t tile = s_tile;
@@ -142,7 +151,10 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     __hip_atomic_store(st, (tile == 0 ? kFlagPrefix : kFlagAggregate) | total, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t bstart = block_exclusive_256(total, s_scan);
-    const uint32_t dstart = block_exclusive_256(ghist[d], s_scan);
+    uint32_t dtotal = 0;
+#pragma unroll 8
+    for (int c = 0; c < kHistCopies; ++c) dtotal += ghist[c * kPasses * kRadix + d];
+    const uint32_t dstart = block_exclusive_256(dtotal, s_scan);
     // look back over the preceding tiles, kLookWindow words in flight at a time
     uint32_t excl = 0;
     if (tile > 0) {
@@ -211,7 +223,7 @@ int64_t sort_blocks(int64_t n) { return (n + kTileKeys - 1) / kTileKeys; }
 size_t radix_workspace_bytes(int64_t n) {
     const int64_t nb = sort_blocks(n);
     Sizer s;
-    s.take<uint64_t>((size_t)kPasses * nb * kRadix + kPasses * kRadix / 2 + kPasses);  // status, hist, tickets
+    s.take<uint64_t>((size_t)kPasses * nb * kRadix + kHistCopies * kPasses * kRadix / 2 + kPasses);
     s.take<int32_t>(1);
     return s.used + 256;
 }
@@ -227,13 +239,20 @@ mh_status radix_sort_u64_hist(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, keys, n, hist);
         MH_HIP_TRY(hipGetLastError());
     }
+    int cus = 0, per_cu = 0, dev = 0;
+    bool use_ticket = true;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_onesweep, kSortThreads, 0) == hipSuccess)
+        use_ticket = nb > (int64_t)cus * per_cu;
     uint64_t* kin = keys;
     uint32_t* vin = vals;
     uint64_t* kout = keys_alt;
     uint32_t* vout = vals_alt;
     for (int pass = 0; pass < kPasses; ++pass) {
         hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n,
-                           pass * 8, hist + pass * kRadix, status + (int64_t)pass * nb * kRadix, tickets + pass, err);
+                           pass * 8, hist + pass * kRadix, status + (int64_t)pass * nb * kRadix, tickets + pass,
+                           use_ticket, err);
         MH_HIP_TRY(hipGetLastError());
         uint64_t* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
@@ -254,7 +273,7 @@ static SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) 
     const int64_t nb = sort_blocks(n);
     Arena ar(ws, ws_bytes);
     const int64_t status_words = (int64_t)kPasses * nb * kRadix;
-    const int64_t extra_words = kPasses * kRadix / 2 + kPasses;
+    const int64_t extra_words = kHistCopies * kPasses * kRadix / 2 + kPasses;
     uint64_t* block = ar.take<uint64_t>(status_words + extra_words);
     int32_t* err = ar.take<int32_t>(1);
     *ok = !ar.overflow;
@@ -262,7 +281,7 @@ static SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) 
     if (!*ok) return s;
     s.status = block;
     s.hist = reinterpret_cast<uint32_t*>(block + status_words);
-    s.tickets = s.hist + kPasses * kRadix;
+    s.tickets = s.hist + kHistCopies * kPasses * kRadix;
     s.err = err;
     s.words = status_words + extra_words;
     return s;

@@ -1,32 +1,17 @@
-// The sampler: plan of row segments and the per-segment rejection sweep
-// (Sec. 2.3-2.5, Alg. 1), plus the two sampling entry points of the C-ABI.
-//
-// Work items are (row, segment) pairs.  Rows cut into two or more segments
-// ("heavy" rows, the large-z hubs) come first in the item space, one item per
-// segment in row order; then every row r < n-1 in rank order, which is an item
-// only if the row has exactly one segment.  Each lane runs one item's chain;
-// a lane whose chain ends takes the wave's next item, so the 64 lanes stay
-// busy whatever the spread of chain lengths.  Waves take items strided by the
-// number of waves, which mixes hub segments and tail rows on every wave.
+// Single-sample entry points: node order, bound, plan of row segments, and
+// the per-segment rejection sweep (Sec. 2.3-2.5, Alg. 1; the sweep itself is
+// in mh_sweep_core.hpp).
 #include "mh_common.hpp"
 #include "mh_internal.hpp"
 #include "mh_stage.hpp"
+#include "mh_sweep_core.hpp"
+#include "mh_prepare.hpp"
 
 namespace mh {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWavesPerBlock = kThreads / kWave;
-
-enum { ST_STEPS = 0, ST_PROPOSALS, ST_ACCEPTS, ST_SEGMENTS, ST_SATURATED, ST_COUNT };
-
-struct Counters {
-    unsigned long long n_edges;
-    unsigned long long stats[ST_COUNT];
-    int32_t status;
-    int32_t pad;
-};
+constexpr int kThreads = kSweepThreads;
 
 __global__ __launch_bounds__(kThreads) void k_mass_of_sorted(const double* __restrict__ zs, int64_t n,
                                                              uint64_t* __restrict__ mass) {
@@ -86,316 +71,42 @@ __global__ __launch_bounds__(kThreads) void k_row_plan(const double* __restrict_
     if (hn) hn[r] = total >= 2 ? (uint64_t)total : 0ull;
 }
 
-struct HeavyRec {
-    int32_t r, g, a, b;
-};
-
-struct SweepArgs {
-    const double* zs;
-    const double* ys;
-    const double* c;
-    const int32_t* perm;
-    const int32_t* nseg;
-    const int32_t* jend;
-    const uint64_t* mq;
-    const uint64_t* P;
-    const uint64_t* hoff;  // null when unsegmented
-    const HeavyRec* rec;   // records of the first rec_cap heavy items
-    int64_t rec_cap;
-    int64_t n;
-    int32_t T;
-    uint32_t key0, key1;
-    uint32_t replica;
-    EdgeOut out;
-    Counters* ctr;
-};
-
-__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* __restrict__ a, int64_t lo, int64_t hi, uint64_t v) {
-    while (lo < hi) {
-        const int64_t mid = lo + (hi - lo) / 2;
-        if (a[mid] >= v) hi = mid; else lo = mid + 1;
-    }
-    return lo;
-}
-
-// Row, segment index and column range of heavy item `it` (it < H).
-__device__ HeavyRec heavy_record(const SweepArgs& A, int64_t it) {
-    const int64_t n = A.n;
-    int64_t lo = 0, hi = n;  // first row index with hoff > it, minus one
-    while (lo < hi) {
-        const int64_t mid = lo + (hi - lo) / 2;
-        if (A.hoff[mid] > (uint64_t)it) hi = mid; else lo = mid + 1;
-    }
-    const int64_t r = lo - 1;
-    const int64_t g = it - (int64_t)A.hoff[r];
-    const int64_t nsg = (int64_t)(A.hoff[r + 1] - A.hoff[r]);
-    const int64_t J = A.jend[r];
-    const int64_t T = A.T;
-    const int64_t nd = (J - r - 1 + T - 1) / T;
-    int64_t a, b;
-    if (g < nd) {
-        a = r + 1 + g * T;
-        b = a + T < J ? a + T : J;
-    } else {
-        const int64_t kk = g - nd;
-        const int64_t ns = nsg - nd;
-        const uint64_t base = A.P[J];
-        const uint64_t m = A.mq[r];
-        a = (kk == 0) ? J : lower_bound_u64(A.P, J, n, base + (uint64_t)kk * m);
-        b = (kk == ns - 1) ? n : lower_bound_u64(A.P, J, n, base + (uint64_t)(kk + 1) * m);
-    }
-    return HeavyRec{(int32_t)r, (int32_t)g, (int32_t)a, (int32_t)b};
-}
-
-__global__ __launch_bounds__(kThreads) void k_heavy_records(SweepArgs A, HeavyRec* __restrict__ rec) {
-    if (A.ctr->status != 0) return;
-    const int64_t H = (int64_t)A.hoff[A.n];
-    const int64_t lim = H < A.rec_cap ? H : A.rec_cap;
+__global__ __launch_bounds__(kThreads) void k_heavy_records(NetDesc D, HeavyRec* __restrict__ rec,
+                                                            const int32_t* status) {
+    if (*status != 0) return;
+    const int64_t H = heavy_items(D);
+    const int64_t lim = H < D.rec_cap ? H : D.rec_cap;
     for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < lim; it += (int64_t)gridDim.x * kThreads)
-        rec[it] = heavy_record(A, it);
+        rec[it] = heavy_record(D, it);
 }
 
-// Lane states of the sweep.  Every loop iteration a lane consumes the global
-// loads it issued in the previous iteration and issues the next ones, so one
-// memory round trip per iteration is overlapped with the Philox block and the
-// logarithm of the next draw, which need no loaded data.
-enum : uint32_t { S_IDLE = 0, S_REC, S_LOAD, S_STEP, S_DONE };
+}  // namespace
 
-template <bool WEIGHTED, bool STATS>
-__global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs A) {
-    __shared__ int32_t s_src[kWavesPerBlock][kStageEdges];
-    __shared__ int32_t s_dst[kWavesPerBlock][kStageEdges];
-    __shared__ int32_t s_w[WEIGHTED ? kWavesPerBlock : 1][WEIGHTED ? kStageEdges : 1];
-    if (A.ctr->status != 0) return;
-
-    const int wave = threadIdx.x >> 6;
-    const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    const int64_t H = A.hoff ? (int64_t)A.hoff[A.n] : 0;
-    const int64_t total = H + (A.n > 1 ? A.n - 1 : 0);
-    const int32_t n32 = (int32_t)A.n;
-    const uint64_t lt = lanemask_lt();
-
-    WaveStage<WEIGHTED> stage{s_src[wave], s_dst[wave], WEIGHTED ? s_w[wave] : nullptr, 0u};
-
-    uint32_t st_steps = 0, st_props = 0, st_acc = 0, st_segs = 0, st_sat = 0;
-    uint32_t state = S_IDLE;
-    bool check_light = false;
-    int32_t r = 0, pos = 0, end = 0, jc = 0;
-    uint32_t step = 0, tag = 0, scand = 0;
-    int32_t id = 0;
-    double s = 0.0, cr = 1.0, ysr = 0.0, tq = 0.0, U2 = 0.0;
-    // values in flight from the previous iteration's loads
-    double ld_s = 0.0, ld_z = 0.0, ld_c = 1.0, ld_y = 0.0;
-    int32_t ld_id = 0, ld_n = 1;
-    HeavyRec ld_rec{0, 0, 0, 0};
-    int64_t kbase = 0;
-
-    for (;;) {
-        // 1. the next draw of every lane that will draw this iteration (no loaded data needed)
-        const bool draws = (state == S_STEP) || (state == S_LOAD);
-        double E = 0.0, U2n = 0.0;
-        if (draws) {
-            const u32x4 R = philox4x32_10(step, (uint32_t)r, A.replica, tag, A.key0, A.key1);
-            E = -log(uniform53(R.v0, R.v1));
-            U2n = uniform53(R.v2, R.v3);
-        }
-        // 2. consume the loads of the previous iteration
-        bool acc = false, go = false;
-        int32_t dst_id = 0, wt = 0;
-        if (state == S_STEP) {
-            const double t = s * ld_z;
-            double lhs, rhs;
-            if (WEIGHTED) {
-                const double e = 1.0 - ysr * ld_y;
-                lhs = (U2 * tq) * (e + t);
-                rhs = t * (cr + tq);
-            } else {
-                lhs = (U2 * tq) * (1.0 + t);
-                rhs = t * (1.0 + tq);
-            }
-            ++st_props;
-            if (lhs < rhs) {
-                acc = true;
-                ++st_acc;
-                dst_id = ld_id;
-                if (WEIGHTED) {
-                    const double bb = ysr * ld_y;
-                    if (bb == 0.0) {
-                        wt = 1;
-                    } else {
-                        const u32x4 V = philox4x32_10(scand, (uint32_t)r, A.replica, tag | 1u, A.key0, A.key1);
-                        const double ratio = log(uniform53(V.v0, V.v1)) / log(bb);
-                        if (ratio >= 2147483646.0) {
-                            wt = 0x7FFFFFFF;
-                            ++st_sat;
-                        } else {
-                            wt = 1 + (int32_t)ratio;
-                        }
-                    }
-                }
-            }
-            tq = t;
-            pos = jc;
-            go = true;
-        } else if (state == S_LOAD) {
-            if (check_light && ld_n != 1) {
-                state = S_IDLE;
-            } else {
-                s = ld_s;
-                id = ld_id;
-                tq = s * ld_z;
-                cr = WEIGHTED ? ld_c : 1.0;
-                ysr = WEIGHTED ? ld_y : 0.0;
-                ++st_segs;
-                go = true;
-            }
-        } else if (state == S_REC) {
-            r = ld_rec.r;
-            pos = ld_rec.a - 1;
-            end = ld_rec.b;
-            tag = (uint32_t)ld_rec.g << 1;
-            step = 0;
-            check_light = false;
-            if (ld_rec.a >= ld_rec.b) {
-                state = S_IDLE;
-            } else {
-                ld_s = A.zs[r];
-                ld_z = A.zs[pos];
-                ld_id = A.perm[r];
-                if (WEIGHTED) {
-                    ld_c = A.c[r];
-                    ld_y = A.ys[r];
-                }
-                state = S_LOAD;
-            }
-        }
-        // 3. the skip: candidate pos + 1 + floor(-log U1 / -log(1 - q)), or the end of the segment
-        if (go) {
-            if (tq == 0.0) {
-                state = S_IDLE;
-            } else {
-                ++st_steps;
-                const double lq = WEIGHTED ? log1p(tq / cr) : log1p(tq);
-                const double d = E / lq;
-                const double room = (double)(end - 1 - pos);
-                if (d >= room) {
-                    state = S_IDLE;
-                } else {
-                    jc = pos + 1 + (int32_t)d;
-                    U2 = U2n;
-                    scand = step;
-                    ++step;
-                    ld_z = A.zs[jc];
-                    ld_id = A.perm[jc];
-                    if (WEIGHTED) ld_y = A.ys[jc];
-                    state = S_STEP;
-                }
-            }
-        }
-        // 4. idle lanes take the wave's next items and issue their loads
-        const uint64_t idle = __ballot(state == S_IDLE);
-        if (idle) {
-            if (state == S_IDLE) {
-                const int64_t it = gwave + (kbase + __popcll(idle & lt)) * nwaves;
-                if (it >= total) {
-                    state = S_DONE;
-                } else if (it < H) {
-                    ld_rec = (it < A.rec_cap) ? A.rec[it] : heavy_record(A, it);
-                    state = S_REC;
-                } else {
-                    r = (int32_t)(it - H);
-                    pos = r;
-                    end = n32;
-                    tag = 0;
-                    step = 0;
-                    check_light = true;
-                    ld_n = A.nseg[r];
-                    ld_s = A.zs[r];
-                    ld_z = ld_s;
-                    ld_id = A.perm[r];
-                    if (WEIGHTED) {
-                        ld_c = A.c[r];
-                        ld_y = A.ys[r];
-                    }
-                    state = S_LOAD;
-                }
-            }
-            kbase += __popcll(idle);
-        }
-        stage.push(acc, id, dst_id, wt, A.out);
-        if (__ballot(state != S_DONE) == 0) break;
-    }
-    stage.flush(A.out);
-
-    if (STATS) {
-        const unsigned long long v0 = wave_sum((unsigned long long)st_steps);
-        const unsigned long long v1 = wave_sum((unsigned long long)st_props);
-        const unsigned long long v2 = wave_sum((unsigned long long)st_acc);
-        const unsigned long long v3 = wave_sum((unsigned long long)st_segs);
-        const unsigned long long v4 = wave_sum((unsigned long long)st_sat);
-        if ((threadIdx.x & 63) == 0) {
-            atomicAdd(&A.ctr->stats[ST_STEPS], v0);
-            atomicAdd(&A.ctr->stats[ST_PROPOSALS], v1);
-            atomicAdd(&A.ctr->stats[ST_ACCEPTS], v2);
-            atomicAdd(&A.ctr->stats[ST_SEGMENTS], v3);
-            atomicAdd(&A.ctr->stats[ST_SATURATED], v4);
-        }
-    }
-}
-
-struct Layout {
-    Counters* ctr;
-    int32_t* perm;
-    double* zs;
-    double* ys;
-    double* c;
-    uint64_t* P;
-    int32_t* nseg;
-    int32_t* jend;
-    uint64_t* mq;
-    uint64_t* hoff;
-    HeavyRec* rec;
-    int64_t rec_cap;
-    char* scratch;
-    size_t scratch_bytes;
-};
-
-// Records kept for up to this many heavy items; items beyond it are located
-// inside the sweep (slower, same result).
-int64_t heavy_record_capacity(int64_t n) { return n + 4096; }
-
+// ---- one prepared network: buffers, sizes and preparation ----
 template <typename A>
-void carve(A& ar, int64_t n, bool weighted, bool segmented, Layout* L) {
-    auto c = ar.template take<Counters>(1);
-    auto perm = ar.template take<int32_t>(n);
-    auto zs = ar.template take<double>(n);
-    auto ys = ar.template take<double>(weighted ? n : 0);
-    auto cc = ar.template take<double>(weighted ? n : 0);
-    auto P = ar.template take<uint64_t>(segmented ? n + 1 : 0);
-    auto nseg = ar.template take<int32_t>(n);
-    auto jend = ar.template take<int32_t>(segmented ? n : 0);
-    auto mq = ar.template take<uint64_t>(segmented ? n : 0);
-    auto hoff = ar.template take<uint64_t>(segmented ? n + 1 : 0);
-    const int64_t rec_cap = segmented ? heavy_record_capacity(n) : 0;
-    auto rec = ar.template take<HeavyRec>(rec_cap);
-    if (L) {
-        L->ctr = (Counters*)c;
-        L->perm = (int32_t*)perm;
-        L->zs = (double*)zs;
-        L->ys = weighted ? (double*)ys : nullptr;
-        L->c = weighted ? (double*)cc : nullptr;
-        L->P = segmented ? (uint64_t*)P : nullptr;
-        L->nseg = (int32_t*)nseg;
-        L->jend = segmented ? (int32_t*)jend : nullptr;
-        L->mq = segmented ? (uint64_t*)mq : nullptr;
-        L->hoff = segmented ? (uint64_t*)hoff : nullptr;
-        L->rec = (HeavyRec*)rec;
-        L->rec_cap = rec_cap;
-    }
+static NetBuffers carve_network_impl(A& ar, int64_t n, bool weighted, int32_t T) {
+    const bool seg = T > 0;
+    NetBuffers B{};
+    B.perm = ar.template take<int32_t>(n);
+    B.zs = ar.template take<double>(n);
+    B.ys = ar.template take<double>(weighted ? n : 0);
+    B.c = ar.template take<double>(weighted ? n : 0);
+    B.P = ar.template take<uint64_t>(seg ? n + 1 : 0);
+    B.nseg = ar.template take<int32_t>(n);
+    B.jend = ar.template take<int32_t>(seg ? n : 0);
+    B.mq = ar.template take<uint64_t>(seg ? n : 0);
+    B.hoff = ar.template take<uint64_t>(seg ? n + 1 : 0);
+    B.rec_cap = seg ? n + 4096 : 0;  // records for up to this many heavy items; more are located in the sweep
+    B.rec = ar.template take<HeavyRec>(B.rec_cap);
+    if (!weighted) B.ys = B.c = nullptr;
+    if (!seg) B.P = nullptr, B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr;
+    B.n = n;
+    B.T = T;
+    B.weighted = weighted;
+    return B;
 }
 
-// Sizer has the same take<T>() calls but returns void; this adapter lets carve() run on both.
+namespace {
 struct SizerAdapter {
     Sizer s;
     template <typename T>
@@ -404,33 +115,100 @@ struct SizerAdapter {
         return nullptr;
     }
 };
+}  // namespace
+
+size_t network_bytes(int64_t n, bool weighted, int32_t T) {
+    SizerAdapter sz;
+    carve_network_impl(sz, n, weighted, T);
+    return sz.s.used + 256;
+}
+
+NetBuffers carve_network(Arena& ar, int64_t n, bool weighted, int32_t T) {
+    return carve_network_impl(ar, n, weighted, T);
+}
+
+size_t prepare_scratch_bytes(int64_t n) {
+    size_t scratch = order_workspace_bytes(n);
+    const size_t s2 = scan_workspace_bytes(n + 1);
+    const size_t s3 = bound_workspace_bytes(n);
+    if (s2 > scratch) scratch = s2;
+    if (s3 > scratch) scratch = s3;
+    return scratch + 256;
+}
+
+NetDesc net_desc(const NetBuffers& B) {
+    NetDesc D;
+    D.zs = B.zs;
+    D.ys = B.ys;
+    D.c = B.c;
+    D.perm = B.perm;
+    D.nseg = B.nseg;
+    D.jend = B.jend;
+    D.mq = B.mq;
+    D.P = B.P;
+    D.hoff = B.hoff;
+    D.rec = B.rec;
+    D.rec_cap = B.rec_cap;
+    D.n = B.n;
+    D.T = B.T;
+    D.pad = 0;
+    return D;
+}
+
+mh_status init_counters(Counters* c, hipStream_t stream) {
+    hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, c);
+    MH_HIP_TRY(hipGetLastError());
+    return MH_OK;
+}
+
+// Order (A1), bound (A2, weighted) and plan (A3) of one network into B.
+mh_status prepare_network(const double* x, const double* y, const NetBuffers& B, int32_t* status, void* scratch,
+                          size_t scratch_bytes, hipStream_t stream, hipEvent_t* ev) {
+    const int64_t n = B.n;
+    if (n <= 0) return MH_OK;
+    const bool seg = B.T > 0;
+    mh_status st = order_nodes(x, B.weighted ? y : nullptr, n, B.perm, B.zs, B.ys, status, B.P, scratch,
+                               scratch_bytes, stream);
+    if (st != MH_OK) return st;
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[1], stream));
+    if (B.weighted) {
+        st = bound_suffix_top2(B.ys, n, B.c, status, scratch, scratch_bytes, stream);
+        if (st != MH_OK) return st;
+    }
+    if (seg) {
+        st = scan_exclusive_u64(B.P, B.P, n, scratch, scratch_bytes, stream);
+        if (st != MH_OK) return st;
+    }
+    const unsigned rows_grid = (unsigned)((n + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_row_plan, dim3(rows_grid), dim3(kThreads), 0, stream, B.zs, B.c, n, B.T, B.P, B.nseg,
+                       B.jend, B.mq, B.hoff);
+    MH_HIP_TRY(hipGetLastError());
+    if (seg) {
+        st = scan_exclusive_u64(B.hoff, B.hoff, n, scratch, scratch_bytes, stream);
+        if (st != MH_OK) return st;
+        hipLaunchKernelGGL(k_heavy_records, dim3(512), dim3(kThreads), 0, stream, net_desc(B), B.rec,
+                           (const int32_t*)status);
+        MH_HIP_TRY(hipGetLastError());
+    }
+    return MH_OK;
+}
+
+namespace {
 
 size_t sample_workspace_bytes(int64_t n, bool weighted, int32_t T) {
     if (n < 0) return 0;
-    SizerAdapter sz;
-    carve(sz, n, weighted, T > 0, nullptr);
-    size_t scratch = order_workspace_bytes(n);
-    size_t s2 = scan_workspace_bytes(n + 1);
-    size_t s3 = bound_workspace_bytes(n);
-    if (s2 > scratch) scratch = s2;
-    if (s3 > scratch) scratch = s3;
-    return sz.s.used + scratch + 512;
+    Sizer s;
+    s.take<Counters>(1);
+    return s.used + network_bytes(n, weighted, T) + prepare_scratch_bytes(n) + 512;
 }
 
-template <typename K>
-int resident_grid(K kernel, int64_t n) {
-    int cus = 256, dev = 0, per_cu = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
-    }
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || per_cu < 1)
-        per_cu = 4;
-    // every block resident at once: the sweep's waves take their items in turn
+template <bool W, bool S>
+void launch_sweep(const SweepLaunch& A, int64_t n, hipStream_t stream) {
+    auto kern = k_sweep<W, S, false, OUT_EDGES>;
     int64_t want = (n + kWave - 1) / kWave;
     if (want < 16) want = 16;
-    const int64_t cap = (int64_t)cus * per_cu;
-    return (int)(want < cap ? want : cap);
+    const int64_t cap = resident_blocks(kern, kThreads);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(want < cap ? want : cap)), dim3(kThreads), 0, stream, A);
 }
 
 mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed, uint32_t replica,
@@ -447,11 +225,10 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
     if (stats_host) *stats_host = mh_stats{0, 0, 0, 0, 0, 0};
     if (n == 0) return MH_OK;
     if (!workspace || ws_bytes < sample_workspace_bytes(n, weighted, T)) return MH_EWORKSPACE;
-    const bool seg = T > 0;
 
     Arena ar(workspace, ws_bytes);
-    Layout L;
-    carve(ar, n, weighted, seg, &L);
+    Counters* ctr = ar.take<Counters>(1);
+    NetBuffers B = carve_network(ar, n, weighted, T);
     if (ar.overflow) return MH_EWORKSPACE;
     const size_t off = (ar.used + 255) & ~size_t(255);
     void* scratch = ar.base + off;
@@ -459,65 +236,32 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
 
     hipEvent_t* ev = plan ? plan->stage_events : nullptr;
     if (ev) MH_HIP_TRY(hipEventRecord(ev[0], stream));
-    hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, L.ctr);
-    MH_HIP_TRY(hipGetLastError());
-    int32_t* status = &L.ctr->status;
-    mh_status st = order_nodes(x, y, n, L.perm, L.zs, L.ys, status, L.P, scratch, scratch_bytes, stream);
+    mh_status st = init_counters(ctr, stream);
     if (st != MH_OK) return st;
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[1], stream));
-    if (weighted) {
-        st = bound_suffix_top2(L.ys, n, L.c, status, scratch, scratch_bytes, stream);
-        if (st != MH_OK) return st;
-    }
-    if (seg) {
-        st = scan_exclusive_u64(L.P, L.P, n, scratch, scratch_bytes, stream);
-        if (st != MH_OK) return st;
-    }
-    const unsigned rows_grid = (unsigned)((n + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_row_plan, dim3(rows_grid), dim3(kThreads), 0, stream, L.zs, L.c, n, T, L.P, L.nseg, L.jend,
-                       L.mq, L.hoff);
-    MH_HIP_TRY(hipGetLastError());
-    if (seg) {
-        st = scan_exclusive_u64(L.hoff, L.hoff, n, scratch, scratch_bytes, stream);
-        if (st != MH_OK) return st;
-    }
+    st = prepare_network(x, y, B, &ctr->status, scratch, scratch_bytes, stream, ev);
+    if (st != MH_OK) return st;
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[2], stream));
 
-    SweepArgs A;
-    A.zs = L.zs;
-    A.ys = L.ys;
-    A.c = L.c;
-    A.perm = L.perm;
-    A.nseg = L.nseg;
-    A.jend = L.jend;
-    A.mq = L.mq;
-    A.P = L.P;
-    A.hoff = L.hoff;
-    A.rec = L.rec;
-    A.rec_cap = L.rec_cap;
-    A.n = n;
-    A.T = T;
+    SweepLaunch A{};
+    A.net = net_desc(B);
+    A.replica = replica;
     A.key0 = (uint32_t)seed;
     A.key1 = (uint32_t)(seed >> 32);
-    A.replica = replica;
-    A.out = EdgeOut{src, dst, w, capacity, &L.ctr->n_edges};
-    A.ctr = L.ctr;
-    if (seg) {
-        hipLaunchKernelGGL(k_heavy_records, dim3(512), dim3(kThreads), 0, stream, A, L.rec);
-        MH_HIP_TRY(hipGetLastError());
-    }
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[2], stream));
+    A.out = EdgeOut{src, dst, w, capacity, &ctr->n_edges};
+    A.sid = nullptr;
+    A.ctr = ctr;
     if (weighted) {
-        if (stats_host) hipLaunchKernelGGL((k_sweep<true, true>), dim3(resident_grid(k_sweep<true, true>, n)), dim3(kThreads), 0, stream, A);
-        else hipLaunchKernelGGL((k_sweep<true, false>), dim3(resident_grid(k_sweep<true, false>, n)), dim3(kThreads), 0, stream, A);
+        if (stats_host) launch_sweep<true, true>(A, n, stream);
+        else launch_sweep<true, false>(A, n, stream);
     } else {
-        if (stats_host) hipLaunchKernelGGL((k_sweep<false, true>), dim3(resident_grid(k_sweep<false, true>, n)), dim3(kThreads), 0, stream, A);
-        else hipLaunchKernelGGL((k_sweep<false, false>), dim3(resident_grid(k_sweep<false, false>, n)), dim3(kThreads), 0, stream, A);
+        if (stats_host) launch_sweep<false, true>(A, n, stream);
+        else launch_sweep<false, false>(A, n, stream);
     }
     MH_HIP_TRY(hipGetLastError());
     if (ev) MH_HIP_TRY(hipEventRecord(ev[3], stream));
 
     Counters hc;
-    MH_HIP_TRY(hipMemcpyAsync(&hc, L.ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
+    MH_HIP_TRY(hipMemcpyAsync(&hc, ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
     MH_HIP_TRY(hipStreamSynchronize(stream));
     if (hc.status != 0) return (mh_status)hc.status;
     *n_edges_host = (int64_t)hc.n_edges;

@@ -1,0 +1,354 @@
+// The rejection sweep (Sec. 2.3-2.5, Alg. 1) as a lane state machine, shared
+// by the single-sample kernel and the batched persistent kernel.
+//
+// Work items are (row, segment) pairs of a prepared network.  Rows cut into
+// two or more segments ("heavy" rows, the large-z hubs) come first in a
+// network's item space, one item per segment in row order; then every row
+// r < n-1 in rank order, which is an item only if the row has exactly one
+// segment.  Each lane runs one item's chain; a lane whose chain ends takes its
+// wave's next item, so the 64 lanes stay busy whatever the spread of chain
+// lengths.  Every loop iteration a lane consumes the global loads it issued in
+// the previous iteration and issues the next ones: one memory round trip per
+// iteration, overlapped with the Philox block and the logarithm of the next
+// draw, which need no loaded data.
+#pragma once
+
+#include "mh_common.hpp"
+#include "mh_stage.hpp"
+
+namespace mh {
+
+constexpr int kSweepThreads = 256;
+constexpr int kSweepWaves = kSweepThreads / kWave;
+
+enum { ST_STEPS = 0, ST_PROPOSALS, ST_ACCEPTS, ST_SEGMENTS, ST_SATURATED, ST_COUNT };
+
+struct Counters {
+    unsigned long long n_edges;
+    unsigned long long stats[ST_COUNT];
+    int32_t status;
+    int32_t pad;
+};
+
+struct HeavyRec {
+    int32_t r, g, a, b;
+};
+
+// A prepared network: sorted parameters, bound and plan.
+struct NetDesc {
+    const double* zs;
+    const double* ys;  // weighted only
+    const double* c;   // weighted only
+    const int32_t* perm;
+    const int32_t* nseg;
+    const int32_t* jend;
+    const uint64_t* mq;
+    const uint64_t* P;
+    const uint64_t* hoff;  // null when unsegmented
+    const HeavyRec* rec;   // records of the first rec_cap heavy items
+    int64_t rec_cap;
+    int64_t n;
+    int32_t T;
+    int32_t pad;
+};
+
+__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* __restrict__ a, int64_t lo, int64_t hi, uint64_t v) {
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] >= v) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t heavy_items(const NetDesc& D) { return D.hoff ? (int64_t)D.hoff[D.n] : 0; }
+
+__device__ __forceinline__ int64_t total_items(const NetDesc& D) {
+    return heavy_items(D) + (D.n > 1 ? D.n - 1 : 0);
+}
+
+// Row, segment index and column range of heavy item `it` (it < H).
+__device__ inline HeavyRec heavy_record(const NetDesc& D, int64_t it) {
+    const int64_t n = D.n;
+    int64_t lo = 0, hi = n;  // first row index with hoff > it, minus one
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (D.hoff[mid] > (uint64_t)it) hi = mid; else lo = mid + 1;
+    }
+    const int64_t r = lo - 1;
+    const int64_t g = it - (int64_t)D.hoff[r];
+    const int64_t nsg = (int64_t)(D.hoff[r + 1] - D.hoff[r]);
+    const int64_t J = D.jend[r];
+    const int64_t T = D.T;
+    const int64_t nd = (J - r - 1 + T - 1) / T;
+    int64_t a, b;
+    if (g < nd) {
+        a = r + 1 + g * T;
+        b = a + T < J ? a + T : J;
+    } else {
+        const int64_t kk = g - nd;
+        const int64_t ns = nsg - nd;
+        const uint64_t base = D.P[J];
+        const uint64_t m = D.mq[r];
+        a = (kk == 0) ? J : lower_bound_u64(D.P, J, n, base + (uint64_t)kk * m);
+        b = (kk == ns - 1) ? n : lower_bound_u64(D.P, J, n, base + (uint64_t)(kk + 1) * m);
+    }
+    return HeavyRec{(int32_t)r, (int32_t)g, (int32_t)a, (int32_t)b};
+}
+
+// Where the items of a launch come from.  Single: one network, one replica.
+// Batch: a list of (network, replica) samples laid end to end.
+struct BatchRef {
+    const NetDesc* nets;        // [n_networks]
+    const int32_t* sample_net;  // [n_samples]
+    const uint32_t* sample_rep; // [n_samples]
+    const uint64_t* item_off;   // [n_samples + 1] exclusive prefix of items
+    int32_t n_samples;
+    int32_t* degrees;           // degree-sink output, or null
+    const int64_t* deg_off;     // [n_samples] start of each sample's degree array
+};
+
+enum SweepOut { OUT_EDGES = 0, OUT_DEGREES = 1 };
+
+struct SweepLaunch {
+    NetDesc net;        // single-sample network (unused in batch launches)
+    uint32_t replica;   // single-sample replica
+    BatchRef batch;
+    uint32_t key0, key1;
+    EdgeOut out;
+    int32_t* sid;       // batch edge output: sample id per edge (may be null)
+    Counters* ctr;
+};
+
+// Lane states
+enum : uint32_t { S_IDLE = 0, S_REC, S_LOAD, S_STEP, S_DONE };
+
+template <bool WEIGHTED, bool STATS, bool BATCH, int OUT>
+__device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src, int32_t* s_dst, int32_t* s_w,
+                                           int32_t* s_sid) {
+    const int wave = threadIdx.x >> 6;
+    const int64_t gwave = (int64_t)blockIdx.x * kSweepWaves + wave;
+    const int64_t nwaves = (int64_t)gridDim.x * kSweepWaves;
+    const uint64_t lt = lanemask_lt();
+    int64_t total;
+    int64_t H_single = 0;
+    if (BATCH) {
+        total = (int64_t)A.batch.item_off[A.batch.n_samples];
+    } else {
+        H_single = heavy_items(A.net);
+        total = H_single + (A.net.n > 1 ? A.net.n - 1 : 0);
+    }
+
+    WaveStage<WEIGHTED> stage{s_src, s_dst, WEIGHTED ? s_w : nullptr, 0u};
+
+    uint32_t st_steps = 0, st_props = 0, st_acc = 0, st_segs = 0, st_sat = 0;
+    uint32_t state = S_IDLE;
+    bool check_light = false;
+    int32_t r = 0, pos = 0, end = 0, jc = 0;
+    uint32_t step = 0, tag = 0, scand = 0, replica = A.replica;
+    int32_t id = 0, sample = 0, row_deg = 0;
+    double s = 0.0, cr = 1.0, ysr = 0.0, tq = 0.0, U2 = 0.0;
+    // the lane's network
+    const double* zs = A.net.zs;
+    const double* ys = A.net.ys;
+    const int32_t* perm = A.net.perm;
+    int32_t* deg = nullptr;
+    // values in flight from the previous iteration's loads
+    double ld_s = 0.0, ld_z = 0.0, ld_c = 1.0, ld_y = 0.0;
+    int32_t ld_id = 0, ld_n = 1;
+    HeavyRec ld_rec{0, 0, 0, 0};
+    int64_t kbase = 0;
+
+    for (;;) {
+        // 1. the next draw of every lane that will draw this iteration
+        const bool draws = (state == S_STEP) || (state == S_LOAD);
+        double E = 0.0, U2n = 0.0;
+        if (draws) {
+            const u32x4 R = philox4x32_10(step, (uint32_t)r, replica, tag, A.key0, A.key1);
+            E = -log(uniform53(R.v0, R.v1));
+            U2n = uniform53(R.v2, R.v3);
+        }
+        // 2. consume the loads of the previous iteration
+        bool acc = false, go = false;
+        int32_t dst_id = 0, wt = 0;
+        if (state == S_STEP) {
+            const double t = s * ld_z;
+            double lhs, rhs;
+            if (WEIGHTED) {
+                const double e = 1.0 - ysr * ld_y;
+                lhs = (U2 * tq) * (e + t);
+                rhs = t * (cr + tq);
+            } else {
+                lhs = (U2 * tq) * (1.0 + t);
+                rhs = t * (1.0 + tq);
+            }
+            ++st_props;
+            if (lhs < rhs) {
+                acc = true;
+                ++st_acc;
+                dst_id = ld_id;
+                if (WEIGHTED) {
+                    const double bb = ysr * ld_y;
+                    if (bb == 0.0) {
+                        wt = 1;
+                    } else {
+                        const u32x4 V = philox4x32_10(scand, (uint32_t)r, replica, tag | 1u, A.key0, A.key1);
+                        const double ratio = log(uniform53(V.v0, V.v1)) / log(bb);
+                        if (ratio >= 2147483646.0) {
+                            wt = 0x7FFFFFFF;
+                            ++st_sat;
+                        } else {
+                            wt = 1 + (int32_t)ratio;
+                        }
+                    }
+                }
+            }
+            tq = t;
+            pos = jc;
+            go = true;
+        } else if (state == S_LOAD) {
+            if (check_light && ld_n != 1) {
+                state = S_IDLE;
+            } else {
+                s = ld_s;
+                id = ld_id;
+                tq = s * ld_z;
+                cr = WEIGHTED ? ld_c : 1.0;
+                ysr = WEIGHTED ? ld_y : 0.0;
+                ++st_segs;
+                go = true;
+            }
+        } else if (state == S_REC) {
+            r = ld_rec.r;
+            pos = ld_rec.a - 1;
+            end = ld_rec.b;
+            tag = (uint32_t)ld_rec.g << 1;
+            step = 0;
+            check_light = false;
+            if (ld_rec.a >= ld_rec.b) {
+                state = S_IDLE;
+            } else {
+                const NetDesc& D = BATCH ? A.batch.nets[A.batch.sample_net[sample]] : A.net;
+                ld_s = zs[r];
+                ld_z = zs[pos];
+                ld_id = perm[r];
+                if (WEIGHTED) {
+                    ld_c = D.c[r];
+                    ld_y = ys[r];
+                }
+                state = S_LOAD;
+            }
+        }
+        if (OUT == OUT_DEGREES && acc) {
+            ++row_deg;
+            atomicAdd(&deg[dst_id], 1);
+        }
+        // 3. the skip: candidate pos + 1 + floor(-log U1 / -log(1 - q)), or the end of the segment
+        if (go) {
+            bool ended = true;
+            if (tq != 0.0) {
+                ++st_steps;
+                const double lq = WEIGHTED ? log1p(tq / cr) : log1p(tq);
+                const double d = E / lq;
+                const double room = (double)(end - 1 - pos);
+                if (d < room) {
+                    ended = false;
+                    jc = pos + 1 + (int32_t)d;
+                    U2 = U2n;
+                    scand = step;
+                    ++step;
+                    ld_z = zs[jc];
+                    ld_id = perm[jc];
+                    if (WEIGHTED) ld_y = ys[jc];
+                    state = S_STEP;
+                }
+            }
+            if (ended) {
+                state = S_IDLE;
+                if (OUT == OUT_DEGREES && row_deg) atomicAdd(&deg[id], row_deg);
+                row_deg = 0;
+            }
+        }
+        // 4. idle lanes take the wave's next items and issue their loads
+        const uint64_t idle = __ballot(state == S_IDLE);
+        if (idle) {
+            if (state == S_IDLE) {
+                int64_t it = gwave + (kbase + __popcll(idle & lt)) * nwaves;
+                if (it >= total) {
+                    state = S_DONE;
+                } else {
+                    int64_t H = H_single;
+                    const NetDesc* Dp = &A.net;
+                    if (BATCH) {
+                        int32_t lo = 0, hi = A.batch.n_samples;  // sample with item_off <= it < next
+                        while (hi - lo > 1) {
+                            const int32_t mid = (lo + hi) >> 1;
+                            if (A.batch.item_off[mid] <= (uint64_t)it) lo = mid; else hi = mid;
+                        }
+                        sample = lo;
+                        it -= (int64_t)A.batch.item_off[lo];
+                        Dp = &A.batch.nets[A.batch.sample_net[lo]];
+                        replica = A.batch.sample_rep[lo];
+                        H = heavy_items(*Dp);
+                        zs = Dp->zs;
+                        ys = Dp->ys;
+                        perm = Dp->perm;
+                        if (OUT == OUT_DEGREES) deg = A.batch.degrees + A.batch.deg_off[lo];
+                    }
+                    if (it < H) {
+                        ld_rec = (it < Dp->rec_cap) ? Dp->rec[it] : heavy_record(*Dp, it);
+                        state = S_REC;
+                    } else {
+                        r = (int32_t)(it - H);
+                        pos = r;
+                        end = (int32_t)Dp->n;
+                        tag = 0;
+                        step = 0;
+                        check_light = true;
+                        ld_n = Dp->nseg[r];
+                        ld_s = zs[r];
+                        ld_z = ld_s;
+                        ld_id = perm[r];
+                        if (WEIGHTED) {
+                            ld_c = Dp->c[r];
+                            ld_y = ys[r];
+                        }
+                        state = S_LOAD;
+                    }
+                }
+            }
+            kbase += __popcll(idle);
+        }
+        if (OUT == OUT_EDGES) stage.push_sid(acc, id, dst_id, wt, sample, s_sid, A.out, A.sid);
+        if (__ballot(state != S_DONE) == 0) break;
+    }
+    if (OUT == OUT_EDGES) stage.flush_sid(s_sid, A.out, A.sid);
+
+    if (STATS) {
+        const unsigned long long v0 = wave_sum((unsigned long long)st_steps);
+        const unsigned long long v1 = wave_sum((unsigned long long)st_props);
+        const unsigned long long v2 = wave_sum((unsigned long long)st_acc);
+        const unsigned long long v3 = wave_sum((unsigned long long)st_segs);
+        const unsigned long long v4 = wave_sum((unsigned long long)st_sat);
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&A.ctr->stats[ST_STEPS], v0);
+            atomicAdd(&A.ctr->stats[ST_PROPOSALS], v1);
+            atomicAdd(&A.ctr->stats[ST_ACCEPTS], v2);
+            atomicAdd(&A.ctr->stats[ST_SEGMENTS], v3);
+            atomicAdd(&A.ctr->stats[ST_SATURATED], v4);
+        }
+    }
+}
+
+template <bool WEIGHTED, bool STATS, bool BATCH, int OUT>
+__global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepLaunch A) {
+    __shared__ int32_t s_src[kSweepWaves][kStageEdges];
+    __shared__ int32_t s_dst[kSweepWaves][kStageEdges];
+    __shared__ int32_t s_w[WEIGHTED ? kSweepWaves : 1][WEIGHTED ? kStageEdges : 1];
+    __shared__ int32_t s_sid[BATCH ? kSweepWaves : 1][BATCH ? kStageEdges : 1];
+    if (A.ctr->status != 0) return;
+    const int wave = threadIdx.x >> 6;
+    sweep_body<WEIGHTED, STATS, BATCH, OUT>(A, s_src[wave], s_dst[wave], WEIGHTED ? s_w[wave] : nullptr,
+                                             BATCH ? s_sid[wave] : nullptr);
+}
+
+}  // namespace mh

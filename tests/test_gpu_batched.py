@@ -1,0 +1,156 @@
+"""GPU parity of the batched persistent sampler against the oracle.
+
+Sample (network i, replica r) of a batch must equal the oracle's sample of
+network i with the same seed, replica and plan parameter, edge for edge; the
+degree-sink mode must equal the degree sequences of those samples; a captured
+hipGraph replays to the same result as the eager call.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mh():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_2509_13230_amd as m
+
+    m.lib()
+    return m
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _nets(seed, sizes, weighted=False):
+    rng = np.random.default_rng(seed)
+    xs, ys = [], []
+    for n in sizes:
+        xs.append(np.exp(rng.normal(-3.0, 1.8, n)))
+        if weighted:
+            ys.append(rng.uniform(0.1, 0.95, n))
+    return xs, (ys if weighted else None)
+
+
+def _keys(src, dst, n, w=None):
+    key = np.asarray(src, np.int64) * n + np.asarray(dst, np.int64)
+    if w is None:
+        return np.sort(key), None
+    o = np.lexsort((np.asarray(w), key))
+    return key[o], np.asarray(w)[o]
+
+
+@pytest.mark.parametrize("seg_work", [0, 8])
+def test_batch_edges_match_oracle(mh, seg_work):
+    sizes = [1, 2, 300, 2500, 40, 1800]
+    xs, _ = _nets(1, sizes)
+    b = mh.Batch([dev(x) for x in xs], seg_work=seg_work, max_samples=64)
+    net = [i for i in range(len(sizes)) for _ in range(3)]
+    rep = [r for _ in sizes for r in (0, 5, 9)]
+    src, dst, _, sid = b.sample_edges(net, rep, seed=17)
+    src, dst, sid = src.cpu().numpy(), dst.cpu().numpy(), sid.cpu().numpy()
+    for s, (i, r) in enumerate(zip(net, rep)):
+        sel = sid == s
+        ora = oracle.sample_mh(xs[i], None, seed=17, replica=r, seg_work=seg_work)
+        if len(ora.tie_rows):
+            continue
+        assert np.array_equal(_keys(src[sel], dst[sel], sizes[i])[0], _keys(ora.src, ora.dst, sizes[i])[0]), (i, r)
+
+
+def test_batch_weighted_edges_match_oracle(mh):
+    sizes = [500, 1200, 64]
+    xs, ys = _nets(2, sizes, weighted=True)
+    b = mh.Batch([dev(x) for x in xs], [dev(y) for y in ys], seg_work=4, max_samples=16)
+    net, rep = [0, 1, 2, 1], [0, 0, 3, 7]
+    src, dst, w, sid = b.sample_edges(net, rep, seed=3)
+    src, dst, w, sid = (t.cpu().numpy() for t in (src, dst, w, sid))
+    for s, (i, r) in enumerate(zip(net, rep)):
+        sel = sid == s
+        ora = oracle.sample_mh(xs[i], ys[i], seed=3, replica=r, seg_work=4)
+        if len(ora.tie_rows):
+            continue
+        kg, wg = _keys(src[sel], dst[sel], sizes[i], w[sel])
+        ko, wo = _keys(ora.src, ora.dst, sizes[i], ora.w)
+        assert np.array_equal(kg, ko) and np.array_equal(wg, wo)
+
+
+def test_batch_degrees_match_oracle(mh):
+    sizes = [700, 3000, 150]
+    xs, _ = _nets(3, sizes)
+    b = mh.Batch([dev(x) for x in xs], seg_work=16, max_samples=16)
+    net, rep = [0, 1, 2, 1, 0], [1, 1, 1, 2, 8]
+    deg, off = b.sample_degrees(net, rep, seed=5)
+    deg = deg.cpu().numpy()
+    for s, (i, r) in enumerate(zip(net, rep)):
+        ora = oracle.sample_mh(xs[i], None, seed=5, replica=r, seg_work=16)
+        ref = np.bincount(ora.src, minlength=sizes[i]) + np.bincount(ora.dst, minlength=sizes[i])
+        if len(ora.tie_rows) == 0:
+            assert np.array_equal(deg[off[s]:off[s + 1]], ref)
+
+
+def test_graph_replays_match_eager(mh):
+    sizes = [1500, 400]
+    xs, _ = _nets(4, sizes)
+    b = mh.Batch([dev(x) for x in xs], seg_work=8, max_samples=8)
+    net = torch.tensor([0, 1, 0], dtype=torch.int32, device="cuda")
+    rep = torch.tensor([2, 2, 3], dtype=torch.int32, device="cuda")
+    eager, off = b.sample_degrees(net.cpu(), rep.cpu(), seed=9)
+    eager = eager.cpu().numpy()
+    deg = torch.empty(int(off[-1]), dtype=torch.int32, device="cuda")
+    g = b.capture_degrees(net, rep, 9, deg, off.cuda())
+    for _ in range(4):
+        deg.fill_(-1)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(deg.cpu().numpy(), eager)
+        # eager work between replays
+        b.sample_degrees([1], [0], seed=1)
+
+
+def test_graph_edge_replays_match_eager(mh):
+    xs, _ = _nets(5, [2000])
+    b = mh.Batch([dev(xs[0])], seg_work=16, max_samples=4)
+    net = torch.tensor([0, 0], dtype=torch.int32, device="cuda")
+    rep = torch.tensor([0, 1], dtype=torch.int32, device="cuda")
+    s0, d0, _, sid0 = b.sample_edges(net.cpu(), rep.cpu(), seed=2)
+    k0 = np.sort(sid0.cpu().numpy().astype(np.int64) * 2**40 + s0.cpu().numpy().astype(np.int64) * 2000 +
+                 d0.cpu().numpy())
+    cap = len(s0) + 1000
+    src = torch.empty(cap, dtype=torch.int32, device="cuda")
+    dst = torch.empty(cap, dtype=torch.int32, device="cuda")
+    sid = torch.empty(cap, dtype=torch.int32, device="cuda")
+    g = b.capture_edges(net, rep, 2, src, dst, None, sid, cap)
+    for _ in range(3):
+        g.launch()
+        m = b.result(cap)
+        assert m == len(s0)
+        k = np.sort(sid[:m].cpu().numpy().astype(np.int64) * 2**40 + src[:m].cpu().numpy().astype(np.int64) * 2000 +
+                    dst[:m].cpu().numpy())
+        assert np.array_equal(k, k0)
+
+
+def test_autotune_then_parity(mh):
+    sizes = [2000, 900, 4000]
+    xs, _ = _nets(6, sizes)
+    b = mh.Batch([dev(x) for x in xs], seg_work=32, max_samples=16)
+    best = b.autotune([0, 1, 2], [0, 0, 0], seg_candidates=(4, 16, 64), grid_candidates=(0, 64))
+    assert best["seg_work"] in (4, 16, 64) and best["ms"] > 0
+    src, dst, _, sid = b.sample_edges([2], [4], seed=8)
+    ora = oracle.sample_mh(xs[2], None, seed=8, replica=4, seg_work=best["seg_work"])
+    if len(ora.tie_rows) == 0:
+        assert np.array_equal(_keys(src.cpu().numpy(), dst.cpu().numpy(), 4000)[0], _keys(ora.src, ora.dst, 4000)[0])
+
+
+def test_bad_network_index(mh):
+    xs, _ = _nets(7, [100])
+    b = mh.Batch([dev(xs[0])], max_samples=4)
+    with pytest.raises(mh.MHError):
+        b.sample_degrees([3], [0])
