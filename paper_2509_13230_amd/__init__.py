@@ -468,7 +468,7 @@ class Batch:
                                        _ptr(rep), net.numel(), seed, MH_BATCH_DEGREES, None, None, None, None, 0,
                                        _ptr(deg), _ptr(offd), grid_blocks, _stream(self.device), ctypes.byref(exe)),
                "mh_batch_capture")
-        return BatchGraph(self.L, exe, self.device)
+        return BatchGraph(self.L, exe, self.device, keep=(net, rep, deg, offd, self.ws))
 
     def capture_edges(self, net, rep, seed, src, dst, w, sid, capacity, grid_blocks=0):
         exe = ctypes.c_void_p()
@@ -476,7 +476,7 @@ class Batch:
                                        _ptr(rep), net.numel(), seed, MH_BATCH_EDGES, _ptr(src), _ptr(dst), _ptr(w),
                                        _ptr(sid), capacity, None, None, grid_blocks, _stream(self.device),
                                        ctypes.byref(exe)), "mh_batch_capture")
-        return BatchGraph(self.L, exe, self.device)
+        return BatchGraph(self.L, exe, self.device, keep=(net, rep, src, dst, w, sid, self.ws))
 
     def autotune(self, probe_net, probe_rep, seg_candidates=(4, 8, 16, 32), grid_candidates=(0,)):
         """Pick seg_work and grid size on a probe batch (degree sink); re-prepares with the winner."""
@@ -503,8 +503,12 @@ class Batch:
 
 
 class BatchGraph:
-    def __init__(self, L, exe, device):
+    """An executable hipGraph of one batch launch.  It holds the tensors whose
+    device addresses the graph captured, so they outlive every replay."""
+
+    def __init__(self, L, exe, device, keep=()):
         self.L, self.exe, self.device = L, exe, device
+        self._keep = keep
 
     def launch(self):
         _check(self.L.mh_graph_launch(self.exe, _stream(self.device)), "mh_graph_launch")

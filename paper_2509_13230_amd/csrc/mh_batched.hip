@@ -242,12 +242,24 @@ mh_status mh_batch_capture(const mh_network* nets, int32_t n_networks, int32_t m
                            hipStream_t stream, hipGraphExec_t* exec_out) {
     if (!exec_out) return MH_EINVAL;
     *exec_out = nullptr;
-    MH_HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    // The legacy default stream cannot be captured: capture on a stream of our
+    // own (default priority) ordered after the caller's work, then drop it.
+    hipStream_t cap = stream;
+    if (stream == nullptr) {
+        MH_HIP_TRY(hipStreamSynchronize(nullptr));
+        MH_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    }
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        if (cap != stream) (void)hipStreamDestroy(cap);
+        return MH_EHIP;
+    }
     mh_status st = mh_batch_sample_async(nets, n_networks, max_samples, workspace, ws_bytes, sample_net, sample_rep,
                                          n_samples, seed, mode, src, dst, w, sid, capacity, degrees, deg_off,
-                                         grid_blocks, stream);
+                                         grid_blocks, cap);
     hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(stream, &graph);
+    e = hipStreamEndCapture(cap, &graph);
+    if (cap != stream) (void)hipStreamDestroy(cap);
     if (st != MH_OK) {
         if (graph) (void)hipGraphDestroy(graph);
         return st;
