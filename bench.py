@@ -85,6 +85,93 @@ def cpu_baseline(x: np.ndarray, seed: int, seg_work: int, budget_s: float) -> di
                       f"{t_total:.1f} s single-threaded"}
 
 
+def batched_ensemble(args, dev) -> dict:
+    """The ensemble workload: 256 networks (N log-uniform in [1e3, 2e5],
+    x = exp(Normal(-5, 2))) x 16 replicas = 4,096 samples.  Times one
+    hipGraph-captured persistent launch over all samples (degree-sink output,
+    preparation of every network done once beforehand and timed separately)
+    against 4,096 plain single-sample calls (order + plan + sweep + edge
+    output each)."""
+    import torch
+
+    import paper_2509_13230_amd as mh
+    import workloads
+
+    nets = workloads.cfg4_networks(seed=4, n_networks=args.batch_networks)
+    xs = [torch.as_tensor(nw.x, device=dev) for nw in nets]
+    R = args.batch_replicas
+    net_ids = [i for i in range(len(xs)) for _ in range(R)]
+    reps = [r for _ in xs for r in range(R)]
+    S = len(net_ids)
+
+    # plain: every sample through the single-sample entry point
+    max_n = max(x.numel() for x in xs)
+    L = mh.lib()
+    plan = mh.PlanParams(args.seg_work, 0, 0, 0, None)
+    ws = torch.empty(L.mh_workspace_bytes(max_n, 0, ctypes.byref(plan)), dtype=torch.uint8, device=dev)
+    # capacity: the largest sample seen on replica 0 of every network, with margin
+    caps = []
+    for x in xs:
+        s_, _ = mh.sample_unweighted(x, seed=args.seed, replica=0, seg_work=args.seg_work, workspace=ws)
+        caps.append(s_.numel())
+    cap = int(max(caps) * 1.1) + 65536
+    src = torch.empty(cap, dtype=torch.int32, device=dev)
+    dst = torch.empty(cap, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_edges = 0
+    for i, r in zip(net_ids, reps):
+        s_, _ = mh.sample_unweighted(xs[i], seed=args.seed, replica=r, seg_work=args.seg_work, out=(src, dst),
+                                     workspace=ws)
+        plain_edges += s_.numel()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    del src, dst, ws
+
+    # batched: prepare once, autotune on a probe, then one graph launch per ensemble
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = mh.Batch(xs, seg_work=args.seg_work, max_samples=S)
+    torch.cuda.synchronize()
+    t_prepare = time.perf_counter() - t0
+    probe = list(range(0, len(xs), max(1, len(xs) // 16)))
+    tuned = b.autotune(probe, [0] * len(probe), seg_candidates=(8, 16, 32), grid_candidates=(0, 1024, 2048))
+    net_t = torch.tensor(net_ids, dtype=torch.int32, device=dev)
+    rep_t = torch.tensor(reps, dtype=torch.int32, device=dev)
+    off = b.degree_offsets(torch.tensor(net_ids))
+    deg = torch.empty(int(off[-1]), dtype=torch.int32, device=dev)
+    offd = off.to(dev)
+    g = b.capture_degrees(net_t, rep_t, args.seed, deg, offd, grid_blocks=tuned["grid_blocks"])
+    g.launch()  # warm-up
+    b.result(-1)
+    runs = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.launch()
+        b.result(-1)
+        runs.append(time.perf_counter() - t0)
+    t_batch = min(runs)
+    batch_edges = int(deg.sum().item()) // 2
+    return {
+        "workload": f"{len(xs)} networks x {R} replicas = {S} samples, N log-uniform in [1e3, 2e5], "
+                    "x = exp(Normal(-5, 2)), unweighted",
+        "samples": S,
+        "edges": batch_edges,
+        "plain_edges": plain_edges,
+        "replicas_per_s_batched": S / t_batch,
+        "replicas_per_s_batched_incl_prepare": S / (t_batch + t_prepare),
+        "replicas_per_s_plain": S / t_plain,
+        "speedup_vs_plain": t_plain / t_batch,
+        "edges_per_s_batched": batch_edges / t_batch,
+        "ms_batched_launch": t_batch * 1e3,
+        "ms_prepare": t_prepare * 1e3,
+        "ms_plain_total": t_plain * 1e3,
+        "output": "degree sink (per-sample degree sequences)",
+        "tuned": tuned,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,9 +179,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seg-work", type=int, default=16)
     ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--grid-blocks", type=int, default=0, help="sweep grid (0 = all resident blocks)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="copy a buffer of this many MiB once first (reference for HBM byte counters)")
+    ap.add_argument("--batch-networks", type=int, default=256)
+    ap.add_argument("--batch-replicas", type=int, default=16)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -111,6 +204,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration_mib > 0:
+        a = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device=dev)
+        bcopy = torch.empty_like(a)
+        bcopy.copy_(a)
+        torch.cuda.synchronize()
+        del a, bcopy
     k_target = workloads.cfg2_degrees(seed=2, n=args.n)
     t0 = time.perf_counter()
     fit = fit_ubcm(k_target, tol=1e-10)
@@ -122,7 +221,7 @@ def main():
           flush=True)
 
     L = mh.lib()
-    plan = mh.PlanParams(args.seg_work, 0, None)
+    plan = mh.PlanParams(args.seg_work, 0, 0, 0, None)
     ws = torch.empty(L.mh_workspace_bytes(n, 0, ctypes.byref(plan)), dtype=torch.uint8, device=dev)
     s0, d0, st0 = mh.sample_unweighted(x, seed=args.seed, replica=0, seg_work=args.seg_work, stats=True,
                                        workspace=ws)
@@ -133,7 +232,7 @@ def main():
 
     def step(replica, events=None):
         s, _ = mh.sample_unweighted(x, seed=args.seed, replica=replica, seg_work=args.seg_work, out=(src, dst),
-                                    workspace=ws, stage_events=events)
+                                    workspace=ws, stage_events=events, grid_blocks=args.grid_blocks)
         return s.numel()
 
     for w in range(args.warmup):
@@ -155,7 +254,7 @@ def main():
     steps_total = 0
     for r in replicas:
         _, _, st = mh.sample_unweighted(x, seed=args.seed, replica=r, seg_work=args.seg_work, stats=True,
-                                        out=(src, dst), workspace=ws)
+                                        out=(src, dst), workspace=ws, grid_blocks=args.grid_blocks)
         steps_total += st["steps"]
     sweep_ms = stage[2] / args.steps
     achieved_lane_ops = steps_total / args.steps * SWEEP_VALU_PER_STEP / (sweep_ms * 1e-3)
@@ -187,6 +286,8 @@ def main():
         "sweep_steps_per_sample": steps_total / args.steps,
         "roofline": roof,
     }
+    if not args.skip_batched:
+        out["batched"] = batched_ensemble(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, args.seed, args.seg_work, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -59,6 +59,8 @@ typedef enum {
 typedef struct {
     int32_t seg_work;
     uint32_t flags; /* reserved, must be 0 */
+    int32_t grid_blocks; /* sweep grid in blocks of 256 threads; 0 = every resident block */
+    int32_t pad;
     /* Optional stage timing: NULL, or an array of MH_STAGE_EVENTS events made
      * by the caller (hipEventCreate).  The samplers record them on `stream` at
      * the start, after the order step, after the bound and plan steps, and after

@@ -48,7 +48,8 @@ class Stats(ctypes.Structure):
 
 
 class PlanParams(ctypes.Structure):
-    _fields_ = [("seg_work", ctypes.c_int32), ("flags", ctypes.c_uint32), ("stage_events", ctypes.c_void_p)]
+    _fields_ = [("seg_work", ctypes.c_int32), ("flags", ctypes.c_uint32), ("grid_blocks", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("stage_events", ctypes.c_void_p)]
 
 
 _lib = None
@@ -133,7 +134,7 @@ class SampleResult:
     stats: dict | None
 
 
-def _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stage_events=None):
+def _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stage_events=None, grid_blocks=0):
     x = _dev_f64(x, "x")
     if y is not None:
         y = _dev_f64(y, "y")
@@ -142,7 +143,7 @@ def _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stag
     n = x.numel()
     dev = x.device
     L = lib()
-    plan = PlanParams(int(seg_work), 0, stage_events)
+    plan = PlanParams(int(seg_work), 0, int(grid_blocks), 0, stage_events)
     wsb = L.mh_workspace_bytes(n, 1 if y is not None else 0, ctypes.byref(plan))
     ws = workspace if workspace is not None and workspace.numel() >= wsb else _workspace(wsb, dev)
     cap = int(capacity) if capacity is not None else max(4096, 4 * n)
@@ -178,20 +179,20 @@ def _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stag
 
 def sample_unweighted(x: torch.Tensor, seed: int = 1, replica: int = 0, seg_work: int = DEFAULT_SEG_WORK,
                       capacity: int | None = None, stats: bool = False, out=None, workspace=None,
-                      stage_events=None):
+                      stage_events=None, grid_blocks: int = 0):
     """One sample of the unweighted model (Sec. 2.4).  Returns (src, dst) int32
     tensors, plus a stats dict when stats=True.  ``out=(src, dst)`` reuses
     buffers (then MH_ECAPACITY raises instead of retrying).  ``stage_events``:
     address of an array of 4 hipEvent_t recorded at the stage boundaries."""
-    r = _sample(x, None, seed, replica, seg_work, capacity, stats, out, workspace, stage_events)
+    r = _sample(x, None, seed, replica, seg_work, capacity, stats, out, workspace, stage_events, grid_blocks)
     return (r.src, r.dst, r.stats) if stats else (r.src, r.dst)
 
 
 def sample_weighted(x: torch.Tensor, y: torch.Tensor, seed: int = 1, replica: int = 0,
                     seg_work: int = DEFAULT_SEG_WORK, capacity: int | None = None, stats: bool = False, out=None,
-                    workspace=None, stage_events=None):
+                    workspace=None, stage_events=None, grid_blocks: int = 0):
     """One sample of the weighted model (Sec. 2.5, Alg. 1): (src, dst, w)."""
-    r = _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stage_events)
+    r = _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stage_events, grid_blocks)
     return (r.src, r.dst, r.w, r.stats) if stats else (r.src, r.dst, r.w)
 
 
@@ -242,7 +243,7 @@ def order(x: torch.Tensor, y: torch.Tensor | None = None):
     zs = torch.empty(n, dtype=torch.float64, device=dev)
     ys = torch.empty(n, dtype=torch.float64, device=dev) if y is not None else None
     status = torch.zeros(1, dtype=torch.int32, device=dev)
-    plan = PlanParams(DEFAULT_SEG_WORK, 0, None)
+    plan = PlanParams(DEFAULT_SEG_WORK, 0, 0, 0, None)
     ws = _workspace(L.mh_workspace_bytes(n, 1 if y is not None else 0, ctypes.byref(plan)), dev)
     _check(L.mh_order(_ptr(x), _ptr(y), n, _ptr(perm), _ptr(zs), _ptr(ys), _ptr(status), _ptr(ws), ws.numel(),
                       _stream(dev)), "mh_order")

@@ -203,11 +203,12 @@ size_t sample_workspace_bytes(int64_t n, bool weighted, int32_t T) {
 }
 
 template <bool W, bool S>
-void launch_sweep(const SweepLaunch& A, int64_t n, hipStream_t stream) {
+void launch_sweep(const SweepLaunch& A, int64_t n, int32_t grid_blocks, hipStream_t stream) {
     auto kern = k_sweep<W, S, false, OUT_EDGES>;
     int64_t want = (n + kWave - 1) / kWave;
     if (want < 16) want = 16;
-    const int64_t cap = resident_blocks(kern, kThreads);
+    int64_t cap = resident_blocks(kern, kThreads);
+    if (grid_blocks > 0 && grid_blocks < cap) cap = grid_blocks;
     hipLaunchKernelGGL(kern, dim3((unsigned)(want < cap ? want : cap)), dim3(kThreads), 0, stream, A);
 }
 
@@ -220,7 +221,7 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
     if (!x && n > 0) return MH_EINVAL;
     if (capacity > 0 && (!src || !dst || (weighted && !w))) return MH_EINVAL;
     const int32_t T = plan ? plan->seg_work : 32;
-    if (T < 0 || (plan && plan->flags != 0)) return MH_EINVAL;
+    if (T < 0 || (plan && (plan->flags != 0 || plan->grid_blocks < 0))) return MH_EINVAL;
     *n_edges_host = 0;
     if (stats_host) *stats_host = mh_stats{0, 0, 0, 0, 0, 0};
     if (n == 0) return MH_OK;
@@ -250,12 +251,13 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
     A.out = EdgeOut{src, dst, w, capacity, &ctr->n_edges};
     A.sid = nullptr;
     A.ctr = ctr;
+    const int32_t gb = plan ? plan->grid_blocks : 0;
     if (weighted) {
-        if (stats_host) launch_sweep<true, true>(A, n, stream);
-        else launch_sweep<true, false>(A, n, stream);
+        if (stats_host) launch_sweep<true, true>(A, n, gb, stream);
+        else launch_sweep<true, false>(A, n, gb, stream);
     } else {
-        if (stats_host) launch_sweep<false, true>(A, n, stream);
-        else launch_sweep<false, false>(A, n, stream);
+        if (stats_host) launch_sweep<false, true>(A, n, gb, stream);
+        else launch_sweep<false, false>(A, n, gb, stream);
     }
     MH_HIP_TRY(hipGetLastError());
     if (ev) MH_HIP_TRY(hipEventRecord(ev[3], stream));

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(L):
 def test_workspace_sizes_grow_with_n(L):
     import paper_2509_13230_amd as mh
 
-    p = mh.PlanParams(32, 0)
+    p = mh.PlanParams(32, 0, 0, 0, None)
     a = L.mh_workspace_bytes(1000, 0, ctypes.byref(p))
     b = L.mh_workspace_bytes(1_000_000, 0, ctypes.byref(p))
     c = L.mh_workspace_bytes(1_000_000, 1, ctypes.byref(p))
@@ -69,7 +69,7 @@ def test_argument_errors_return_before_device_work(L):
     # negative plan parameter
     import paper_2509_13230_amd as mh
 
-    bad = mh.PlanParams(-3, 0)
+    bad = mh.PlanParams(-3, 0, 0, 0, None)
     assert L.mh_sample_unweighted(ctypes.c_void_p(16), 10, 1, 0, ctypes.byref(bad), ctypes.c_void_p(16),
                                   ctypes.c_void_p(16), 5, ctypes.byref(n), ctypes.c_void_p(256), 1 << 20, None,
                                   None) == -1
