@@ -207,8 +207,17 @@ void launch_sweep(const SweepLaunch& A, int64_t n, int32_t grid_blocks, hipStrea
     auto kern = k_sweep<W, S, false, OUT_EDGES>;
     int64_t want = (n + kWave - 1) / kWave;
     if (want < 16) want = 16;
+    // Default: 3 blocks (12 waves) per CU.  With fewer, larger per-wave item
+    // lists the lanes of a wave stay busier while its long chains finish, and
+    // 3 waves per SIMD still cover the load latency (measured on N = 1e6).
     int64_t cap = resident_blocks(kern, kThreads);
-    if (grid_blocks > 0 && grid_blocks < cap) cap = grid_blocks;
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (grid_blocks > 0) {
+        if (grid_blocks < cap) cap = grid_blocks;
+    } else if ((int64_t)3 * cus < cap) {
+        cap = (int64_t)3 * cus;
+    }
     hipLaunchKernelGGL(kern, dim3((unsigned)(want < cap ? want : cap)), dim3(kThreads), 0, stream, A);
 }
 
@@ -220,7 +229,7 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
     if (!n_edges_host || n < 0 || n > 0x7FFFFFFFll || capacity < 0) return MH_EINVAL;
     if (!x && n > 0) return MH_EINVAL;
     if (capacity > 0 && (!src || !dst || (weighted && !w))) return MH_EINVAL;
-    const int32_t T = plan ? plan->seg_work : 32;
+    const int32_t T = plan ? plan->seg_work : 16;
     if (T < 0 || (plan && (plan->flags != 0 || plan->grid_blocks < 0))) return MH_EINVAL;
     *n_edges_host = 0;
     if (stats_host) *stats_host = mh_stats{0, 0, 0, 0, 0, 0};
@@ -318,7 +327,7 @@ mh_status plan_counts_impl(const double* zs, const double* c, int64_t n, int32_t
 extern "C" {
 
 size_t mh_workspace_bytes(int64_t n, int weighted, const mh_plan_params* plan) {
-    return mh::sample_workspace_bytes(n, weighted != 0, plan ? plan->seg_work : 32);
+    return mh::sample_workspace_bytes(n, weighted != 0, plan ? plan->seg_work : 16);
 }
 
 mh_status mh_sample_unweighted(const double* x, int64_t n, uint64_t seed, uint32_t replica,
