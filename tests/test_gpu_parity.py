@@ -153,12 +153,12 @@ def test_edge_cases(mh):
     for x in (np.zeros(0), np.array([2.0]), np.array([3.0, 0.5]), np.zeros(100), np.full(500, 0.2)):
         if len(x) == 0:
             continue
-        src, dst = mh.sample_unweighted(dev(x), seed=3)
+        src, dst = mh.sample_unweighted(dev(x), seed=3, seg_work=32)
         ora = oracle.sample_mh(x, None, seed=3, seg_work=32)
         compare_edges((src, dst), ora, len(x), ora.tie_rows)
     x = np.full(400, 0.3)
     y = np.full(400, 0.7)
-    src, dst, w = mh.sample_weighted(dev(x), dev(y), seed=4)
+    src, dst, w = mh.sample_weighted(dev(x), dev(y), seed=4, seg_work=32)
     ora = oracle.sample_mh(x, y, seed=4, seg_work=32)
     compare_edges((src, dst, w), ora, 400, ora.tie_rows, weighted=True)
 
@@ -250,3 +250,36 @@ def test_expected_degree_grad_matches_oracle(mh, weighted):
     assert np.max(np.abs(gx.cpu().numpy() - rx)) <= 1e-10 * scale
     if weighted:
         assert np.max(np.abs(gy.cpu().numpy() - ry)) <= 1e-10 * np.abs(ry).max()
+
+
+# ------------------------------------------------------------------ full sizes
+def test_full_size_unweighted_matches_oracle(mh):
+    # N = 1,000,000, power-law targets (exponent 2.1, k in [1, 1e4]); the bench's
+    # launch configuration (seg_work 16, default grid).  x follows the
+    # sparse-limit recipe of the targets (inputs never come from the device).
+    x = workloads.chung_lu_scale(workloads.cfg2_degrees())
+    for replica in (1000, 1001):
+        src, dst = mh.sample_unweighted(dev(x), seed=1, replica=replica, seg_work=16)
+        ora = oracle.sample_mh(x, None, seed=1, replica=replica, seg_work=16, capacity=3_000_000)
+        compare_edges((src, dst), ora, len(x), ora.tie_rows)
+
+
+def test_full_size_weighted_matches_oracle(mh):
+    # N = 200,000 weighted targets (k power law 2.3 on [1, 5000], s = k (1 + Gamma(2, 3)))
+    k, s = workloads.cfg3_targets()
+    x, y = workloads.uecm_recipe(k, s)
+    src, dst, w = mh.sample_weighted(dev(x), dev(y), seed=1, replica=7, seg_work=16)
+    ora = oracle.sample_mh(x, y, seed=1, replica=7, seg_work=16, capacity=2_000_000)
+    compare_edges((src, dst, w), ora, len(x), ora.tie_rows, weighted=True)
+
+
+def test_bruteforce_50k_prefix_sampled_rows(mh):
+    # all 1.25e9 pairs of the first 50,000 nodes on the GPU; rows checked one by one
+    x = workloads.chung_lu_scale(workloads.cfg2_degrees())[:50_000]
+    src, dst = mh.sample_bruteforce(dev(x), seed=2, replica=0, capacity=4_000_000)
+    src, dst = src.cpu().numpy(), dst.cpu().numpy()
+    rng = np.random.default_rng(0)
+    rows = np.concatenate([np.arange(0, 40), rng.choice(50_000, 40, replace=False), np.arange(49_990, 50_000)])
+    for i in rows:
+        s, d, _, _ = oracle.sample_bf(x, None, seed=2, replica=0, row_begin=int(i), row_end=int(i) + 1)
+        assert np.array_equal(np.sort(dst[src == i]), np.sort(d)), i
