@@ -10,7 +10,10 @@ the expected-degree kernel and its adjoint:
 * weighted: Newton-CG on the convex negative log-likelihood in natural
   coordinates (log x, log y).  Its gradient is (k(x,y) - k*, s(x,y) - s*) and
   its Hessian-vector product is the adjoint of (k, s) applied to the vector,
-  times (x, y) by the chain rule.
+  times (x, y) by the chain rule.  CG is Jacobi-preconditioned with the
+  leading diagonal terms (m k, m s); the step length comes from the sign of
+  the directional derivative along the Newton direction (the objective is
+  convex), bisected when the full step overshoots.
 
 Residuals are reported as max_c |k_c - k*_c| / k*_c (and the same for s).
 """
@@ -68,7 +71,8 @@ def fit_uecm(k_target, s_target, tol: float = 1e-8, max_newton: int = 200, cg_it
     """Fit (x, y) so that expected degrees and strengths match the targets.
 
     Requires 0 < k_i <= s_i.  Nodes with s_i == k_i have no finite MLE (y -> 0,
-    x -> infinity with x*y finite); they are held at y = 1e-12.
+    x -> infinity with x*y finite); their y is held at its start, 1e-6, and only
+    x is fitted for them (their strength then exceeds k_i by a relative ~1e-6).
     """
     k_target = np.asarray(k_target, dtype=np.float64)
     s_target = np.asarray(s_target, dtype=np.float64)
@@ -105,6 +109,10 @@ def fit_uecm(k_target, s_target, tol: float = 1e-8, max_newton: int = 200, cg_it
         h2 = torch.where(free_y, gy * y, torch.zeros_like(gy))
         return h1, h2
 
+    def feasible(et_n):
+        top = torch.topk(et_n, 2).values if et_n.numel() >= 2 else et_n
+        return et_n.numel() < 2 or float(top[0] + top[1]) < 0
+
     res_k = res_s = np.inf
     it = 0
     for it in range(1, max_newton + 1):
@@ -115,42 +123,61 @@ def fit_uecm(k_target, s_target, tol: float = 1e-8, max_newton: int = 200, cg_it
             print(f"newton {it}: res_k={res_k:.3e} res_s={res_s:.3e}")
         if res_k <= tol and res_s <= tol:
             break
-        # conjugate gradients on H d = -g
+        # preconditioned conjugate gradients on H d = -g; Jacobi scale from the
+        # diagonal's leading terms (m k for log x, m s for log y)
+        P1 = 1.0 / torch.clamp(mult * k, min=1e-300)
+        P2 = torch.where(free_y, 1.0 / torch.clamp(mult * s, min=1e-300), torch.zeros_like(s))
         d1 = torch.zeros_like(g1)
         d2 = torch.zeros_like(g2)
         r1, r2 = -g1, -g2
-        p1, p2 = r1.clone(), r2.clone()
-        rr = float((r1 * r1).sum() + (r2 * r2).sum())
-        rr0 = rr
+        z1, z2 = P1 * r1, P2 * r2
+        p1, p2 = z1.clone(), z2.clone()
+        rz = float((r1 * z1).sum() + (r2 * z2).sum())
+        rz0 = rz
         for _ in range(cg_iters):
             h1, h2 = hvp(th, et, p1, p2)
             php = float((p1 * h1).sum() + (p2 * h2).sum())
             if php <= 0:
                 break
-            a = rr / php
+            a = rz / php
             d1 += a * p1
             d2 += a * p2
             r1 -= a * h1
             r2 -= a * h2
-            rr_new = float((r1 * r1).sum() + (r2 * r2).sum())
-            if rr_new <= 1e-24 * rr0:
+            z1, z2 = P1 * r1, P2 * r2
+            rz_new = float((r1 * z1).sum() + (r2 * z2).sum())
+            if rz_new <= 1e-28 * rz0:
                 break
-            p1 = r1 + (rr_new / rr) * p1
-            p2 = r2 + (rr_new / rr) * p2
-            rr = rr_new
-        # backtracking on feasibility (y_i y_j < 1) and gradient norm
-        step = 1.0
-        gn = float((g1 * g1).sum() + (g2 * g2).sum())
-        for _ in range(30):
-            th_n = th + step * d1
-            et_n = torch.clamp(et + step * d2, max=-1e-12)
-            ys = torch.sort(et_n, descending=True).values
-            feasible = ys.numel() < 2 or float(ys[0] + ys[1]) < 0
-            if feasible:
-                n1, n2, _, _ = grad(th_n, et_n)
-                if float((n1 * n1).sum() + (n2 * n2).sum()) < gn or step < 1e-6:
-                    break
-            step *= 0.5
+            p1 = z1 + (rz_new / rz) * p1
+            p2 = z2 + (rz_new / rz) * p2
+            rz = rz_new
+        # line search on the directional derivative phi'(t) = d . grad(theta + t d) (convex):
+        # keep t = 1 while phi' < 0 there, else bisect for phi' = 0 on [0, 1]
+        def dphi(t):
+            et_n = torch.clamp(et + t * d2, max=-1e-12)
+            if not feasible(et_n):
+                return None, None, None
+            n1, n2, _, _ = grad(th + t * d1, et_n)
+            return float((d1 * n1).sum() + (d2 * n2).sum()), th + t * d1, et_n
+
+        t_hi = 1.0
+        val, th_n, et_n = dphi(t_hi)
+        while val is None and t_hi > 1e-8:
+            t_hi *= 0.5
+            val, th_n, et_n = dphi(t_hi)
+        if val is None:
+            break
+        if val > 0:
+            lo, hi = 0.0, t_hi
+            for _ in range(12):
+                mid = 0.5 * (lo + hi)
+                v, th_m, et_m = dphi(mid)
+                if v is None or v > 0:
+                    hi = mid
+                else:
+                    lo, th_n, et_n = mid, th_m, et_m
+            if lo == 0.0:
+                _, th_n, et_n = dphi(hi)
         th, et = th_n, et_n
     x, y = torch.exp(th), torch.exp(et)
     return FitResult(x=x.cpu().numpy()[inv], y=y.cpu().numpy()[inv], iterations=it, residual=res_k, residual_s=res_s)
