@@ -3,6 +3,7 @@
 // (product of the two largest y among the ranks not yet processed).
 #include "mh_common.hpp"
 #include "mh_internal.hpp"
+#include "mh_sweep_core.hpp"
 
 namespace mh {
 
@@ -93,14 +94,20 @@ __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict
 __global__ __launch_bounds__(kThreads) void k_finish_order(const uint64_t* __restrict__ keys,
                                                            const uint32_t* __restrict__ vals, int64_t n,
                                                            int32_t* __restrict__ perm, double* __restrict__ zs,
+                                                           NodeRec* __restrict__ node,
                                                            const double* __restrict__ y, double* __restrict__ ys,
                                                            uint64_t* __restrict__ mass, int32_t* status) {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= n) return;
     const uint32_t id = vals[r];
     const double z = key_value(keys[r]);
-    perm[r] = (int32_t)id;
-    zs[r] = z;
+    if (node) {
+        node[r].z = z;
+        node[r].id = (int32_t)id;
+    } else {
+        perm[r] = (int32_t)id;
+        zs[r] = z;
+    }
     if (ys) ys[r] = y[id];
     if (mass) mass[r] = mass_q(z);
     if (r == 0 && !isfinite(z * z)) raise_status(status, MH_EINVAL);
@@ -240,7 +247,8 @@ size_t order_workspace_bytes(int64_t n) {
 }
 
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
-                      int32_t* status, uint64_t* mass_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+                      NodeRec* node, int32_t* status, uint64_t* mass_out, void* ws, size_t ws_bytes,
+                      hipStream_t stream) {
     if (n <= 0) return MH_OK;
     Arena ar(ws, ws_bytes);
     uint64_t* keys = ar.take<uint64_t>(n);
@@ -260,8 +268,8 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
     st = radix_sort_u64(keys, vals, keys_alt, vals_alt, n, sort_ws, sort_bytes, true, status, stream);
     if (st != MH_OK) return st;
     const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_finish_order, dim3(grid), dim3(kThreads), 0, stream, keys, vals, n, perm, zs, y, y ? ys : nullptr,
-                       mass_out, status);
+    hipLaunchKernelGGL(k_finish_order, dim3(grid), dim3(kThreads), 0, stream, keys, vals, n, perm, zs, node, y,
+                       y ? ys : nullptr, mass_out, status);
     MH_HIP_TRY(hipGetLastError());
     return MH_OK;
 }

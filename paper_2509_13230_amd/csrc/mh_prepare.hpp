@@ -9,12 +9,10 @@ namespace mh {
 
 // Device buffers of one prepared network (writable views of a NetDesc).
 struct NetBuffers {
-    int32_t* perm;
-    double* zs;
+    NodeRec* node;
     double* ys;
     double* c;
     uint64_t* P;
-    int32_t* nseg;
     int32_t* jend;
     uint64_t* mq;
     uint64_t* hoff;

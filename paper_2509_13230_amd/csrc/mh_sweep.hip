@@ -13,10 +13,21 @@ namespace {
 
 constexpr int kThreads = kSweepThreads;
 
-__global__ __launch_bounds__(kThreads) void k_mass_of_sorted(const double* __restrict__ zs, int64_t n,
-                                                             uint64_t* __restrict__ mass) {
+// Packs separately given sorted z into node records and their column masses
+// (used by the stand-alone plan entry point).
+__global__ __launch_bounds__(kThreads) void k_pack_sorted(const double* __restrict__ zs, int64_t n,
+                                                          NodeRec* __restrict__ node, uint64_t* __restrict__ mass) {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (r < n) mass[r] = mass_q(zs[r]);
+    if (r >= n) return;
+    node[r].z = zs[r];
+    node[r].id = (int32_t)r;
+    if (mass) mass[r] = mass_q(zs[r]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_unpack_nseg(const NodeRec* __restrict__ node, int64_t n,
+                                                          int32_t* __restrict__ nseg) {
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r < n) nseg[r] = node[r].nseg;
 }
 
 __global__ void k_init_counters(Counters* c) {
@@ -29,25 +40,25 @@ __global__ void k_init_counters(Counters* c) {
 }
 
 // ---- plan: per row, the number of segments and the data to locate them ----
-__global__ __launch_bounds__(kThreads) void k_row_plan(const double* __restrict__ zs, const double* __restrict__ c,
+__global__ __launch_bounds__(kThreads) void k_row_plan(NodeRec* __restrict__ node, const double* __restrict__ c,
                                                        int64_t n, int32_t T, const uint64_t* __restrict__ P,
-                                                       int32_t* __restrict__ nseg, int32_t* __restrict__ jend,
+                                                       int32_t* __restrict__ jend,
                                                        uint64_t* __restrict__ mq, uint64_t* __restrict__ hn) {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= n) return;
     int64_t total = 0;
-    const double s = zs[r];
+    const double s = node[r].z;
     if (r < n - 1 && s != 0.0) {
         if (T <= 0) {
             total = 1;
         } else {
             const double cr = c ? c[r] : 1.0;
             int64_t J = r + 1;
-            if (s * zs[r + 1] >= cr) {
+            if (s * node[r + 1].z >= cr) {
                 int64_t lo = r + 2, hi = n;  // first j in [lo, n] with s*zs[j] < cr (n if none)
                 while (lo < hi) {
                     const int64_t mid = lo + (hi - lo) / 2;
-                    if (s * zs[mid] < cr) hi = mid; else lo = mid + 1;
+                    if (s * node[mid].z < cr) hi = mid; else lo = mid + 1;
                 }
                 J = lo;
             }
@@ -67,7 +78,7 @@ __global__ __launch_bounds__(kThreads) void k_row_plan(const double* __restrict_
             mq[r] = m;
         }
     }
-    nseg[r] = total > 0x7FFFFFFF ? 0x7FFFFFFF : (int32_t)total;
+    node[r].nseg = total > 0x7FFFFFFF ? 0x7FFFFFFF : (int32_t)total;
     if (hn) hn[r] = total >= 2 ? (uint64_t)total : 0ull;
 }
 
@@ -87,12 +98,10 @@ template <typename A>
 static NetBuffers carve_network_impl(A& ar, int64_t n, bool weighted, int32_t T) {
     const bool seg = T > 0;
     NetBuffers B{};
-    B.perm = ar.template take<int32_t>(n);
-    B.zs = ar.template take<double>(n);
+    B.node = ar.template take<NodeRec>(n);
     B.ys = ar.template take<double>(weighted ? n : 0);
     B.c = ar.template take<double>(weighted ? n : 0);
     B.P = ar.template take<uint64_t>(seg ? n + 1 : 0);
-    B.nseg = ar.template take<int32_t>(n);
     B.jend = ar.template take<int32_t>(seg ? n : 0);
     B.mq = ar.template take<uint64_t>(seg ? n : 0);
     B.hoff = ar.template take<uint64_t>(seg ? n + 1 : 0);
@@ -138,11 +147,9 @@ size_t prepare_scratch_bytes(int64_t n) {
 
 NetDesc net_desc(const NetBuffers& B) {
     NetDesc D;
-    D.zs = B.zs;
+    D.node = B.node;
     D.ys = B.ys;
     D.c = B.c;
-    D.perm = B.perm;
-    D.nseg = B.nseg;
     D.jend = B.jend;
     D.mq = B.mq;
     D.P = B.P;
@@ -167,8 +174,8 @@ mh_status prepare_network(const double* x, const double* y, const NetBuffers& B,
     const int64_t n = B.n;
     if (n <= 0) return MH_OK;
     const bool seg = B.T > 0;
-    mh_status st = order_nodes(x, B.weighted ? y : nullptr, n, B.perm, B.zs, B.ys, status, B.P, scratch,
-                               scratch_bytes, stream);
+    mh_status st = order_nodes(x, B.weighted ? y : nullptr, n, nullptr, nullptr, B.ys, B.node, status, B.P,
+                               scratch, scratch_bytes, stream);
     if (st != MH_OK) return st;
     if (ev) MH_HIP_TRY(hipEventRecord(ev[1], stream));
     if (B.weighted) {
@@ -180,8 +187,8 @@ mh_status prepare_network(const double* x, const double* y, const NetBuffers& B,
         if (st != MH_OK) return st;
     }
     const unsigned rows_grid = (unsigned)((n + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_row_plan, dim3(rows_grid), dim3(kThreads), 0, stream, B.zs, B.c, n, B.T, B.P, B.nseg,
-                       B.jend, B.mq, B.hoff);
+    hipLaunchKernelGGL(k_row_plan, dim3(rows_grid), dim3(kThreads), 0, stream, B.node, B.c, n, B.T, B.P, B.jend,
+                       B.mq, B.hoff);
     MH_HIP_TRY(hipGetLastError());
     if (seg) {
         st = scan_exclusive_u64(B.hoff, B.hoff, n, scratch, scratch_bytes, stream);
@@ -293,6 +300,7 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
 // ---- plan counts entry (also used by the C-ABI) ----
 size_t plan_workspace_bytes_impl(int64_t n) {
     Sizer s;
+    s.take<NodeRec>(n);
     s.take<uint64_t>(n + 1);
     s.take<int32_t>(n);
     s.take<uint64_t>(n);
@@ -304,20 +312,23 @@ mh_status plan_counts_impl(const double* zs, const double* c, int64_t n, int32_t
     if (n < 0 || T < 0 || (n > 0 && (!zs || !nseg))) return MH_EINVAL;
     if (n == 0) return MH_OK;
     Arena ar(ws, ws_bytes);
+    NodeRec* node = ar.take<NodeRec>(n);
     uint64_t* P = ar.take<uint64_t>(n + 1);
     int32_t* jend = ar.take<int32_t>(n);
     uint64_t* mq = ar.take<uint64_t>(n);
     if (ar.overflow) return MH_EWORKSPACE;
     const size_t off = (ar.used + 255) & ~size_t(255);
     const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_pack_sorted, dim3(grid), dim3(kThreads), 0, stream, zs, n, node, T > 0 ? P : nullptr);
+    MH_HIP_TRY(hipGetLastError());
     if (T > 0) {
-        hipLaunchKernelGGL(k_mass_of_sorted, dim3(grid), dim3(kThreads), 0, stream, zs, n, P);
-        MH_HIP_TRY(hipGetLastError());
         mh_status st = scan_exclusive_u64(P, P, n, ar.base + off, ws_bytes - off, stream);
         if (st != MH_OK) return st;
     }
-    hipLaunchKernelGGL(k_row_plan, dim3(grid), dim3(kThreads), 0, stream, zs, c, n, T, P, nseg, jend, mq,
+    hipLaunchKernelGGL(k_row_plan, dim3(grid), dim3(kThreads), 0, stream, node, c, n, T, P, jend, mq,
                        (uint64_t*)nullptr);
+    MH_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_unpack_nseg, dim3(grid), dim3(kThreads), 0, stream, node, n, nseg);
     MH_HIP_TRY(hipGetLastError());
     return MH_OK;
 }

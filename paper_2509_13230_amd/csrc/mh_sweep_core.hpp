@@ -34,13 +34,19 @@ struct HeavyRec {
     int32_t r, g, a, b;
 };
 
+// One node by rank, packed so that a candidate costs one 16-byte load (one
+// cache line) instead of separate gathers of z and id.
+struct __attribute__((aligned(16))) NodeRec {
+    double z;      // sorted key z (descending)
+    int32_t id;    // node id at this rank
+    int32_t nseg;  // segments of this rank's row
+};
+
 // A prepared network: sorted parameters, bound and plan.
 struct NetDesc {
-    const double* zs;
+    const NodeRec* node;
     const double* ys;  // weighted only
     const double* c;   // weighted only
-    const int32_t* perm;
-    const int32_t* nseg;
     const int32_t* jend;
     const uint64_t* mq;
     const uint64_t* P;
@@ -148,9 +154,8 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
     int32_t id = 0, sample = 0, row_deg = 0;
     double s = 0.0, cr = 1.0, ysr = 0.0, tq = 0.0, U2 = 0.0;
     // the lane's network
-    const double* zs = A.net.zs;
+    const NodeRec* node = A.net.node;
     const double* ys = A.net.ys;
-    const int32_t* perm = A.net.perm;
     int32_t* deg = nullptr;
     // values in flight from the previous iteration's loads
     double ld_s = 0.0, ld_z = 0.0, ld_c = 1.0, ld_y = 0.0;
@@ -228,9 +233,10 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
                 state = S_IDLE;
             } else {
                 const NetDesc& D = BATCH ? A.batch.nets[A.batch.sample_net[sample]] : A.net;
-                ld_s = zs[r];
-                ld_z = zs[pos];
-                ld_id = perm[r];
+                const NodeRec nr = node[r];
+                ld_s = nr.z;
+                ld_id = nr.id;
+                ld_z = node[pos].z;
                 if (WEIGHTED) {
                     ld_c = D.c[r];
                     ld_y = ys[r];
@@ -256,8 +262,9 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
                     U2 = U2n;
                     scand = step;
                     ++step;
-                    ld_z = zs[jc];
-                    ld_id = perm[jc];
+                    const NodeRec nj = node[jc];
+                    ld_z = nj.z;
+                    ld_id = nj.id;
                     if (WEIGHTED) ld_y = ys[jc];
                     state = S_STEP;
                 }
@@ -289,9 +296,8 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
                         Dp = &A.batch.nets[A.batch.sample_net[lo]];
                         replica = A.batch.sample_rep[lo];
                         H = heavy_items(*Dp);
-                        zs = Dp->zs;
+                        node = Dp->node;
                         ys = Dp->ys;
-                        perm = Dp->perm;
                         if (OUT == OUT_DEGREES) deg = A.batch.degrees + A.batch.deg_off[lo];
                     }
                     if (it < H) {
@@ -304,10 +310,11 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
                         tag = 0;
                         step = 0;
                         check_light = true;
-                        ld_n = Dp->nseg[r];
-                        ld_s = zs[r];
-                        ld_z = ld_s;
-                        ld_id = perm[r];
+                        const NodeRec nr = node[r];
+                        ld_n = nr.nseg;
+                        ld_s = nr.z;
+                        ld_z = nr.z;
+                        ld_id = nr.id;
                         if (WEIGHTED) {
                             ld_c = Dp->c[r];
                             ld_y = ys[r];
