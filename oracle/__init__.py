@@ -60,6 +60,13 @@ def lib() -> ctypes.CDLL:
         L.mho_plan_row.restype = i64
         L.mho_sample_mh.argtypes = [vp, vp, i64, u64, u32, i32, vp, vp, vp, i64, vp, vp, i64, P(i64)]
         L.mho_sample_mh.restype = i64
+        L.mho_sample_bipartite.argtypes = [vp, vp, i64, vp, vp, i64, ctypes.c_int, u64, u32, i32, vp, vp, vp, i64,
+                                           vp, vp, i64, P(i64)]
+        L.mho_sample_bipartite.restype = i64
+        L.mho_sample_bipartite_bf.argtypes = [vp, vp, i64, vp, vp, i64, ctypes.c_int, u64, u32, vp, vp, vp, i64]
+        L.mho_sample_bipartite_bf.restype = i64
+        L.mho_plan_row_bipartite.argtypes = [vp, i64, d, d, i32, vp, vp, i64]
+        L.mho_plan_row_bipartite.restype = i64
         L.mho_sample_bf.argtypes = [vp, vp, i64, u64, u32, i64, i64, vp, vp, vp, i64, P(i64)]
         L.mho_sample_bf.restype = i64
         L.mho_expected_degree.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
@@ -226,3 +233,52 @@ def expected_degree_grad(x, y=None, mult=None, gk=None, gs=None):
     gy = np.zeros(n) if y is not None else None
     lib().mho_expected_degree_grad(_p(x), _p(y), _p(mult), n, _p(gk), _p(gs), _p(gx), _p(gy))
     return gx, gy
+
+
+def sample_bipartite(xr, xc, yr=None, yc=None, exclude_self=False, seed: int = 1, replica: int = 0,
+                     seg_work: int = 0, capacity: int | None = None) -> Sample:
+    """Bipartite (rows = "+" set, columns = "-" set) or, with exclude_self,
+    directed sampler (rows = out-parameters, columns = in-parameters)."""
+    xr, xc, yr, yc = _f64(xr), _f64(xc), _f64(yr), _f64(yc)
+    st = Stats()
+    ntr = ctypes.c_int64(0)
+    cap = capacity if capacity is not None else max(1024, 8 * (len(xr) + len(xc)))
+    while True:
+        src = np.zeros(cap, dtype=np.int32)
+        dst = np.zeros(cap, dtype=np.int32)
+        w = np.zeros(cap, dtype=np.int32) if yr is not None else None
+        ties = np.zeros(1024, dtype=np.int32)
+        m = lib().mho_sample_bipartite(_p(xr), _p(yr), len(xr), _p(xc), _p(yc), len(xc), int(exclude_self), seed,
+                                       replica, seg_work, _p(src), _p(dst), _p(w), cap, ctypes.byref(st), _p(ties),
+                                       len(ties), ctypes.byref(ntr))
+        if m < 0:
+            raise ValueError("oracle: invalid parameters (code %d)" % m)
+        if m <= cap:
+            break
+        cap = int(m)
+    return Sample(src[:m], dst[:m], None if w is None else w[:m], st.as_dict(),
+                  ties[: min(ntr.value, len(ties))].copy())
+
+
+def sample_bipartite_bf(xr, xc, yr=None, yc=None, exclude_self=False, seed: int = 1, replica: int = 0,
+                        capacity: int | None = None):
+    xr, xc, yr, yc = _f64(xr), _f64(xc), _f64(yr), _f64(yc)
+    cap = capacity if capacity is not None else max(1024, len(xr) * len(xc))
+    src = np.zeros(cap, dtype=np.int32)
+    dst = np.zeros(cap, dtype=np.int32)
+    w = np.zeros(cap, dtype=np.int32) if yr is not None else None
+    m = lib().mho_sample_bipartite_bf(_p(xr), _p(yr), len(xr), _p(xc), _p(yc), len(xc), int(exclude_self), seed,
+                                      replica, _p(src), _p(dst), _p(w), cap)
+    if m < 0:
+        raise ValueError("oracle: invalid parameters (code %d)" % m)
+    return src[:m], dst[:m], (None if w is None else w[:m])
+
+
+def plan_row_bipartite(zcs, s: float, c: float, seg_work: int):
+    """Column segments [a_k, b_k) of one bipartite row (value s, bound c)."""
+    zcs = _f64(zcs)
+    cnt = lib().mho_plan_row_bipartite(_p(zcs), len(zcs), s, c, seg_work, None, None, 0)
+    a = np.zeros(max(cnt, 1), dtype=np.int64)
+    b = np.zeros(max(cnt, 1), dtype=np.int64)
+    lib().mho_plan_row_bipartite(_p(zcs), len(zcs), s, c, seg_work, _p(a), _p(b), cnt)
+    return a[:cnt], b[:cnt]

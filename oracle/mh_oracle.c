@@ -379,6 +379,225 @@ done:
     return es.count;
 }
 
+/* ------------------------------------------------------------------ bipartite */
+/* Bipartite and directed networks (Sec. 2.6): the "+" nodes (rows) and the "-"
+   nodes (columns) are sorted by their own parameters, and every "+" node sweeps
+   the whole "-" list with the same skip / accept / update rule.  Readings:
+   the chain of a column range [a, b) starts before column a with the proposal
+   probability of column a itself (it bounds every later column); the weighted
+   bound of row r is Y_r = y_r * (largest column y) (the smallest beta_+ + beta_-
+   that row r can meet); the same segment rule cuts a row's column range, with
+   first column 0 instead of r + 1. */
+static row_plan bip_row_info(const plan_ctx* cols, double s, double c) {
+    row_plan rp = {0, 0, 0, 0};
+    int64_t nc = cols->n;
+    if (nc == 0 || s == 0.0) return rp;
+    if (cols->seg_work <= 0) { rp.J = nc; rp.nd = 1; return rp; }
+    int64_t T = cols->seg_work;
+    rp.J = first_below(cols, s, c, 0, nc);
+    rp.nd = (rp.J + T - 1) / T;
+    if (rp.J < nc) {
+        double md = ((double)T * c / s) * 4294967296.0;
+        uint64_t m;
+        if (!(md < 4611686018427387904.0)) m = (uint64_t)1 << 62;
+        else if (md < 1.0) m = 1;
+        else m = (uint64_t)md;
+        uint64_t mass = cols->P[nc] - cols->P[rp.J];
+        rp.m = m;
+        rp.ns = (mass == 0) ? 1 : (int64_t)((mass + m - 1) / m);
+    }
+    return rp;
+}
+
+static void bip_segment(const plan_ctx* cols, const row_plan* rp, int64_t k, int64_t* a, int64_t* b) {
+    int64_t nc = cols->n;
+    if (cols->seg_work <= 0) { *a = 0; *b = nc; return; }
+    int64_t T = cols->seg_work;
+    if (k < rp->nd) {
+        *a = k * T;
+        int64_t e = (k + 1) * T;
+        *b = e < rp->J ? e : rp->J;
+        return;
+    }
+    int64_t kk = k - rp->nd;
+    uint64_t base = cols->P[rp->J];
+    *a = (kk == 0) ? rp->J : lower_bound_mass(cols, rp->J, nc, base + (uint64_t)kk * rp->m);
+    *b = (kk == rp->ns - 1) ? nc : lower_bound_mass(cols, rp->J, nc, base + (uint64_t)(kk + 1) * rp->m);
+}
+
+int64_t mho_plan_row_bipartite(const double* zcs, int64_t nc, double s, double c, int32_t seg_work,
+                               int64_t* a, int64_t* b, int64_t cap) {
+    plan_ctx cols;
+    if (plan_init(&cols, zcs, NULL, nc, seg_work) != MHO_OK) return MHO_EINVAL;
+    row_plan rp = bip_row_info(&cols, s, c);
+    int64_t cnt = rp.nd + rp.ns;
+    for (int64_t k = 0; k < cnt && k < cap; ++k) bip_segment(&cols, &rp, k, &a[k], &b[k]);
+    plan_free(&cols);
+    return cnt;
+}
+
+static int finite_nonneg(const double* v, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!(v[i] >= 0.0) || !isfinite(v[i])) return 0;
+    return 1;
+}
+
+static int valid_bip(const double* xr, const double* yr, int64_t nr, const double* xc, const double* yc, int64_t nc) {
+    if (nr < 0 || nc < 0 || nr > 2147483647LL || nc > 2147483647LL) return 0;
+    if (!finite_nonneg(xr, nr) || !finite_nonneg(xc, nc)) return 0;
+    if (yr && (!finite_nonneg(yr, nr) || !finite_nonneg(yc, nc))) return 0;
+    double zr = 0.0, zc = 0.0, yrm = 0.0, ycm = 0.0;
+    for (int64_t i = 0; i < nr; ++i) {
+        double z = yr ? xr[i] * yr[i] : xr[i];
+        if (!isfinite(z)) return 0;
+        if (z > zr) zr = z;
+        if (yr && yr[i] > yrm) yrm = yr[i];
+    }
+    for (int64_t j = 0; j < nc; ++j) {
+        double z = yr ? xc[j] * yc[j] : xc[j];
+        if (!isfinite(z)) return 0;
+        if (z > zc) zc = z;
+        if (yr && yc[j] > ycm) ycm = yc[j];
+    }
+    if (!isfinite(zr * zc)) return 0;
+    if (yr && nr > 0 && nc > 0 && !(yrm * ycm < 1.0)) return 0;
+    return 1;
+}
+
+int64_t mho_sample_bipartite(const double* xr, const double* yr, int64_t nr, const double* xc, const double* yc,
+                             int64_t nc, int exclude_self, uint64_t seed, uint32_t replica, int32_t seg_work,
+                             int32_t* src, int32_t* dst, int32_t* w, int64_t capacity, mho_stats* stats,
+                             int32_t* tie_rows, int64_t tie_cap, int64_t* n_tie_rows) {
+    mho_stats st;
+    memset(&st, 0, sizeof(st));
+    int64_t ntr = 0;
+    if (!xr || !xc || seg_work < 0 || (yr && !yc)) return MHO_EINVAL;
+    if (!valid_bip(xr, yr, nr, xc, yc, nc)) return MHO_EINVAL;
+    edge_sink es = {src, dst, w, capacity, 0};
+    if (nr > 0 && nc > 0) {
+        double* zr = (double*)malloc(sizeof(double) * (size_t)nr);
+        double* zc = (double*)malloc(sizeof(double) * (size_t)nc);
+        int32_t* pr = (int32_t*)malloc(sizeof(int32_t) * (size_t)nr);
+        int32_t* pcn = (int32_t*)malloc(sizeof(int32_t) * (size_t)nc);
+        double* zrs = (double*)malloc(sizeof(double) * (size_t)nr);
+        double* zcs = (double*)malloc(sizeof(double) * (size_t)nc);
+        for (int64_t i = 0; i < nr; ++i) zr[i] = yr ? xr[i] * yr[i] : xr[i];
+        for (int64_t j = 0; j < nc; ++j) zc[j] = yr ? xc[j] * yc[j] : xc[j];
+        mho_order(zr, nr, pr);
+        mho_order(zc, nc, pcn);
+        double ymax_c = 0.0;
+        for (int64_t i = 0; i < nr; ++i) zrs[i] = zr[pr[i]];
+        for (int64_t j = 0; j < nc; ++j) {
+            zcs[j] = zc[pcn[j]];
+            if (yr && yc[j] > ymax_c) ymax_c = yc[j];
+        }
+        plan_ctx cols;
+        plan_init(&cols, zcs, NULL, nc, seg_work);
+        uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+        for (int64_t r = 0; r < nr; ++r) {
+            double s = zrs[r];
+            int32_t id_r = pr[r];
+            double yrr = yr ? yr[id_r] : 0.0;
+            double cr = yr ? 1.0 - yrr * ymax_c : 1.0;
+            row_plan rp = bip_row_info(&cols, s, cr);
+            int64_t nseg = rp.nd + rp.ns;
+            int row_tie = 0;
+            for (int64_t g = 0; g < nseg; ++g) {
+                int64_t a, b;
+                bip_segment(&cols, &rp, g, &a, &b);
+                if (a >= b) continue;
+                ++st.segments;
+                int64_t pos = a - 1;
+                double tq = s * zcs[a];
+                uint32_t step = 0;
+                for (;;) {
+                    if (tq == 0.0) break;
+                    uint32_t ctr[4] = {step, (uint32_t)r, replica, (uint32_t)(g << 1)};
+                    uint32_t u[4];
+                    mho_philox4x32_10(ctr, key, u);
+                    ++st.steps;
+                    double U1 = mho_u53(u[0], u[1]);
+                    double U2 = mho_u53(u[2], u[3]);
+                    double lq = yr ? log1p(tq / cr) : log1p(tq);
+                    double d = -log(U1) / lq;
+                    double room = (double)(b - 1 - pos);
+                    if (near_int(d) || fabs(d - room) <= 1e-12 * (room > 1.0 ? room : 1.0)) row_tie = 1;
+                    if (d >= room) break;
+                    int64_t j = pos + 1 + (int64_t)d;
+                    double t = s * zcs[j];
+                    int32_t id_j = pcn[j];
+                    double lhs, rhs, bb = 0.0;
+                    if (yr) {
+                        bb = yrr * yc[id_j];
+                        double e = 1.0 - bb;
+                        lhs = (U2 * tq) * (e + t);
+                        rhs = t * (cr + tq);
+                    } else {
+                        lhs = (U2 * tq) * (1.0 + t);
+                        rhs = t * (1.0 + tq);
+                    }
+                    ++st.proposals;
+                    if (fabs(lhs - rhs) <= 1e-12 * rhs) row_tie = 1;
+                    if (lhs < rhs && !(exclude_self && id_j == id_r)) {
+                        int32_t wt = 0;
+                        if (yr) {
+                            uint32_t ctr2[4] = {step, (uint32_t)r, replica, (uint32_t)((g << 1) | 1)};
+                            uint32_t v[4];
+                            mho_philox4x32_10(ctr2, key, v);
+                            wt = draw_weight(mho_u53(v[0], v[1]), bb, &st.saturated_w, &row_tie);
+                        }
+                        ++st.accepts;
+                        emit(&es, id_r, id_j, wt);
+                    }
+                    tq = t;
+                    pos = j;
+                    ++step;
+                }
+            }
+            if (row_tie) {
+                ++st.near_ties;
+                if (tie_rows && ntr < tie_cap) tie_rows[ntr] = id_r;
+                ++ntr;
+            }
+        }
+        plan_free(&cols);
+        free(zr); free(zc); free(pr); free(pcn); free(zrs); free(zcs);
+    }
+    if (stats) *stats = st;
+    if (n_tie_rows) *n_tie_rows = ntr;
+    return es.count;
+}
+
+int64_t mho_sample_bipartite_bf(const double* xr, const double* yr, int64_t nr, const double* xc,
+                                const double* yc, int64_t nc, int exclude_self, uint64_t seed, uint32_t replica,
+                                int32_t* src, int32_t* dst, int32_t* w, int64_t capacity) {
+    if (!xr || !xc || (yr && !yc) || !valid_bip(xr, yr, nr, xc, yc, nc)) return MHO_EINVAL;
+    edge_sink es = {src, dst, w, capacity, 0};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    int64_t sat = 0;
+    for (int64_t i = 0; i < nr; ++i) {
+        double zi = yr ? xr[i] * yr[i] : xr[i];
+        for (int64_t j = 0; j < nc; ++j) {
+            if (exclude_self && i == j) continue;
+            double zj = yr ? xc[j] * yc[j] : xc[j];
+            double t = zi * zj;
+            uint32_t ctr[4] = {(uint32_t)j, (uint32_t)i, replica, 0xFFFFFFFEu};
+            uint32_t u[4];
+            mho_philox4x32_10(ctr, key, u);
+            double e = yr ? 1.0 - yr[i] * yc[j] : 1.0;
+            if (mho_u53(u[0], u[1]) * (e + t) < t) {
+                int32_t wt = 0;
+                if (yr) {
+                    int tie = 0;
+                    wt = draw_weight(mho_u53(u[2], u[3]), yr[i] * yc[j], &sat, &tie);
+                }
+                emit(&es, (int32_t)i, (int32_t)j, wt);
+            }
+        }
+    }
+    return es.count;
+}
+
 /* ------------------------------------------------------------------ brute force */
 /* The brute-force sampler (Sec. 2.2): every pair i < j is an edge with
    probability p_ij, independently.  One Philox block per pair, counter

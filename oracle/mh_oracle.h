@@ -65,6 +65,26 @@ int64_t mho_sample_mh(const double* x, const double* y, int64_t n, uint64_t seed
                       int32_t seg_work, int32_t* src, int32_t* dst, int32_t* w, int64_t capacity,
                       mho_stats* stats, int32_t* tie_rows, int64_t tie_cap, int64_t* n_tie_rows);
 
+/* Bipartite / directed sampler (Sec. 2.6).  Rows are the "+" set (xr, yr, nr),
+   columns the "-" set (xc, yc, nc), each sorted by its own z descending (ties
+   by id); every row sweeps all columns; yr == NULL selects the unweighted
+   model (then yc is ignored).  exclude_self: a candidate whose column id equals
+   the row id is never accepted (directed networks without self-loops, both
+   sets indexing the same nodes).  Edges are (row id, column id[, w]). */
+int64_t mho_sample_bipartite(const double* xr, const double* yr, int64_t nr, const double* xc, const double* yc,
+                             int64_t nc, int exclude_self, uint64_t seed, uint32_t replica, int32_t seg_work,
+                             int32_t* src, int32_t* dst, int32_t* w, int64_t capacity, mho_stats* stats,
+                             int32_t* tie_rows, int64_t tie_cap, int64_t* n_tie_rows);
+/* Column ranges of one bipartite row with value s = z_r and bound c (1 for the
+   unweighted model) over the sorted column values zcs.  Returns the count. */
+int64_t mho_plan_row_bipartite(const double* zcs, int64_t nc, double s, double c, int32_t seg_work,
+                               int64_t* a, int64_t* b, int64_t cap);
+/* Brute force for the bipartite / directed model: every (row i, column j) pair,
+   counter (j, i, replica, 0xFFFFFFFE). */
+int64_t mho_sample_bipartite_bf(const double* xr, const double* yr, int64_t nr, const double* xc,
+                                const double* yc, int64_t nc, int exclude_self, uint64_t seed, uint32_t replica,
+                                int32_t* src, int32_t* dst, int32_t* w, int64_t capacity);
+
 /* Brute-force Bernoulli sampler over pairs i<j with i in [row_begin, row_end),
    j in (i, n).  Edges in (i, j) lexicographic order, src = i, dst = j. */
 int64_t mho_sample_bf(const double* x, const double* y, int64_t n, uint64_t seed, uint32_t replica,
