@@ -109,6 +109,33 @@ mh_status mh_sample_weighted(const double* x, const double* y, int64_t n, uint64
                              void* workspace, size_t ws_bytes, mh_stats* stats_host,
                              hipStream_t stream);
 
+/* Two node sets: bipartite and directed networks (Sec. 2.6).  Rows are the
+ * "+" set (x_rows, y_rows, n_rows), columns the "-" set (x_cols, y_cols,
+ * n_cols); p_ij is the model's formula with z_i from the row set and z_j from
+ * the column set.  Each set is sorted by its own z (descending, ties by id)
+ * and every row sweeps all columns with the same skip / accept / update rule;
+ * a chain over the column range [a, b) starts with the proposal probability of
+ * column a itself, and the weighted bound of row r is
+ * Y_r = y_r * max_j y_cols[j] (the smallest beta+_r + beta-_j row r can meet).
+ * The plan rule above applies with first column 0 and n = n_cols.
+ *   y_rows, y_cols  both NULL (unweighted) or both device float64 (weighted;
+ *                   w receives the weights, and every y_i y_j must be < 1).
+ *   flags           0, or MH_BIP_NO_SELF: the two sets index the same nodes
+ *                   (rows = out-parameters, columns = in-parameters of a
+ *                   directed network) and the pair (i, i) is never an edge.
+ *   src, dst        edge = (row id, column id); order unspecified.
+ *   workspace       >= mh_bipartite_workspace_bytes(n_rows, n_cols, weighted, plan).
+ * The other arguments, the outputs and the errors are those of the one-set
+ * samplers; (max row z)(max column z) must be finite.  An empty set gives an
+ * empty sample without reading the other set. */
+#define MH_BIP_NO_SELF 1u
+size_t mh_bipartite_workspace_bytes(int64_t n_rows, int64_t n_cols, int weighted, const mh_plan_params* plan);
+mh_status mh_sample_bipartite(const double* x_rows, const double* y_rows, int64_t n_rows,
+                              const double* x_cols, const double* y_cols, int64_t n_cols, uint32_t flags,
+                              uint64_t seed, uint32_t replica, const mh_plan_params* plan, int32_t* src,
+                              int32_t* dst, int32_t* w, int64_t capacity, int64_t* n_edges_host,
+                              void* workspace, size_t ws_bytes, mh_stats* stats_host, hipStream_t stream);
+
 /* Brute-force sampler (Sec. 2.2): every pair i < j with i in [row_begin,
  * row_end) is an edge with probability p_ij, one Philox block per pair.
  * y == NULL selects the unweighted model (w may be NULL then).  Edges are

@@ -75,6 +75,9 @@ def lib() -> ctypes.CDLL:
         "mh_sample_unweighted": ([vp, i64, u64, u32, P(PlanParams), vp, vp, i64, P(i64), vp, sz, P(Stats), vp], ctypes.c_int),
         "mh_sample_weighted": ([vp, vp, i64, u64, u32, P(PlanParams), vp, vp, vp, i64, P(i64), vp, sz, P(Stats), vp],
                                ctypes.c_int),
+        "mh_bipartite_workspace_bytes": ([i64, i64, ctypes.c_int, P(PlanParams)], sz),
+        "mh_sample_bipartite": ([vp, vp, i64, vp, vp, i64, u32, u64, u32, P(PlanParams), vp, vp, vp, i64, P(i64), vp,
+                                 sz, P(Stats), vp], ctypes.c_int),
         "mh_bruteforce_workspace_bytes": ([i64], sz),
         "mh_sample_bruteforce": ([vp, vp, i64, u64, u32, i64, i64, vp, vp, vp, i64, P(i64), vp, sz, vp], ctypes.c_int),
         "mh_order": ([vp, vp, i64, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
@@ -194,6 +197,60 @@ def sample_weighted(x: torch.Tensor, y: torch.Tensor, seed: int = 1, replica: in
     """One sample of the weighted model (Sec. 2.5, Alg. 1): (src, dst, w)."""
     r = _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stage_events, grid_blocks)
     return (r.src, r.dst, r.w, r.stats) if stats else (r.src, r.dst, r.w)
+
+
+MH_BIP_NO_SELF = 1
+
+
+def sample_bipartite(x_rows: torch.Tensor, x_cols: torch.Tensor, y_rows: torch.Tensor | None = None,
+                     y_cols: torch.Tensor | None = None, exclude_self: bool = False, seed: int = 1, replica: int = 0,
+                     seg_work: int = DEFAULT_SEG_WORK, capacity: int | None = None, stats: bool = False, out=None,
+                     workspace=None, stage_events=None, grid_blocks: int = 0) -> SampleResult:
+    """One sample of a bipartite network (Sec. 2.6): rows = "+" set, columns =
+    "-" set; weighted when y_rows and y_cols are given.  exclude_self: directed
+    network without self-loops (rows = out-, columns = in-parameters of the
+    same nodes).  Returns a SampleResult of (row id, column id[, w])."""
+    xr = _dev_f64(x_rows, "x_rows")
+    xc = _dev_f64(x_cols, "x_cols")
+    if (y_rows is None) != (y_cols is None):
+        raise ValueError("give both y_rows and y_cols, or neither")
+    weighted = y_rows is not None
+    yr = _dev_f64(y_rows, "y_rows") if weighted else None
+    yc = _dev_f64(y_cols, "y_cols") if weighted else None
+    if weighted and (yr.shape != xr.shape or yc.shape != xc.shape):
+        raise ValueError("x and y of a node set must have the same shape")
+    nr, nc = xr.numel(), xc.numel()
+    dev = xr.device
+    L = lib()
+    plan = PlanParams(int(seg_work), 0, int(grid_blocks), 0, stage_events)
+    wsb = L.mh_bipartite_workspace_bytes(nr, nc, 1 if weighted else 0, ctypes.byref(plan))
+    ws = workspace if workspace is not None and workspace.numel() >= wsb else _workspace(wsb, dev)
+    cap = int(capacity) if capacity is not None else max(4096, 4 * (nr + nc))
+    if out is not None:
+        src, dst = out[0], out[1]
+        w = out[2] if weighted else None
+        cap = min(src.numel(), dst.numel(), w.numel() if w is not None else src.numel())
+    else:
+        src = dst = w = None
+    flags = MH_BIP_NO_SELF if exclude_self else 0
+    nedge = ctypes.c_int64(0)
+    st = Stats()
+    for _attempt in range(2):
+        if src is None or src.numel() < cap:
+            src = torch.empty(cap, dtype=torch.int32, device=dev)
+            dst = torch.empty(cap, dtype=torch.int32, device=dev)
+            w = torch.empty(cap, dtype=torch.int32, device=dev) if weighted else None
+        status = L.mh_sample_bipartite(_ptr(xr), _ptr(yr), nr, _ptr(xc), _ptr(yc), nc, flags, seed, replica,
+                                       ctypes.byref(plan), _ptr(src), _ptr(dst), _ptr(w), cap, ctypes.byref(nedge),
+                                       _ptr(ws), ws.numel(), ctypes.byref(st) if stats else None, _stream(dev))
+        if status == MH_ECAPACITY and out is None:
+            cap = int(nedge.value)
+            src = None
+            continue
+        _check(status, "mh_sample_bipartite")
+        break
+    m = int(nedge.value)
+    return SampleResult(src[:m], dst[:m], None if w is None else w[:m], st.as_dict() if stats else None)
 
 
 def sample_bruteforce(x: torch.Tensor, y: torch.Tensor | None = None, seed: int = 1, replica: int = 0,

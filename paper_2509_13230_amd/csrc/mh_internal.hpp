@@ -78,10 +78,11 @@ struct SortedView {
 
 size_t order_workspace_bytes(int64_t n);
 // Writes the order either as packed records (node != null: z and id; nseg is
-// left for the plan) or as separate perm / zs arrays.
+// left for the plan) or as separate perm / zs arrays.  check_square: the
+// largest z squared must be finite (one node set, where it is the largest t).
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
                       NodeRec* node, int32_t* status, uint64_t* mass_out, void* ws, size_t ws_bytes,
-                      hipStream_t stream);
+                      hipStream_t stream, bool check_square = true);
 
 size_t bound_workspace_bytes(int64_t n);
 mh_status bound_suffix_top2(const double* ys, int64_t n, double* c, int32_t* status, void* ws, size_t ws_bytes,

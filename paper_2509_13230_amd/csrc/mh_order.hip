@@ -96,7 +96,8 @@ __global__ __launch_bounds__(kThreads) void k_finish_order(const uint64_t* __res
                                                            int32_t* __restrict__ perm, double* __restrict__ zs,
                                                            NodeRec* __restrict__ node,
                                                            const double* __restrict__ y, double* __restrict__ ys,
-                                                           uint64_t* __restrict__ mass, int32_t* status) {
+                                                           uint64_t* __restrict__ mass, int32_t check_square,
+                                                           int32_t* status) {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= n) return;
     const uint32_t id = vals[r];
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_finish_order(const uint64_t* __res
     }
     if (ys) ys[r] = y[id];
     if (mass) mass[r] = mass_q(z);
-    if (r == 0 && !isfinite(z * z)) raise_status(status, MH_EINVAL);
+    if (check_square && r == 0 && !isfinite(z * z)) raise_status(status, MH_EINVAL);
 }
 
 // ---- suffix top-2 of ys: the monoid keeps the two largest values (multiset) ----
@@ -248,7 +249,7 @@ size_t order_workspace_bytes(int64_t n) {
 
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
                       NodeRec* node, int32_t* status, uint64_t* mass_out, void* ws, size_t ws_bytes,
-                      hipStream_t stream) {
+                      hipStream_t stream, bool check_square) {
     if (n <= 0) return MH_OK;
     Arena ar(ws, ws_bytes);
     uint64_t* keys = ar.take<uint64_t>(n);
@@ -269,7 +270,7 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
     if (st != MH_OK) return st;
     const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_finish_order, dim3(grid), dim3(kThreads), 0, stream, keys, vals, n, perm, zs, node, y,
-                       y ? ys : nullptr, mass_out, status);
+                       y ? ys : nullptr, mass_out, (int32_t)check_square, status);
     MH_HIP_TRY(hipGetLastError());
     return MH_OK;
 }

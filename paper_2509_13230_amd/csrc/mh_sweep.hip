@@ -40,37 +40,44 @@ __global__ void k_init_counters(Counters* c) {
 }
 
 // ---- plan: per row, the number of segments and the data to locate them ----
+// Row r's columns are [first, nc) with first = r + 1 (one node set, col ==
+// node) or 0 (two node sets).  Dense part: the columns j < J with
+// s z_j >= c_r, cut every T columns; sparse part: [J, nc) cut where the column
+// mass (prefix sums P of floor(z 2^32)) reaches multiples of
+// m = floor(T c_r / s 2^32), the mass whose expected candidate count is ~T.
 __global__ __launch_bounds__(kThreads) void k_row_plan(NodeRec* __restrict__ node, const double* __restrict__ c,
-                                                       int64_t n, int32_t T, const uint64_t* __restrict__ P,
+                                                       int64_t n, const NodeRec* __restrict__ col, int64_t nc,
+                                                       int32_t bip, int32_t T, const uint64_t* __restrict__ P,
                                                        int32_t* __restrict__ jend,
                                                        uint64_t* __restrict__ mq, uint64_t* __restrict__ hn) {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= n) return;
     int64_t total = 0;
     const double s = node[r].z;
-    if (r < n - 1 && s != 0.0) {
+    const int64_t first = bip ? 0 : r + 1;
+    if (first < nc && s != 0.0) {
         if (T <= 0) {
             total = 1;
         } else {
             const double cr = c ? c[r] : 1.0;
-            int64_t J = r + 1;
-            if (s * node[r + 1].z >= cr) {
-                int64_t lo = r + 2, hi = n;  // first j in [lo, n] with s*zs[j] < cr (n if none)
+            int64_t J = first;
+            if (s * col[first].z >= cr) {
+                int64_t lo = first + 1, hi = nc;  // first j in [lo, nc] with s*z_j < cr (nc if none)
                 while (lo < hi) {
                     const int64_t mid = lo + (hi - lo) / 2;
-                    if (s * node[mid].z < cr) hi = mid; else lo = mid + 1;
+                    if (s * col[mid].z < cr) hi = mid; else lo = mid + 1;
                 }
                 J = lo;
             }
-            const int64_t nd = (J - r - 1 + T - 1) / T;
+            const int64_t nd = (J - first + T - 1) / T;
             int64_t ns = 0;
             uint64_t m = 0;
-            if (J < n) {
+            if (J < nc) {
                 const double md = ((double)T * cr / s) * 4294967296.0;
                 if (!(md < 4611686018427387904.0)) m = (uint64_t)1 << 62;
                 else if (md < 1.0) m = 1;
                 else m = (uint64_t)md;
-                const uint64_t mass = P[n] - P[J];
+                const uint64_t mass = P[nc] - P[J];
                 ns = (mass == 0) ? 1 : (int64_t)((mass + m - 1) / m);
             }
             total = nd + ns;
@@ -156,9 +163,12 @@ NetDesc net_desc(const NetBuffers& B) {
     D.hoff = B.hoff;
     D.rec = B.rec;
     D.rec_cap = B.rec_cap;
+    D.col = B.node;
+    D.ysc = B.ys;
     D.n = B.n;
+    D.ncol = B.n;
     D.T = B.T;
-    D.pad = 0;
+    D.flags = 0;
     return D;
 }
 
@@ -187,8 +197,8 @@ mh_status prepare_network(const double* x, const double* y, const NetBuffers& B,
         if (st != MH_OK) return st;
     }
     const unsigned rows_grid = (unsigned)((n + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_row_plan, dim3(rows_grid), dim3(kThreads), 0, stream, B.node, B.c, n, B.T, B.P, B.jend,
-                       B.mq, B.hoff);
+    hipLaunchKernelGGL(k_row_plan, dim3(rows_grid), dim3(kThreads), 0, stream, B.node, (const double*)B.c, n,
+                       (const NodeRec*)B.node, n, 0, B.T, (const uint64_t*)B.P, B.jend, B.mq, B.hoff);
     MH_HIP_TRY(hipGetLastError());
     if (seg) {
         st = scan_exclusive_u64(B.hoff, B.hoff, n, scratch, scratch_bytes, stream);
@@ -209,9 +219,9 @@ size_t sample_workspace_bytes(int64_t n, bool weighted, int32_t T) {
     return s.used + network_bytes(n, weighted, T) + prepare_scratch_bytes(n) + 512;
 }
 
-template <bool W, bool S>
+template <bool W, bool S, bool BIP = false>
 void launch_sweep(const SweepLaunch& A, int64_t n, int32_t grid_blocks, hipStream_t stream) {
-    auto kern = k_sweep<W, S, false, OUT_EDGES>;
+    auto kern = k_sweep<W, S, false, OUT_EDGES, BIP>;
     int64_t want = (n + kWave - 1) / kWave;
     if (want < 16) want = 16;
     // Default: 3 blocks (12 waves) per CU.  With fewer, larger per-wave item
@@ -325,13 +335,233 @@ mh_status plan_counts_impl(const double* zs, const double* c, int64_t n, int32_t
         mh_status st = scan_exclusive_u64(P, P, n, ar.base + off, ws_bytes - off, stream);
         if (st != MH_OK) return st;
     }
-    hipLaunchKernelGGL(k_row_plan, dim3(grid), dim3(kThreads), 0, stream, node, c, n, T, P, jend, mq,
-                       (uint64_t*)nullptr);
+    hipLaunchKernelGGL(k_row_plan, dim3(grid), dim3(kThreads), 0, stream, node, c, n, (const NodeRec*)node, n, 0,
+                       T, (const uint64_t*)P, jend, mq, (uint64_t*)nullptr);
     MH_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_unpack_nseg, dim3(grid), dim3(kThreads), 0, stream, node, n, nseg);
     MH_HIP_TRY(hipGetLastError());
     return MH_OK;
 }
+
+// ---- two node sets: bipartite and directed networks (Sec. 2.6) ----
+namespace {
+
+// Largest column y, as the bit pattern of a non-negative double (which orders
+// like the value), reduced with one atomic max per wave into *bits.
+__global__ __launch_bounds__(kThreads) void k_max_bits(const double* __restrict__ v, int64_t n,
+                                                       unsigned long long* __restrict__ bits) {
+    unsigned long long m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const double x = v[i];
+        const unsigned long long b = (x > 0.0) ? (unsigned long long)__double_as_longlong(x) : 0ull;
+        m = b > m ? b : m;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off, kWave);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(bits, m);
+}
+
+__global__ void k_zero_bits(unsigned long long* bits) {
+    if (threadIdx.x == 0) *bits = 0;
+}
+
+// Row bound c_r = 1 - y_r * max_j y_j (the smallest beta+_r + beta-_j row r can
+// meet), and the checks of the two sets together: the largest t (product of
+// the two largest z) is finite and every y_r y_j < 1.
+__global__ __launch_bounds__(kThreads) void k_bip_bound(const NodeRec* __restrict__ rows,
+                                                        const NodeRec* __restrict__ cols,
+                                                        const double* __restrict__ ys, int64_t nr,
+                                                        const unsigned long long* __restrict__ ymax_bits,
+                                                        double* __restrict__ c, int32_t* status) {
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r == 0 && !isfinite(rows[0].z * cols[0].z)) raise_status(status, MH_EINVAL);
+    if (!c || r >= nr) return;
+    const double ym = __longlong_as_double((long long)*ymax_bits);
+    const double Y = ys[r] * ym;
+    c[r] = 1.0 - Y;
+    if (!(Y < 1.0)) raise_status(status, MH_EINVAL);
+}
+
+// Device buffers of a prepared bipartite network.
+struct BipBuffers {
+    NodeRec* rows;
+    double* ysr;
+    double* c;
+    int32_t* jend;
+    uint64_t* mq;
+    uint64_t* hoff;
+    HeavyRec* rec;
+    int64_t rec_cap;
+    NodeRec* cols;
+    double* ysc;
+    uint64_t* P;
+    unsigned long long* ymax;
+};
+
+template <typename A>
+BipBuffers carve_bipartite(A& ar, int64_t nr, int64_t nc, bool weighted, int32_t T) {
+    const bool seg = T > 0;
+    BipBuffers B{};
+    B.rows = ar.template take<NodeRec>(nr);
+    B.ysr = ar.template take<double>(weighted ? nr : 0);
+    B.c = ar.template take<double>(weighted ? nr : 0);
+    B.jend = ar.template take<int32_t>(seg ? nr : 0);
+    B.mq = ar.template take<uint64_t>(seg ? nr : 0);
+    B.hoff = ar.template take<uint64_t>(seg ? nr + 1 : 0);
+    B.rec_cap = seg ? nr + 4096 : 0;
+    B.rec = ar.template take<HeavyRec>(B.rec_cap);
+    B.cols = ar.template take<NodeRec>(nc);
+    B.ysc = ar.template take<double>(weighted ? nc : 0);
+    B.P = ar.template take<uint64_t>(seg ? nc + 1 : 0);
+    B.ymax = ar.template take<unsigned long long>(1);
+    if (!weighted) B.ysr = B.c = B.ysc = nullptr;
+    if (!seg) B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.P = nullptr;
+    return B;
+}
+
+size_t bipartite_workspace_bytes(int64_t nr, int64_t nc, bool weighted, int32_t T) {
+    if (nr < 0 || nc < 0) return 0;
+    SizerAdapter sz;
+    sz.s.take<Counters>(1);
+    carve_bipartite(sz, nr, nc, weighted, T);
+    size_t scratch = prepare_scratch_bytes(nr);
+    const size_t s2 = prepare_scratch_bytes(nc);
+    if (s2 > scratch) scratch = s2;
+    return sz.s.used + scratch + 768;
+}
+
+NetDesc bip_desc(const BipBuffers& B, int64_t nr, int64_t nc, int32_t T, uint32_t flags) {
+    NetDesc D;
+    D.node = B.rows;
+    D.ys = B.ysr;
+    D.c = B.c;
+    D.col = B.cols;
+    D.ysc = B.ysc;
+    D.jend = B.jend;
+    D.mq = B.mq;
+    D.P = B.P;
+    D.hoff = B.hoff;
+    D.rec = B.rec;
+    D.rec_cap = B.rec_cap;
+    D.n = nr;
+    D.ncol = nc;
+    D.T = T;
+    D.flags = NET_BIPARTITE | ((flags & MH_BIP_NO_SELF) ? NET_NO_SELF : 0);
+    return D;
+}
+
+mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, const double* xc, const double* yc,
+                                int64_t nc, uint32_t flags, uint64_t seed, uint32_t replica,
+                                const mh_plan_params* plan, int32_t* src, int32_t* dst, int32_t* w,
+                                int64_t capacity, int64_t* n_edges_host, void* workspace, size_t ws_bytes,
+                                mh_stats* stats_host, hipStream_t stream) {
+    const bool weighted = (yr != nullptr);
+    if (!n_edges_host || nr < 0 || nc < 0 || nr > 0x7FFFFFFFll || nc > 0x7FFFFFFFll || capacity < 0)
+        return MH_EINVAL;
+    if ((yr == nullptr) != (yc == nullptr) || (flags & ~MH_BIP_NO_SELF) != 0) return MH_EINVAL;
+    if ((!xr && nr > 0) || (!xc && nc > 0)) return MH_EINVAL;
+    if (capacity > 0 && (!src || !dst || (weighted && !w))) return MH_EINVAL;
+    const int32_t T = plan ? plan->seg_work : 16;
+    if (T < 0 || (plan && (plan->flags != 0 || plan->grid_blocks < 0))) return MH_EINVAL;
+    *n_edges_host = 0;
+    if (stats_host) *stats_host = mh_stats{0, 0, 0, 0, 0, 0};
+    if (nr == 0 || nc == 0) return MH_OK;
+    if (!workspace || ws_bytes < bipartite_workspace_bytes(nr, nc, weighted, T)) return MH_EWORKSPACE;
+
+    Arena ar(workspace, ws_bytes);
+    Counters* ctr = ar.take<Counters>(1);
+    BipBuffers B = carve_bipartite(ar, nr, nc, weighted, T);
+    if (ar.overflow) return MH_EWORKSPACE;
+    const size_t off = (ar.used + 255) & ~size_t(255);
+    void* scratch = ar.base + off;
+    const size_t scratch_bytes = ws_bytes - off;
+    int32_t* status = &ctr->status;
+    const bool seg = T > 0;
+
+    hipEvent_t* ev = plan ? plan->stage_events : nullptr;
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[0], stream));
+    mh_status st = init_counters(ctr, stream);
+    if (st != MH_OK) return st;
+    // A1: each set sorted by its own z; the column masses for the plan
+    st = order_nodes(xr, yr, nr, nullptr, nullptr, B.ysr, B.rows, status, nullptr, scratch, scratch_bytes, stream,
+                     false);
+    if (st != MH_OK) return st;
+    st = order_nodes(xc, yc, nc, nullptr, nullptr, B.ysc, B.cols, status, B.P, scratch, scratch_bytes, stream,
+                     false);
+    if (st != MH_OK) return st;
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[1], stream));
+    // A2: row bounds and the joint checks
+    if (weighted) {
+        hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, stream, B.ymax);
+        MH_HIP_TRY(hipGetLastError());
+        int64_t g = (nc + kThreads - 1) / kThreads;
+        if (g > 1024) g = 1024;
+        hipLaunchKernelGGL(k_max_bits, dim3((unsigned)g), dim3(kThreads), 0, stream, (const double*)B.ysc, nc,
+                           B.ymax);
+        MH_HIP_TRY(hipGetLastError());
+    }
+    const unsigned rows_grid = (unsigned)((nr + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_bip_bound, dim3(weighted ? rows_grid : 1u), dim3(kThreads), 0, stream,
+                       (const NodeRec*)B.rows, (const NodeRec*)B.cols, (const double*)B.ysr, nr,
+                       (const unsigned long long*)B.ymax, B.c, status);
+    MH_HIP_TRY(hipGetLastError());
+    // A3: plan over the columns
+    if (seg) {
+        st = scan_exclusive_u64(B.P, B.P, nc, scratch, scratch_bytes, stream);
+        if (st != MH_OK) return st;
+    }
+    hipLaunchKernelGGL(k_row_plan, dim3(rows_grid), dim3(kThreads), 0, stream, B.rows, (const double*)B.c, nr,
+                       (const NodeRec*)B.cols, nc, 1, T, (const uint64_t*)B.P, B.jend, B.mq, B.hoff);
+    MH_HIP_TRY(hipGetLastError());
+    const NetDesc D = bip_desc(B, nr, nc, T, flags);
+    if (seg) {
+        st = scan_exclusive_u64(B.hoff, B.hoff, nr, scratch, scratch_bytes, stream);
+        if (st != MH_OK) return st;
+        hipLaunchKernelGGL(k_heavy_records, dim3(512), dim3(kThreads), 0, stream, D, B.rec, (const int32_t*)status);
+        MH_HIP_TRY(hipGetLastError());
+    }
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[2], stream));
+
+    SweepLaunch A{};
+    A.net = D;
+    A.replica = replica;
+    A.key0 = (uint32_t)seed;
+    A.key1 = (uint32_t)(seed >> 32);
+    A.out = EdgeOut{src, dst, w, capacity, &ctr->n_edges};
+    A.sid = nullptr;
+    A.ctr = ctr;
+    const int32_t gb = plan ? plan->grid_blocks : 0;
+    if (weighted) {
+        if (stats_host) launch_sweep<true, true, true>(A, nr, gb, stream);
+        else launch_sweep<true, false, true>(A, nr, gb, stream);
+    } else {
+        if (stats_host) launch_sweep<false, true, true>(A, nr, gb, stream);
+        else launch_sweep<false, false, true>(A, nr, gb, stream);
+    }
+    MH_HIP_TRY(hipGetLastError());
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[3], stream));
+
+    Counters hc;
+    MH_HIP_TRY(hipMemcpyAsync(&hc, ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
+    MH_HIP_TRY(hipStreamSynchronize(stream));
+    if (hc.status != 0) return (mh_status)hc.status;
+    *n_edges_host = (int64_t)hc.n_edges;
+    if (stats_host) {
+        stats_host->steps = (int64_t)hc.stats[ST_STEPS];
+        stats_host->proposals = (int64_t)hc.stats[ST_PROPOSALS];
+        stats_host->accepts = (int64_t)hc.stats[ST_ACCEPTS];
+        stats_host->segments = (int64_t)hc.stats[ST_SEGMENTS];
+        stats_host->saturated_w = (int64_t)hc.stats[ST_SATURATED];
+        stats_host->n_edges = (int64_t)hc.n_edges;
+    }
+    if ((int64_t)hc.n_edges > capacity) return MH_ECAPACITY;
+    return MH_OK;
+}
+
+}  // namespace
 
 }  // namespace mh
 
@@ -369,6 +599,23 @@ size_t mh_plan_workspace_bytes(int64_t n) { return mh::plan_workspace_bytes_impl
 mh_status mh_plan_counts(const double* zs, const double* c, int64_t n, int32_t seg_work, int32_t* nseg,
                          void* workspace, size_t ws_bytes, hipStream_t stream) {
     return mh::plan_counts_impl(zs, c, n, seg_work, nseg, workspace, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+size_t mh_bipartite_workspace_bytes(int64_t n_rows, int64_t n_cols, int weighted, const mh_plan_params* plan) {
+    return mh::bipartite_workspace_bytes(n_rows, n_cols, weighted != 0, plan ? plan->seg_work : 16);
+}
+
+mh_status mh_sample_bipartite(const double* x_rows, const double* y_rows, int64_t n_rows, const double* x_cols,
+                              const double* y_cols, int64_t n_cols, uint32_t flags, uint64_t seed, uint32_t replica,
+                              const mh_plan_params* plan, int32_t* src, int32_t* dst, int32_t* w, int64_t capacity,
+                              int64_t* n_edges_host, void* workspace, size_t ws_bytes, mh_stats* stats_host,
+                              hipStream_t stream) {
+    return mh::sample_bipartite_impl(x_rows, y_rows, n_rows, x_cols, y_cols, n_cols, flags, seed, replica, plan,
+                                     src, dst, w, capacity, n_edges_host, workspace, ws_bytes, stats_host, stream);
 }
 
 }  // extern "C"

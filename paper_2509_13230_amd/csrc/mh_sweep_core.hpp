@@ -3,12 +3,20 @@
 //
 // Work items are (row, segment) pairs of a prepared network.  Rows cut into
 // two or more segments ("heavy" rows, the large-z hubs) come first in a
-// network's item space, one item per segment in row order; then every row
-// r < n-1 in rank order, which is an item only if the row has exactly one
-// segment.  Each lane runs one item's chain; a lane whose chain ends takes its
-// wave's next item, so the 64 lanes stay busy whatever the spread of chain
-// lengths.  Every loop iteration a lane consumes the global loads it issued in
-// the previous iteration and issues the next ones: one memory round trip per
+// network's item space, one item per segment in row order; then every row in
+// rank order (r < n-1 for one node set, every row for two), which is an item
+// only if the row has exactly one segment.
+//
+// One node set (Secs. 2.3-2.5): row r sweeps columns r+1..n-1 of the same
+// sorted list, its chain starting at column r.  Two node sets (Sec. 2.6): the
+// rows are the "+" nodes, the columns the "-" nodes, each sorted by its own
+// parameters; every row sweeps columns 0..n_col-1 and a chain over the column
+// range [a, b) starts with the proposal probability of column a itself.
+//
+// Each lane runs one item's chain; a lane whose chain ends takes its wave's
+// next item, so the 64 lanes stay busy whatever the spread of chain lengths.
+// Every loop iteration a lane consumes the global loads it issued in the
+// previous iteration and issues the next ones: one memory round trip per
 // iteration, overlapped with the Philox block and the logarithm of the next
 // draw, which need no loaded data.
 #pragma once
@@ -42,20 +50,26 @@ struct __attribute__((aligned(16))) NodeRec {
     int32_t nseg;  // segments of this rank's row
 };
 
-// A prepared network: sorted parameters, bound and plan.
+enum : int32_t { NET_BIPARTITE = 1, NET_NO_SELF = 2 };
+
+// A prepared network: sorted parameters, bound and plan.  With one node set
+// the column arrays alias the row arrays.
 struct NetDesc {
-    const NodeRec* node;
-    const double* ys;  // weighted only
-    const double* c;   // weighted only
+    const NodeRec* node;   // rows by rank
+    const double* ys;      // row y by rank (weighted only)
+    const double* c;       // row bound 1 - Y_r (weighted only)
+    const NodeRec* col;    // columns by rank
+    const double* ysc;     // column y by rank (weighted only)
     const int32_t* jend;
     const uint64_t* mq;
-    const uint64_t* P;
+    const uint64_t* P;     // prefix masses of the columns
     const uint64_t* hoff;  // null when unsegmented
     const HeavyRec* rec;   // records of the first rec_cap heavy items
     int64_t rec_cap;
-    int64_t n;
+    int64_t n;             // rows
+    int64_t ncol;          // columns
     int32_t T;
-    int32_t pad;
+    int32_t flags;         // NET_BIPARTITE, NET_NO_SELF
 };
 
 __device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* __restrict__ a, int64_t lo, int64_t hi, uint64_t v) {
@@ -68,9 +82,11 @@ __device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* __restrict__ 
 
 __device__ __forceinline__ int64_t heavy_items(const NetDesc& D) { return D.hoff ? (int64_t)D.hoff[D.n] : 0; }
 
-__device__ __forceinline__ int64_t total_items(const NetDesc& D) {
-    return heavy_items(D) + (D.n > 1 ? D.n - 1 : 0);
+__device__ __forceinline__ int64_t light_rows(const NetDesc& D) {
+    return (D.flags & NET_BIPARTITE) ? D.n : (D.n > 1 ? D.n - 1 : 0);
 }
+
+__device__ __forceinline__ int64_t total_items(const NetDesc& D) { return heavy_items(D) + light_rows(D); }
 
 // Row, segment index and column range of heavy item `it` (it < H).
 __device__ inline HeavyRec heavy_record(const NetDesc& D, int64_t it) {
@@ -85,18 +101,20 @@ __device__ inline HeavyRec heavy_record(const NetDesc& D, int64_t it) {
     const int64_t nsg = (int64_t)(D.hoff[r + 1] - D.hoff[r]);
     const int64_t J = D.jend[r];
     const int64_t T = D.T;
-    const int64_t nd = (J - r - 1 + T - 1) / T;
+    const int64_t first = (D.flags & NET_BIPARTITE) ? 0 : r + 1;
+    const int64_t nc = D.ncol;
+    const int64_t nd = (J - first + T - 1) / T;
     int64_t a, b;
     if (g < nd) {
-        a = r + 1 + g * T;
+        a = first + g * T;
         b = a + T < J ? a + T : J;
     } else {
         const int64_t kk = g - nd;
         const int64_t ns = nsg - nd;
         const uint64_t base = D.P[J];
         const uint64_t m = D.mq[r];
-        a = (kk == 0) ? J : lower_bound_u64(D.P, J, n, base + (uint64_t)kk * m);
-        b = (kk == ns - 1) ? n : lower_bound_u64(D.P, J, n, base + (uint64_t)(kk + 1) * m);
+        a = (kk == 0) ? J : lower_bound_u64(D.P, J, nc, base + (uint64_t)kk * m);
+        b = (kk == ns - 1) ? nc : lower_bound_u64(D.P, J, nc, base + (uint64_t)(kk + 1) * m);
     }
     return HeavyRec{(int32_t)r, (int32_t)g, (int32_t)a, (int32_t)b};
 }
@@ -128,9 +146,12 @@ struct SweepLaunch {
 // Lane states
 enum : uint32_t { S_IDLE = 0, S_REC, S_LOAD, S_STEP, S_DONE };
 
-template <bool WEIGHTED, bool STATS, bool BATCH, int OUT>
+// BIP: two node sets (single-sample launches only); the column arrays and the
+// chain start differ, and NET_NO_SELF rejects the candidate with the row's id.
+template <bool WEIGHTED, bool STATS, bool BATCH, int OUT, bool BIP>
 __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src, int32_t* s_dst, int32_t* s_w,
                                            int32_t* s_sid) {
+    static_assert(!(BIP && BATCH), "two-set networks are sampled one at a time");
     const int wave = threadIdx.x >> 6;
     const int64_t gwave = (int64_t)blockIdx.x * kSweepWaves + wave;
     const int64_t nwaves = (int64_t)gridDim.x * kSweepWaves;
@@ -141,8 +162,9 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
         total = (int64_t)A.batch.item_off[A.batch.n_samples];
     } else {
         H_single = heavy_items(A.net);
-        total = H_single + (A.net.n > 1 ? A.net.n - 1 : 0);
+        total = H_single + light_rows(A.net);
     }
+    const bool no_self = BIP && (A.net.flags & NET_NO_SELF);
 
     WaveStage<WEIGHTED> stage{s_src, s_dst, WEIGHTED ? s_w : nullptr, 0u};
 
@@ -156,6 +178,11 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
     // the lane's network
     const NodeRec* node = A.net.node;
     const double* ys = A.net.ys;
+    // column arrays: their own only with two node sets (never batched); with
+    // one set the candidates are read through `node` / `ys`, which follow the
+    // lane's current network
+    const NodeRec* col = BIP ? A.net.col : nullptr;
+    const double* ysc = BIP ? A.net.ysc : nullptr;
     int32_t* deg = nullptr;
     // values in flight from the previous iteration's loads
     double ld_s = 0.0, ld_z = 0.0, ld_c = 1.0, ld_y = 0.0;
@@ -187,7 +214,7 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
                 rhs = t * (1.0 + tq);
             }
             ++st_props;
-            if (lhs < rhs) {
+            if (lhs < rhs && !(BIP && no_self && ld_id == id)) {
                 acc = true;
                 ++st_acc;
                 dst_id = ld_id;
@@ -236,7 +263,7 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
                 const NodeRec nr = node[r];
                 ld_s = nr.z;
                 ld_id = nr.id;
-                ld_z = node[pos].z;
+                ld_z = BIP ? col[ld_rec.a].z : node[pos].z;
                 if (WEIGHTED) {
                     ld_c = D.c[r];
                     ld_y = ys[r];
@@ -262,10 +289,10 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
                     U2 = U2n;
                     scand = step;
                     ++step;
-                    const NodeRec nj = node[jc];
+                    const NodeRec nj = (BIP ? col : node)[jc];
                     ld_z = nj.z;
                     ld_id = nj.id;
-                    if (WEIGHTED) ld_y = ys[jc];
+                    if (WEIGHTED) ld_y = (BIP ? ysc : ys)[jc];
                     state = S_STEP;
                 }
             }
@@ -305,15 +332,15 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
                         state = S_REC;
                     } else {
                         r = (int32_t)(it - H);
-                        pos = r;
-                        end = (int32_t)Dp->n;
+                        pos = BIP ? -1 : r;
+                        end = (int32_t)(BIP ? Dp->ncol : Dp->n);
                         tag = 0;
                         step = 0;
                         check_light = true;
                         const NodeRec nr = node[r];
                         ld_n = nr.nseg;
                         ld_s = nr.z;
-                        ld_z = nr.z;
+                        ld_z = BIP ? col[0].z : nr.z;
                         ld_id = nr.id;
                         if (WEIGHTED) {
                             ld_c = Dp->c[r];
@@ -346,7 +373,7 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
     }
 }
 
-template <bool WEIGHTED, bool STATS, bool BATCH, int OUT>
+template <bool WEIGHTED, bool STATS, bool BATCH, int OUT, bool BIP = false>
 __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepLaunch A) {
     __shared__ int32_t s_src[kSweepWaves][kStageEdges];
     __shared__ int32_t s_dst[kSweepWaves][kStageEdges];
@@ -354,8 +381,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepLaunch A) {
     __shared__ int32_t s_sid[BATCH ? kSweepWaves : 1][BATCH ? kStageEdges : 1];
     if (A.ctr->status != 0) return;
     const int wave = threadIdx.x >> 6;
-    sweep_body<WEIGHTED, STATS, BATCH, OUT>(A, s_src[wave], s_dst[wave], WEIGHTED ? s_w[wave] : nullptr,
-                                             BATCH ? s_sid[wave] : nullptr);
+    sweep_body<WEIGHTED, STATS, BATCH, OUT, BIP>(A, s_src[wave], s_dst[wave], WEIGHTED ? s_w[wave] : nullptr,
+                                                  BATCH ? s_sid[wave] : nullptr);
 }
 
 }  // namespace mh

@@ -29,7 +29,8 @@ def L():
 def test_header_declares_entry_points():
     names = _declared()
     for must in ("mh_sample_unweighted", "mh_sample_weighted", "mh_sample_bruteforce", "mh_expected_degree_fwd",
-                 "mh_expected_degree_bwd", "mh_order", "mh_bound", "mh_plan_counts", "mh_workspace_bytes"):
+                 "mh_expected_degree_bwd", "mh_order", "mh_bound", "mh_plan_counts", "mh_workspace_bytes",
+                 "mh_sample_bipartite", "mh_bipartite_workspace_bytes"):
         assert must in names
 
 
@@ -74,6 +75,37 @@ def test_argument_errors_return_before_device_work(L):
                                   ctypes.c_void_p(16), 5, ctypes.byref(n), ctypes.c_void_p(256), 1 << 20, None,
                                   None) == -1
     assert L.mh_status_string(-2) == b"output capacity too small"
+
+
+def test_bipartite_argument_errors(L):
+    import paper_2509_13230_amd as mh
+
+    n = ctypes.c_int64(7)
+    P = ctypes.c_void_p(16)
+    ws = ctypes.c_void_p(256)
+
+    def call(xr, yr, nr, xc, yc, nc, flags=0, plan=None, cap=0, src=None, dst=None, w=None, nptr=ctypes.byref(n),
+             workspace=None, wsb=0):
+        return L.mh_sample_bipartite(xr, yr, nr, xc, yc, nc, flags, 1, 0, plan, src, dst, w, cap, nptr, workspace,
+                                     wsb, None, None)
+
+    assert call(P, None, 10, P, None, 10, nptr=None) == -1           # no n_edges_host
+    assert call(P, None, -1, P, None, 10) == -1                      # negative size
+    assert call(P, P, 10, P, None, 10) == -1                         # one y missing
+    assert call(P, None, 10, P, None, 10, flags=2) == -1             # unknown flag
+    assert call(None, None, 10, P, None, 10) == -1                   # no row parameters
+    assert call(P, None, 10, P, None, 10, cap=5) == -1               # capacity without outputs
+    bad = mh.PlanParams(-1, 0, 0, 0, None)
+    assert call(P, None, 10, P, None, 10, plan=ctypes.byref(bad)) == -1
+    assert call(P, None, 10, P, None, 10, workspace=ws, wsb=1024) == -4  # workspace too small
+    assert call(None, None, 0, P, None, 10) == 0 and n.value == 0    # an empty set: empty sample
+    n.value = 7
+    assert call(P, None, 10, None, None, 0) == 0 and n.value == 0
+    p = mh.PlanParams(16, 0, 0, 0, None)
+    a = L.mh_bipartite_workspace_bytes(1000, 2000, 0, ctypes.byref(p))
+    b = L.mh_bipartite_workspace_bytes(1_000_000, 2000, 0, ctypes.byref(p))
+    c = L.mh_bipartite_workspace_bytes(1_000_000, 2000, 1, ctypes.byref(p))
+    assert 0 < a < b < c < 200 * 1_002_000
 
 
 def test_binding_fails_loudly_without_device():

@@ -26,6 +26,8 @@ __all__ = [
     "cfg3_targets",
     "cfg4_networks",
     "cfg5_targets",
+    "bipartite_params",
+    "directed_params",
     "sha256",
     "Network",
 ]
@@ -135,3 +137,40 @@ def cfg5_targets(seed: int = 5, n_ubcm: int = 100_000, n_uecm: int = 50_000, kma
     g = rng.gamma(2.0, 3.0, size=n_uecm)
     s_w = np.maximum(np.rint(k_w * (1.0 + g)).astype(np.int64), k_w)
     return k_u, (k_w, s_w)
+
+
+def bipartite_params(seed: int = 6, n_rows: int = 1_000_000, n_cols: int = 500_000, weighted: bool = False):
+    """Two-set case (Sec. 2.6): row degrees power law 2.1 on [1, 10^4], column
+    degrees power law 2.5 on [1, 10^4] rescaled to the same edge total;
+    x+ = k+ / sqrt(E), x- = k- / sqrt(E) (E = sum of row degrees), the
+    sparse-limit scaling of a bipartite network.  Weighted: y+ and y- uniform
+    on [0.05, 0.95]; the product z = x y keeps that scaling.
+    Returns (x_rows, x_cols, y_rows, y_cols) with y None when unweighted."""
+    rng = np.random.default_rng(seed)
+    kr = powerlaw_degrees(rng, n_rows, 2.1, 1, 10_000).astype(np.float64)
+    kc = powerlaw_degrees(rng, n_cols, 2.5, 1, 10_000).astype(np.float64)
+    kc *= kr.sum() / kc.sum()
+    e = np.sqrt(kr.sum())
+    zr, zc = kr / e, kc / e
+    if not weighted:
+        return zr, zc, None, None
+    yr = rng.uniform(0.05, 0.95, n_rows)
+    yc = rng.uniform(0.05, 0.95, n_cols)
+    return zr / yr, zc / yc, yr, yc
+
+
+def directed_params(seed: int = 7, n: int = 500_000, weighted: bool = False):
+    """Directed case (Sec. 2.6): out- and in-degrees, power laws 2.2 and 2.6 on
+    [1, 5000], drawn independently, in-degrees rescaled to the out total;
+    x_out = k_out / sqrt(E), x_in = k_in / sqrt(E).  Weighted: y uniform on
+    [0.05, 0.95] for each side.  Returns (x_out, x_in, y_out, y_in)."""
+    rng = np.random.default_rng(seed)
+    ko = powerlaw_degrees(rng, n, 2.2, 1, 5_000).astype(np.float64)
+    ki = powerlaw_degrees(rng, n, 2.6, 1, 5_000).astype(np.float64)
+    ki *= ko.sum() / ki.sum()
+    e = np.sqrt(ko.sum())
+    if not weighted:
+        return ko / e, ki / e, None, None
+    yo = rng.uniform(0.05, 0.95, n)
+    yi = rng.uniform(0.05, 0.95, n)
+    return ko / e / yo, ki / e / yi, yo, yi
