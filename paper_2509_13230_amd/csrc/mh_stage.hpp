@@ -1,13 +1,17 @@
 // Per-wave edge staging: accepted edges are packed into a wave-private LDS
 // buffer by ballot + popcount and written out in coalesced runs, with one
-// device-scope atomic per run to reserve output slots.
+// device-scope atomic per run to reserve output slots.  All waves reserve
+// from one counter, and a device atomic on one address is serviced about once
+// per 12 ns on MI355X, so runs are long (a wave flushes at ~1000 edges) and
+// the last, partial runs of a block's waves are written together, with one
+// atomic, by the block's last wave to finish.
 #pragma once
 
 #include "mh_common.hpp"
 
 namespace mh {
 
-constexpr int kStageEdges = 512;               // per wave
+constexpr int kStageEdges = 1024;              // per wave
 constexpr int kStageFlushAt = kStageEdges - kWave;
 
 struct EdgeOut {
@@ -93,5 +97,49 @@ struct WaveStage {
         fill = 0;
     }
 };
+
+// End of a block's work: each wave leaves its unflushed count in s_fill and
+// counts itself in *s_arrived (LDS, zeroed at block start); the last wave to
+// arrive reserves the slots of all the block's stages with one atomic and
+// writes them.  Stage w of kind X is at s_X + w * kStageEdges.
+template <bool WEIGHTED, int WAVES>
+__device__ __forceinline__ void block_final_flush(uint32_t fill, const int32_t* s_src, const int32_t* s_dst,
+                                                  const int32_t* s_w, const int32_t* s_sid, uint32_t* s_fill,
+                                                  uint32_t* s_arrived, const EdgeOut& out, int32_t* sid_out) {
+    const int lane = (int)__lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    if (lane == 0) s_fill[wave] = fill;
+    __threadfence_block();  // this wave's stage and count are written before it counts itself
+    uint32_t prev = 0;
+    if (lane == 0) prev = atomicAdd(s_arrived, 1u);
+    prev = __shfl(prev, 0, kWave);
+    if (prev != (uint32_t)(WAVES - 1)) return;
+    __threadfence_block();
+    uint32_t offs[WAVES];
+    uint32_t total = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        offs[w] = total;
+        total += s_fill[w];
+    }
+    if (total == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(out.count, (unsigned long long)total);
+    base = __shfl(base, 0, kWave);
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        const uint32_t f = s_fill[w];
+        const int off = w * kStageEdges;
+        for (uint32_t k = (uint32_t)lane; k < f; k += kWave) {
+            const unsigned long long idx = base + offs[w] + k;
+            if (idx < (unsigned long long)out.capacity) {
+                out.src[idx] = s_src[off + k];
+                out.dst[idx] = s_dst[off + k];
+                if (WEIGHTED) out.w[idx] = s_w[off + k];
+                if (s_sid && sid_out) sid_out[idx] = s_sid[off + k];
+            }
+        }
+    }
+}
 
 }  // namespace mh

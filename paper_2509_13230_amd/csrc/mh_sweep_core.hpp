@@ -148,8 +148,9 @@ enum : uint32_t { S_IDLE = 0, S_REC, S_LOAD, S_STEP, S_DONE };
 
 // BIP: two node sets (single-sample launches only); the column arrays and the
 // chain start differ, and NET_NO_SELF rejects the candidate with the row's id.
+// Returns the number of edges left in the wave's stage (written by the caller).
 template <bool WEIGHTED, bool STATS, bool BATCH, int OUT, bool BIP>
-__device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src, int32_t* s_dst, int32_t* s_w,
+__device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_src, int32_t* s_dst, int32_t* s_w,
                                            int32_t* s_sid) {
     static_assert(!(BIP && BATCH), "two-set networks are sampled one at a time");
     const int wave = threadIdx.x >> 6;
@@ -355,8 +356,6 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
         if (OUT == OUT_EDGES) stage.push_sid(acc, id, dst_id, wt, sample, s_sid, A.out, A.sid);
         if (__ballot(state != S_DONE) == 0) break;
     }
-    if (OUT == OUT_EDGES) stage.flush_sid(s_sid, A.out, A.sid);
-
     if (STATS) {
         const unsigned long long v0 = wave_sum((unsigned long long)st_steps);
         const unsigned long long v1 = wave_sum((unsigned long long)st_props);
@@ -371,6 +370,7 @@ __device__ __forceinline__ void sweep_body(const SweepLaunch& A, int32_t* s_src,
             atomicAdd(&A.ctr->stats[ST_SATURATED], v4);
         }
     }
+    return stage.fill;
 }
 
 template <bool WEIGHTED, bool STATS, bool BATCH, int OUT, bool BIP = false>
@@ -379,10 +379,17 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepLaunch A) {
     __shared__ int32_t s_dst[kSweepWaves][kStageEdges];
     __shared__ int32_t s_w[WEIGHTED ? kSweepWaves : 1][WEIGHTED ? kStageEdges : 1];
     __shared__ int32_t s_sid[BATCH ? kSweepWaves : 1][BATCH ? kStageEdges : 1];
+    __shared__ uint32_t s_fill[kSweepWaves];
+    __shared__ uint32_t s_arrived;
     if (A.ctr->status != 0) return;
+    if (threadIdx.x == 0) s_arrived = 0;
+    __syncthreads();
     const int wave = threadIdx.x >> 6;
-    sweep_body<WEIGHTED, STATS, BATCH, OUT, BIP>(A, s_src[wave], s_dst[wave], WEIGHTED ? s_w[wave] : nullptr,
-                                                  BATCH ? s_sid[wave] : nullptr);
+    const uint32_t fill = sweep_body<WEIGHTED, STATS, BATCH, OUT, BIP>(
+        A, s_src[wave], s_dst[wave], WEIGHTED ? s_w[wave] : nullptr, BATCH ? s_sid[wave] : nullptr);
+    if (OUT == OUT_EDGES)
+        block_final_flush<WEIGHTED, kSweepWaves>(fill, &s_src[0][0], &s_dst[0][0], WEIGHTED ? &s_w[0][0] : nullptr,
+                                                 BATCH ? &s_sid[0][0] : nullptr, s_fill, &s_arrived, A.out, A.sid);
 }
 
 }  // namespace mh
