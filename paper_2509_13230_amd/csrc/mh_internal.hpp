@@ -55,12 +55,27 @@ mh_status scan_exclusive_u64(const uint64_t* in, uint64_t* out, int64_t n, void*
 mh_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void* ws, size_t ws_bytes,
                              hipStream_t stream);
 
+// Single-kernel variant (decoupled look-back) for sums below 2^62.  state:
+// scan_onepass_state_words(n) u64 words, all zero at launch (a caller zeroes
+// them in an earlier kernel); err (device, not null) receives MH_EHIP if a
+// look-back stalls.
+int64_t scan_onepass_state_words(int64_t n);
+mh_status scan_exclusive_u64_onepass(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* state, int32_t* err,
+                                     hipStream_t stream);
+
 // ---- radix sort of (key, value) pairs ascending by key, stable ----
+// Copies of the digit histograms: enough that no address takes more than a few
+// dozen of the counting kernel's atomics, few enough that each pass sums them
+// with one round of loads.
+constexpr int kRadixHistCopies = 4;
 size_t radix_workspace_bytes(int64_t n);
 // Zeroes the sort's scratch (in ws) and returns its histogram array for a fused
-// counting kernel: 32 copies of 8 x 256 counts (copy c, pass p, digit d at
-// [(c * 8 + p) * 256 + d]); a counting block adds into copy blockIdx % 32.
-mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream);
+// counting kernel: kRadixHistCopies copies of 8 x 256 counts (copy c, pass p,
+// digit d at [(c * 8 + p) * 256 + d]); a counting block adds into copy
+// blockIdx % kRadixHistCopies.
+// extra_zero / extra_words: another range of u64 words zeroed by the same kernel.
+mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream,
+                        uint64_t* extra_zero = nullptr, int64_t extra_words = 0);
 // Sorts keys[0..n) / vals[0..n) using alt buffers of the same size; the result
 // ends in keys/vals (8 passes of 8 bits).  hist_ready: the histogram returned
 // by radix_prepare already holds the counts.  err (optional, device) receives
@@ -80,9 +95,12 @@ size_t order_workspace_bytes(int64_t n);
 // Writes the order either as packed records (node != null: z and id; nseg is
 // left for the plan) or as separate perm / zs arrays.  check_square: the
 // largest z squared must be finite (one node set, where it is the largest t).
+// extra_zero / extra_words: u64 words zeroed on the way (look-back state of
+// later steps).
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
                       NodeRec* node, int32_t* status, uint64_t* mass_out, void* ws, size_t ws_bytes,
-                      hipStream_t stream, bool check_square = true);
+                      hipStream_t stream, bool check_square = true, uint64_t* extra_zero = nullptr,
+                      int64_t extra_words = 0);
 
 size_t bound_workspace_bytes(int64_t n);
 mh_status bound_suffix_top2(const double* ys, int64_t n, double* c, int32_t* status, void* ws, size_t ws_bytes,

@@ -85,8 +85,8 @@ __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict
     }
     if (bad) raise_status(status, MH_EINVAL);
     __syncthreads();
-    // one of 32 histogram copies per block (the sort sums them)
-    uint32_t* copy = hist + (blockIdx.x % 32) * 8 * 256;
+    // one of the histogram copies per block (the sort sums them)
+    uint32_t* copy = hist + (blockIdx.x % kRadixHistCopies) * 8 * 256;
     for (int i = threadIdx.x; i < 8 * 256; i += kThreads)
         if (h[i]) atomicAdd(&copy[i], h[i]);
 }
@@ -249,7 +249,7 @@ size_t order_workspace_bytes(int64_t n) {
 
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
                       NodeRec* node, int32_t* status, uint64_t* mass_out, void* ws, size_t ws_bytes,
-                      hipStream_t stream, bool check_square) {
+                      hipStream_t stream, bool check_square, uint64_t* extra_zero, int64_t extra_words) {
     if (n <= 0) return MH_OK;
     Arena ar(ws, ws_bytes);
     uint64_t* keys = ar.take<uint64_t>(n);
@@ -261,7 +261,7 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
     void* sort_ws = ar.base + off;
     const size_t sort_bytes = ws_bytes > off ? ws_bytes - off : 0;
     uint32_t* hist = nullptr;
-    mh_status st = radix_prepare(sort_ws, sort_bytes, n, &hist, stream);
+    mh_status st = radix_prepare(sort_ws, sort_bytes, n, &hist, stream, extra_zero, extra_words);
     if (st != MH_OK) return st;
     const unsigned tiles = (unsigned)((n + kPrepTile - 1) / kPrepTile);
     hipLaunchKernelGGL(k_prep_keys, dim3(tiles), dim3(kThreads), 0, stream, x, y, n, keys, vals, hist, status);

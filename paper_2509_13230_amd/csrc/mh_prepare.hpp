@@ -18,6 +18,8 @@ struct NetBuffers {
     uint64_t* hoff;
     HeavyRec* rec;
     int64_t rec_cap;
+    uint64_t* scan_state;  // look-back state of the two plan scans (P, then hoff)
+    int64_t scan_words;
     int64_t n;
     int32_t T;
     bool weighted;

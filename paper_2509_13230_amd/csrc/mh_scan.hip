@@ -121,9 +121,124 @@ mh_status scan_impl(const T* in, T* out, int64_t n, Arena& ar, hipStream_t strea
     return MH_OK;
 }
 
+// ---- single pass: one kernel, decoupled look-back over tiles ----
+constexpr int kOneItems = 16;
+constexpr int kOneTile = kScanThreads * kOneItems;  // 4096
+constexpr uint32_t kOneSpinLimit = 1u << 20;
+// Look-back word per tile, zero at launch: the flag in the top two bits (1 = the
+// tile's own sum, 2 = the inclusive prefix through the tile) and the value in
+// the low 62.  Flag and value travel in one relaxed atomic, so no fence is
+// needed between them.  Prefix sums must stay below 2^62 (the caller checks).
+constexpr uint64_t kOneAgg = 1ull << 62;
+constexpr uint64_t kOneInc = 2ull << 62;
+constexpr uint64_t kOneValue = kOneAgg - 1;
+
+// Blocks take tiles blockIdx, blockIdx + gridDim, ... with the whole grid
+// resident, so a tile waits only on lower tiles that are being processed.
+__global__ __launch_bounds__(kScanThreads) void k_scan_onepass(const uint64_t* in, uint64_t* out, int64_t n,
+                                                               int64_t tiles, uint64_t* state, int32_t* err) {
+    __shared__ uint64_t lds_items[kOneTile];
+    __shared__ uint64_t lds_waves[kScanThreads / kWave];
+    __shared__ uint64_t s_excl;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t base = tile * kOneTile;
+#pragma unroll
+        for (int k = 0; k < kOneItems; ++k) {
+            const int idx = k * kScanThreads + threadIdx.x;
+            const int64_t i = base + idx;
+            lds_items[idx] = (i < n) ? in[i] : 0ull;
+        }
+        __syncthreads();
+        uint64_t vals[kOneItems];
+        uint64_t run = 0;
+#pragma unroll
+        for (int k = 0; k < kOneItems; ++k) {
+            vals[k] = lds_items[threadIdx.x * kOneItems + k];
+            run += vals[k];
+        }
+        uint64_t total;
+        const uint64_t before = block_exclusive_scan(run, lds_waves, &total);
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(&state[tile], (tile == 0 ? kOneInc : kOneAgg) | total, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            if (tile == 0) s_excl = 0;
+        }
+        if (wave == 0 && tile > 0) {
+            // lane l looks at tile t - l; sum published sums back to the
+            // nearest inclusive prefix, re-polling where a tile is not yet out
+            uint64_t excl = 0;
+            int64_t t = tile - 1;
+            uint32_t spins = 0;
+            for (;;) {
+                const int64_t tt = t - lane;
+                const uint64_t w =
+                    (tt >= 0) ? __hip_atomic_load(&state[tt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kOneInc;
+                const uint64_t f = w & ~kOneValue;
+                const uint64_t none = __ballot(f == 0);
+                const uint64_t incl = __ballot(f == kOneInc);
+                const int first_none = none ? (int)__ffsll((unsigned long long)none) - 1 : kWave;
+                const int first_incl = incl ? (int)__ffsll((unsigned long long)incl) - 1 : kWave;
+                const bool finish = first_incl < first_none;
+                const int used = finish ? first_incl + 1 : first_none;
+                excl += wave_sum(lane < used ? (w & kOneValue) : 0ull);
+                if (finish) break;
+                t -= used;
+                if (used == 0) {
+                    if (++spins > kOneSpinLimit) {
+                        raise_status(err, MH_EHIP);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            if (lane == 0) {
+                __hip_atomic_store(&state[tile], kOneInc | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_excl = excl;
+            }
+        }
+        __syncthreads();
+        uint64_t acc = s_excl + before;
+#pragma unroll
+        for (int k = 0; k < kOneItems; ++k) {
+            lds_items[threadIdx.x * kOneItems + k] = acc;
+            acc += vals[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kOneItems; ++k) {
+            const int idx = k * kScanThreads + threadIdx.x;
+            const int64_t i = base + idx;
+            if (i < n) out[i] = lds_items[idx];
+        }
+        if (threadIdx.x == 0 && base + kOneTile >= n) out[n] = s_excl + total;
+        __syncthreads();  // the next tile reuses the LDS
+    }
+}
+
 }  // namespace
 
 size_t scan_workspace_bytes(int64_t n) { return levels_bytes<uint64_t>(n); }
+
+int64_t scan_onepass_state_words(int64_t n) { return n > 0 ? (n + kOneTile - 1) / kOneTile : 1; }
+
+mh_status scan_exclusive_u64_onepass(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* state, int32_t* err,
+                                     hipStream_t stream) {
+    if (n < 0) return MH_EINVAL;
+    const int64_t tiles = scan_onepass_state_words(n);
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scan_onepass, kScanThreads, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int64_t resident = (int64_t)cus * per_cu;
+    const int64_t grid = tiles < resident ? tiles : resident;
+    hipLaunchKernelGGL(k_scan_onepass, dim3((unsigned)grid), dim3(kScanThreads), 0, stream, in, out, n, tiles, state,
+                       err);
+    MH_HIP_TRY(hipGetLastError());
+    return MH_OK;
+}
 
 mh_status scan_exclusive_u64(const uint64_t* in, uint64_t* out, int64_t n, void* ws, size_t ws_bytes,
                              hipStream_t stream) {

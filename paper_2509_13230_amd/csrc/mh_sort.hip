@@ -19,10 +19,13 @@ namespace mh {
 
 namespace {
 
-constexpr int kSortThreads = 256;
+// 16 waves share a tile (4 keys per lane): a pass is a chain of dependent
+// steps (load, rank, publish, look back, scatter) on ~250 tiles for 1M keys,
+// so the waves of a block, not more tiles, are what hide its latencies.
+constexpr int kSortThreads = 1024;
 constexpr int kSortWaves = kSortThreads / kWave;
-constexpr int kKeysPerLane = 16;
-constexpr int kWaveKeys = kWave * kKeysPerLane;     // 1024, contiguous per wave
+constexpr int kKeysPerLane = 4;
+constexpr int kWaveKeys = kWave * kKeysPerLane;     // 256, contiguous per wave
 constexpr int kTileKeys = kWaveKeys * kSortWaves;  // 4096 per block
 constexpr int kRadix = 256;
 constexpr int kPasses = 8;
@@ -31,9 +34,8 @@ constexpr uint64_t kFlagPrefix = 2ull << 32;
 constexpr uint32_t kSpinLimit = 1u << 20;
 constexpr int kLookWindow = 8;
 // The counting kernel adds its block histograms into kHistCopies copies (block
-// b into copy b % kHistCopies), so that no address sees more than a few of the
-// device-scope atomics; readers sum the copies.
-constexpr int kHistCopies = 32;
+// b into copy b % kHistCopies); readers sum the copies.
+constexpr int kHistCopies = kRadixHistCopies;
 
 // Lanes (among `valid`) whose digit equals this lane's.
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -47,8 +49,8 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
     return m;
 }
 
-// Exclusive scan of one value per thread (256 threads) through LDS.
-__device__ __forceinline__ uint32_t block_exclusive_256(uint32_t v, uint32_t* lds_wave) {
+// Exclusive scan of one value per thread (all kSortThreads) through LDS.
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* lds_wave) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t inc = wave_inclusive_scan(v);
     if (lane == 63) lds_wave[wave] = inc;
@@ -61,9 +63,12 @@ __device__ __forceinline__ uint32_t block_exclusive_256(uint32_t v, uint32_t* ld
     return before + inc - v;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_zero_u64(uint64_t* __restrict__ p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSortThreads)
-        p[i] = 0;
+// Zeroes two ranges of u64 words (the second may be empty).
+__global__ __launch_bounds__(kSortThreads) void k_zero_u64(uint64_t* __restrict__ p, int64_t n,
+                                                           uint64_t* __restrict__ q, int64_t m) {
+    const int64_t stride = (int64_t)gridDim.x * kSortThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n; i += stride) p[i] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < m; i += stride) q[i] = 0;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n,
@@ -139,25 +144,27 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     }
     __syncthreads();
 
-    const int d = threadIdx.x;  // one digit per thread
-    uint32_t total = 0;
-#pragma unroll
-    for (int w = 0; w < kSortWaves; ++w) {
-        const uint32_t c = cnt[w][d];
-        cnt[w][d] = total;  // becomes the wave's offset inside the block's digit run
-        total += c;
-    }
+    const int d = threadIdx.x;  // one digit per thread of the first kRadix
+    const bool dig = d < kRadix;
+    uint32_t total = 0, dtotal = 0;
     uint64_t* st = status + tile * kRadix + d;
-    __hip_atomic_store(st, (tile == 0 ? kFlagPrefix : kFlagAggregate) | total, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t bstart = block_exclusive_256(total, s_scan);
-    uint32_t dtotal = 0;
-#pragma unroll 8
-    for (int c = 0; c < kHistCopies; ++c) dtotal += ghist[c * kPasses * kRadix + d];
-    const uint32_t dstart = block_exclusive_256(dtotal, s_scan);
+    if (dig) {
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) {
+            const uint32_t c = cnt[w][d];
+            cnt[w][d] = total;  // becomes the wave's offset inside the block's digit run
+            total += c;
+        }
+        __hip_atomic_store(st, (tile == 0 ? kFlagPrefix : kFlagAggregate) | total, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int c = 0; c < kHistCopies; ++c) dtotal += ghist[c * kPasses * kRadix + d];
+    }
+    const uint32_t bstart = block_exclusive(total, s_scan);
+    const uint32_t dstart = block_exclusive(dtotal, s_scan);
     // look back over the preceding tiles, kLookWindow words in flight at a time
     uint32_t excl = 0;
-    if (tile > 0) {
+    if (dig && tile > 0) {
         int64_t t = tile - 1;
         uint32_t spins = 0;
         bool done = false;
@@ -182,7 +189,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
             t -= used;
             if (used == 0) {
                 if (++spins > kSpinLimit) {
-                    raise_status(err, MH_EHIP);
+                    raise_status(err, MH_EHIP);  // the scatter below stays in bounds
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
@@ -190,8 +197,10 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
         }
         __hip_atomic_store(st, kFlagPrefix | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    s_bstart[d] = bstart;
-    s_goff[d] = dstart + excl - bstart;
+    if (dig) {
+        s_bstart[d] = bstart;
+        s_goff[d] = dstart + excl - bstart;
+    }
     __syncthreads();
 
     // reorder the tile by digit in LDS, then write each digit's run contiguously
@@ -211,8 +220,10 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
         const uint64_t key = s_keys[i];
         const uint32_t dd = (uint32_t)(key >> shift) & (kRadix - 1);
         const uint32_t pos = s_goff[dd] + (uint32_t)i;
-        kout[pos] = key;
-        vout[pos] = s_vals[i];
+        if (pos < (uint64_t)n) {  // always, unless a look-back gave up (then the error is raised)
+            kout[pos] = key;
+            vout[pos] = s_vals[i];
+        }
     }
 }
 
@@ -287,13 +298,17 @@ static SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) 
     return s;
 }
 
-mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream) {
+mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream,
+                        uint64_t* extra_zero, int64_t extra_words) {
     bool ok = false;
     SortScratch s = sort_scratch(ws, ws_bytes, n, &ok);
     if (!ok) return MH_EWORKSPACE;
-    int64_t blocks = (s.words + kSortThreads - 1) / kSortThreads;
+    if (!extra_zero) extra_words = 0;
+    const int64_t most = s.words > extra_words ? s.words : extra_words;
+    int64_t blocks = (most + kSortThreads - 1) / kSortThreads;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), dim3(kSortThreads), 0, stream, s.status, s.words);
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), dim3(kSortThreads), 0, stream, s.status, s.words,
+                       extra_zero, extra_words);
     MH_HIP_TRY(hipGetLastError());
     *hist = s.hist;
     return MH_OK;

@@ -100,6 +100,15 @@ __global__ __launch_bounds__(kThreads) void k_heavy_records(NetDesc D, HeavyRec*
 
 }  // namespace
 
+// Exclusive scan of a plan array in place: one kernel (look-back) while its
+// sums stay below 2^62, which holds for up to 2^30 entries (masses are at most
+// 2^32 each; segment counts are far smaller); three kernels beyond.
+static mh_status plan_scan(uint64_t* a, int64_t n, uint64_t* state, int32_t* status, void* scratch,
+                           size_t scratch_bytes, hipStream_t stream) {
+    if (n <= (int64_t)1 << 30) return scan_exclusive_u64_onepass(a, a, n, state, status, stream);
+    return scan_exclusive_u64(a, a, n, scratch, scratch_bytes, stream);
+}
+
 // ---- one prepared network: buffers, sizes and preparation ----
 template <typename A>
 static NetBuffers carve_network_impl(A& ar, int64_t n, bool weighted, int32_t T) {
@@ -114,8 +123,10 @@ static NetBuffers carve_network_impl(A& ar, int64_t n, bool weighted, int32_t T)
     B.hoff = ar.template take<uint64_t>(seg ? n + 1 : 0);
     B.rec_cap = seg ? n + 4096 : 0;  // records for up to this many heavy items; more are located in the sweep
     B.rec = ar.template take<HeavyRec>(B.rec_cap);
+    B.scan_words = seg ? 2 * scan_onepass_state_words(n) : 0;
+    B.scan_state = ar.template take<uint64_t>(B.scan_words);
     if (!weighted) B.ys = B.c = nullptr;
-    if (!seg) B.P = nullptr, B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr;
+    if (!seg) B.P = nullptr, B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.scan_state = nullptr;
     B.n = n;
     B.T = T;
     B.weighted = weighted;
@@ -185,7 +196,7 @@ mh_status prepare_network(const double* x, const double* y, const NetBuffers& B,
     if (n <= 0) return MH_OK;
     const bool seg = B.T > 0;
     mh_status st = order_nodes(x, B.weighted ? y : nullptr, n, nullptr, nullptr, B.ys, B.node, status, B.P,
-                               scratch, scratch_bytes, stream);
+                               scratch, scratch_bytes, stream, true, B.scan_state, B.scan_words);
     if (st != MH_OK) return st;
     if (ev) MH_HIP_TRY(hipEventRecord(ev[1], stream));
     if (B.weighted) {
@@ -193,7 +204,7 @@ mh_status prepare_network(const double* x, const double* y, const NetBuffers& B,
         if (st != MH_OK) return st;
     }
     if (seg) {
-        st = scan_exclusive_u64(B.P, B.P, n, scratch, scratch_bytes, stream);
+        st = plan_scan(B.P, n, B.scan_state, status, scratch, scratch_bytes, stream);
         if (st != MH_OK) return st;
     }
     const unsigned rows_grid = (unsigned)((n + kThreads - 1) / kThreads);
@@ -201,7 +212,7 @@ mh_status prepare_network(const double* x, const double* y, const NetBuffers& B,
                        (const NodeRec*)B.node, n, 0, B.T, (const uint64_t*)B.P, B.jend, B.mq, B.hoff);
     MH_HIP_TRY(hipGetLastError());
     if (seg) {
-        st = scan_exclusive_u64(B.hoff, B.hoff, n, scratch, scratch_bytes, stream);
+        st = plan_scan(B.hoff, n, B.scan_state + scan_onepass_state_words(n), status, scratch, scratch_bytes, stream);
         if (st != MH_OK) return st;
         hipLaunchKernelGGL(k_heavy_records, dim3(512), dim3(kThreads), 0, stream, net_desc(B), B.rec,
                            (const int32_t*)status);
@@ -399,6 +410,8 @@ struct BipBuffers {
     double* ysc;
     uint64_t* P;
     unsigned long long* ymax;
+    uint64_t* scan_state;  // look-back state: P scan over the columns, then hoff over the rows
+    int64_t scan_words;
 };
 
 template <typename A>
@@ -417,8 +430,10 @@ BipBuffers carve_bipartite(A& ar, int64_t nr, int64_t nc, bool weighted, int32_t
     B.ysc = ar.template take<double>(weighted ? nc : 0);
     B.P = ar.template take<uint64_t>(seg ? nc + 1 : 0);
     B.ymax = ar.template take<unsigned long long>(1);
+    B.scan_words = seg ? scan_onepass_state_words(nc) + scan_onepass_state_words(nr) : 0;
+    B.scan_state = ar.template take<uint64_t>(B.scan_words);
     if (!weighted) B.ysr = B.c = B.ysc = nullptr;
-    if (!seg) B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.P = nullptr;
+    if (!seg) B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.P = nullptr, B.scan_state = nullptr;
     return B;
 }
 
@@ -487,7 +502,7 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
     if (st != MH_OK) return st;
     // A1: each set sorted by its own z; the column masses for the plan
     st = order_nodes(xr, yr, nr, nullptr, nullptr, B.ysr, B.rows, status, nullptr, scratch, scratch_bytes, stream,
-                     false);
+                     false, B.scan_state, B.scan_words);
     if (st != MH_OK) return st;
     st = order_nodes(xc, yc, nc, nullptr, nullptr, B.ysc, B.cols, status, B.P, scratch, scratch_bytes, stream,
                      false);
@@ -510,7 +525,7 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
     MH_HIP_TRY(hipGetLastError());
     // A3: plan over the columns
     if (seg) {
-        st = scan_exclusive_u64(B.P, B.P, nc, scratch, scratch_bytes, stream);
+        st = plan_scan(B.P, nc, B.scan_state, status, scratch, scratch_bytes, stream);
         if (st != MH_OK) return st;
     }
     hipLaunchKernelGGL(k_row_plan, dim3(rows_grid), dim3(kThreads), 0, stream, B.rows, (const double*)B.c, nr,
@@ -518,7 +533,8 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
     MH_HIP_TRY(hipGetLastError());
     const NetDesc D = bip_desc(B, nr, nc, T, flags);
     if (seg) {
-        st = scan_exclusive_u64(B.hoff, B.hoff, nr, scratch, scratch_bytes, stream);
+        st = plan_scan(B.hoff, nr, B.scan_state + scan_onepass_state_words(nc), status, scratch, scratch_bytes,
+                       stream);
         if (st != MH_OK) return st;
         hipLaunchKernelGGL(k_heavy_records, dim3(512), dim3(kThreads), 0, stream, D, B.rec, (const int32_t*)status);
         MH_HIP_TRY(hipGetLastError());

@@ -78,6 +78,17 @@ def test_order_matches_oracle(mh, n):
     assert np.array_equal(zs.cpu().numpy(), x[ref])
 
 
+def test_order_beyond_count_tiles_matches_oracle(mh):
+    # more tiles of 4096 keys than blocks resident at once: the sort's blocks
+    # take their tiles by ticket
+    rng = np.random.default_rng(12)
+    n = 2048 * 4096 + 12_345
+    x = np.round(rng.lognormal(-2, 1.5, n), 5)
+    perm, zs, _, status = mh.order(dev(x))
+    assert int(status.item()) == 0
+    assert np.array_equal(perm.cpu().numpy(), oracle.order(x))
+
+
 def test_order_weighted_key_is_rounded_product(mh):
     rng = np.random.default_rng(3)
     n = 20_000
