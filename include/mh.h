@@ -109,6 +109,29 @@ mh_status mh_sample_weighted(const double* x, const double* y, int64_t n, uint64
                              void* workspace, size_t ws_bytes, mh_stats* stats_host,
                              hipStream_t stream);
 
+/* Asynchronous samplers: the same work as mh_sample_unweighted /
+ * mh_sample_weighted, enqueued on `stream` without waiting for it, so that
+ * samples can follow one another on a stream with no host round trip between
+ * them.  Argument errors are returned at once; the sample's edge count and
+ * status stay in the workspace until mh_sample_result() reads them (it waits
+ * for the stream).  A later call on the same workspace replaces them, in
+ * stream order; the output buffers and the workspace must not be touched by
+ * other work on other streams before the sample completes.  No statistics. */
+mh_status mh_sample_unweighted_async(const double* x, int64_t n, uint64_t seed, uint32_t replica,
+                                     const mh_plan_params* plan, int32_t* src, int32_t* dst,
+                                     int64_t capacity, void* workspace, size_t ws_bytes,
+                                     hipStream_t stream);
+mh_status mh_sample_weighted_async(const double* x, const double* y, int64_t n, uint64_t seed,
+                                   uint32_t replica, const mh_plan_params* plan, int32_t* src,
+                                   int32_t* dst, int32_t* w, int64_t capacity, void* workspace,
+                                   size_t ws_bytes, hipStream_t stream);
+/* Waits for `stream` and reads the last asynchronous sample of `workspace`:
+ * *n_edges_host = its edge count; MH_ECAPACITY if that exceeds capacity (the
+ * capacity the sample was given); MH_EINVAL / MH_EHIP if the device found
+ * invalid parameters or a stalled step. */
+mh_status mh_sample_result(const void* workspace, size_t ws_bytes, int64_t capacity,
+                           int64_t* n_edges_host, hipStream_t stream);
+
 /* Two node sets: bipartite and directed networks (Sec. 2.6).  Rows are the
  * "+" set (x_rows, y_rows, n_rows), columns the "-" set (x_cols, y_cols,
  * n_cols); p_ij is the model's formula with z_i from the row set and z_j from

@@ -75,6 +75,10 @@ def lib() -> ctypes.CDLL:
         "mh_sample_unweighted": ([vp, i64, u64, u32, P(PlanParams), vp, vp, i64, P(i64), vp, sz, P(Stats), vp], ctypes.c_int),
         "mh_sample_weighted": ([vp, vp, i64, u64, u32, P(PlanParams), vp, vp, vp, i64, P(i64), vp, sz, P(Stats), vp],
                                ctypes.c_int),
+        "mh_sample_unweighted_async": ([vp, i64, u64, u32, P(PlanParams), vp, vp, i64, vp, sz, vp], ctypes.c_int),
+        "mh_sample_weighted_async": ([vp, vp, i64, u64, u32, P(PlanParams), vp, vp, vp, i64, vp, sz, vp],
+                                     ctypes.c_int),
+        "mh_sample_result": ([vp, sz, i64, P(i64), vp], ctypes.c_int),
         "mh_bipartite_workspace_bytes": ([i64, i64, ctypes.c_int, P(PlanParams)], sz),
         "mh_sample_bipartite": ([vp, vp, i64, vp, vp, i64, u32, u64, u32, P(PlanParams), vp, vp, vp, i64, P(i64), vp,
                                  sz, P(Stats), vp], ctypes.c_int),
@@ -197,6 +201,46 @@ def sample_weighted(x: torch.Tensor, y: torch.Tensor, seed: int = 1, replica: in
     """One sample of the weighted model (Sec. 2.5, Alg. 1): (src, dst, w)."""
     r = _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stage_events, grid_blocks)
     return (r.src, r.dst, r.w, r.stats) if stats else (r.src, r.dst, r.w)
+
+
+def sample_async(x: torch.Tensor, y: torch.Tensor | None, out, workspace: torch.Tensor, seed: int = 1,
+                 replica: int = 0, seg_work: int = DEFAULT_SEG_WORK, stage_events=None, grid_blocks: int = 0):
+    """Enqueue one sample (unweighted if y is None) on the current stream
+    without waiting.  ``out = (src, dst[, w])`` and ``workspace`` (at least
+    mh_workspace_bytes) are required and belong to the sample until
+    ``sample_result`` has read it back."""
+    x = _dev_f64(x, "x")
+    if y is not None:
+        y = _dev_f64(y, "y")
+        if y.shape != x.shape:
+            raise ValueError("x and y must have the same shape")
+    n = x.numel()
+    L = lib()
+    plan = PlanParams(int(seg_work), 0, int(grid_blocks), 0, stage_events)
+    wsb = L.mh_workspace_bytes(n, 1 if y is not None else 0, ctypes.byref(plan))
+    if workspace.numel() < wsb:
+        raise ValueError(f"workspace of {workspace.numel()} bytes, {wsb} needed")
+    src, dst = out[0], out[1]
+    w = out[2] if y is not None else None
+    cap = min(src.numel(), dst.numel(), w.numel() if w is not None else src.numel())
+    stream = _stream(x.device)
+    if y is None:
+        status = L.mh_sample_unweighted_async(_ptr(x), n, seed, replica, ctypes.byref(plan), _ptr(src), _ptr(dst),
+                                              cap, _ptr(workspace), workspace.numel(), stream)
+    else:
+        status = L.mh_sample_weighted_async(_ptr(x), _ptr(y), n, seed, replica, ctypes.byref(plan), _ptr(src),
+                                            _ptr(dst), _ptr(w), cap, _ptr(workspace), workspace.numel(), stream)
+    _check(status, "mh_sample_async")
+    return cap
+
+
+def sample_result(workspace: torch.Tensor, capacity: int) -> int:
+    """Edge count of the last asynchronous sample of ``workspace`` (waits)."""
+    nedge = ctypes.c_int64(0)
+    status = lib().mh_sample_result(_ptr(workspace), workspace.numel(), int(capacity), ctypes.byref(nedge),
+                                    _stream(workspace.device))
+    _check(status, "mh_sample_result")
+    return int(nedge.value)
 
 
 MH_BIP_NO_SELF = 1

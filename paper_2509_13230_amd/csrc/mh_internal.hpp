@@ -48,6 +48,16 @@ struct Sizer {
         if (e_ != hipSuccess) return MH_EHIP;         \
     } while (0)
 
+// ---- device facts, queried once per device (and kernel) and kept ----
+// Compute units of the current device (256 if the query fails).
+int device_cus();
+// Blocks of `kernel` with `threads` threads that one CU holds at once (>= 1).
+int blocks_per_cu(const void* kernel, int threads);
+template <typename K>
+int64_t resident_blocks(K kernel, int threads) {
+    return (int64_t)device_cus() * blocks_per_cu(reinterpret_cast<const void*>(kernel), threads);
+}
+
 // ---- exclusive scans: out[0..n] with out[n] = total (in may alias out) ----
 size_t scan_workspace_bytes(int64_t n);
 mh_status scan_exclusive_u64(const uint64_t* in, uint64_t* out, int64_t n, void* ws, size_t ws_bytes,

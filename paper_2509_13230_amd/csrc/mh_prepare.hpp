@@ -34,17 +34,4 @@ mh_status init_counters(Counters* c, hipStream_t stream);
 mh_status prepare_network(const double* x, const double* y, const NetBuffers& B, int32_t* status, void* scratch,
                           size_t scratch_bytes, hipStream_t stream, hipEvent_t* ev);
 
-// Blocks of `kernel` (with `threads` threads) that fit on the device at once.
-template <typename K>
-int64_t resident_blocks(K kernel, int threads) {
-    int cus = 256, dev = 0, per_cu = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
-    }
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    return (int64_t)cus * per_cu;
-}
-
 }  // namespace mh

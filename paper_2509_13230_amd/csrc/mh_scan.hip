@@ -227,12 +227,7 @@ mh_status scan_exclusive_u64_onepass(const uint64_t* in, uint64_t* out, int64_t 
                                      hipStream_t stream) {
     if (n < 0) return MH_EINVAL;
     const int64_t tiles = scan_onepass_state_words(n);
-    int dev = 0, cus = 256, per_cu = 1;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scan_onepass, kScanThreads, 0) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    const int64_t resident = (int64_t)cus * per_cu;
+    const int64_t resident = resident_blocks(k_scan_onepass, kScanThreads);
     const int64_t grid = tiles < resident ? tiles : resident;
     hipLaunchKernelGGL(k_scan_onepass, dim3((unsigned)grid), dim3(kScanThreads), 0, stream, in, out, n, tiles, state,
                        err);

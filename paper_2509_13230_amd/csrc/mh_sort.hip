@@ -250,12 +250,7 @@ mh_status radix_sort_u64_hist(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, keys, n, hist);
         MH_HIP_TRY(hipGetLastError());
     }
-    int cus = 0, per_cu = 0, dev = 0;
-    bool use_ticket = true;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_onesweep, kSortThreads, 0) == hipSuccess)
-        use_ticket = nb > (int64_t)cus * per_cu;
+    const bool use_ticket = nb > resident_blocks(k_onesweep, kSortThreads);
     uint64_t* kin = keys;
     uint32_t* vin = vals;
     uint64_t* kout = keys_alt;

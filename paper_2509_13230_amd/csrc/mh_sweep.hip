@@ -239,8 +239,7 @@ void launch_sweep(const SweepLaunch& A, int64_t n, int32_t grid_blocks, hipStrea
     // lists the lanes of a wave stay busier while its long chains finish, and
     // 3 waves per SIMD still cover the load latency (measured on N = 1e6).
     int64_t cap = resident_blocks(kern, kThreads);
-    int cus = 256, dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int cus = device_cus();
     if (grid_blocks > 0) {
         if (grid_blocks < cap) cap = grid_blocks;
     } else if ((int64_t)3 * cus < cap) {
@@ -249,56 +248,9 @@ void launch_sweep(const SweepLaunch& A, int64_t n, int32_t grid_blocks, hipStrea
     hipLaunchKernelGGL(kern, dim3((unsigned)(want < cap ? want : cap)), dim3(kThreads), 0, stream, A);
 }
 
-mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed, uint32_t replica,
-                      const mh_plan_params* plan, int32_t* src, int32_t* dst, int32_t* w, int64_t capacity,
-                      int64_t* n_edges_host, void* workspace, size_t ws_bytes, mh_stats* stats_host,
-                      hipStream_t stream) {
-    const bool weighted = (y != nullptr);
-    if (!n_edges_host || n < 0 || n > 0x7FFFFFFFll || capacity < 0) return MH_EINVAL;
-    if (!x && n > 0) return MH_EINVAL;
-    if (capacity > 0 && (!src || !dst || (weighted && !w))) return MH_EINVAL;
-    const int32_t T = plan ? plan->seg_work : 16;
-    if (T < 0 || (plan && (plan->flags != 0 || plan->grid_blocks < 0))) return MH_EINVAL;
-    *n_edges_host = 0;
-    if (stats_host) *stats_host = mh_stats{0, 0, 0, 0, 0, 0};
-    if (n == 0) return MH_OK;
-    if (!workspace || ws_bytes < sample_workspace_bytes(n, weighted, T)) return MH_EWORKSPACE;
-
-    Arena ar(workspace, ws_bytes);
-    Counters* ctr = ar.take<Counters>(1);
-    NetBuffers B = carve_network(ar, n, weighted, T);
-    if (ar.overflow) return MH_EWORKSPACE;
-    const size_t off = (ar.used + 255) & ~size_t(255);
-    void* scratch = ar.base + off;
-    const size_t scratch_bytes = ws_bytes - off;
-
-    hipEvent_t* ev = plan ? plan->stage_events : nullptr;
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[0], stream));
-    mh_status st = init_counters(ctr, stream);
-    if (st != MH_OK) return st;
-    st = prepare_network(x, y, B, &ctr->status, scratch, scratch_bytes, stream, ev);
-    if (st != MH_OK) return st;
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[2], stream));
-
-    SweepLaunch A{};
-    A.net = net_desc(B);
-    A.replica = replica;
-    A.key0 = (uint32_t)seed;
-    A.key1 = (uint32_t)(seed >> 32);
-    A.out = EdgeOut{src, dst, w, capacity, &ctr->n_edges};
-    A.sid = nullptr;
-    A.ctr = ctr;
-    const int32_t gb = plan ? plan->grid_blocks : 0;
-    if (weighted) {
-        if (stats_host) launch_sweep<true, true>(A, n, gb, stream);
-        else launch_sweep<true, false>(A, n, gb, stream);
-    } else {
-        if (stats_host) launch_sweep<false, true>(A, n, gb, stream);
-        else launch_sweep<false, false>(A, n, gb, stream);
-    }
-    MH_HIP_TRY(hipGetLastError());
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[3], stream));
-
+// Reads a sample's counters back (waits for the stream).
+mh_status read_counters(const Counters* ctr, int64_t capacity, int64_t* n_edges_host, mh_stats* stats_host,
+                        hipStream_t stream) {
     Counters hc;
     MH_HIP_TRY(hipMemcpyAsync(&hc, ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
     MH_HIP_TRY(hipStreamSynchronize(stream));
@@ -314,6 +266,70 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
     }
     if ((int64_t)hc.n_edges > capacity) return MH_ECAPACITY;
     return MH_OK;
+}
+
+// Checks the arguments and enqueues a whole sample on `stream`; the counters
+// (edge count, status, statistics) are left at the start of the workspace.
+mh_status enqueue_sample(const double* x, const double* y, int64_t n, uint64_t seed, uint32_t replica,
+                         const mh_plan_params* plan, int32_t* src, int32_t* dst, int32_t* w, int64_t capacity,
+                         void* workspace, size_t ws_bytes, bool stats, hipStream_t stream) {
+    const bool weighted = (y != nullptr);
+    if (n < 0 || n > 0x7FFFFFFFll || capacity < 0) return MH_EINVAL;
+    if (!x && n > 0) return MH_EINVAL;
+    if (capacity > 0 && (!src || !dst || (weighted && !w))) return MH_EINVAL;
+    const int32_t T = plan ? plan->seg_work : 16;
+    if (T < 0 || (plan && (plan->flags != 0 || plan->grid_blocks < 0))) return MH_EINVAL;
+    if (!workspace || ws_bytes < sample_workspace_bytes(n, weighted, T)) return MH_EWORKSPACE;
+
+    Arena ar(workspace, ws_bytes);
+    Counters* ctr = ar.take<Counters>(1);
+    NetBuffers B = carve_network(ar, n, weighted, T);
+    if (ar.overflow) return MH_EWORKSPACE;
+    const size_t off = (ar.used + 255) & ~size_t(255);
+    void* scratch = ar.base + off;
+    const size_t scratch_bytes = ws_bytes - off;
+
+    hipEvent_t* ev = plan ? plan->stage_events : nullptr;
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[0], stream));
+    mh_status st = init_counters(ctr, stream);
+    if (st != MH_OK || n == 0) return st;
+    st = prepare_network(x, y, B, &ctr->status, scratch, scratch_bytes, stream, ev);
+    if (st != MH_OK) return st;
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[2], stream));
+
+    SweepLaunch A{};
+    A.net = net_desc(B);
+    A.replica = replica;
+    A.key0 = (uint32_t)seed;
+    A.key1 = (uint32_t)(seed >> 32);
+    A.out = EdgeOut{src, dst, w, capacity, &ctr->n_edges};
+    A.sid = nullptr;
+    A.ctr = ctr;
+    const int32_t gb = plan ? plan->grid_blocks : 0;
+    if (weighted) {
+        if (stats) launch_sweep<true, true>(A, n, gb, stream);
+        else launch_sweep<true, false>(A, n, gb, stream);
+    } else {
+        if (stats) launch_sweep<false, true>(A, n, gb, stream);
+        else launch_sweep<false, false>(A, n, gb, stream);
+    }
+    MH_HIP_TRY(hipGetLastError());
+    if (ev) MH_HIP_TRY(hipEventRecord(ev[3], stream));
+    return MH_OK;
+}
+
+mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed, uint32_t replica,
+                      const mh_plan_params* plan, int32_t* src, int32_t* dst, int32_t* w, int64_t capacity,
+                      int64_t* n_edges_host, void* workspace, size_t ws_bytes, mh_stats* stats_host,
+                      hipStream_t stream) {
+    if (!n_edges_host) return MH_EINVAL;
+    *n_edges_host = 0;
+    if (stats_host) *stats_host = mh_stats{0, 0, 0, 0, 0, 0};
+    if (n == 0) return (n >= 0 && capacity >= 0) ? MH_OK : MH_EINVAL;
+    mh_status st = enqueue_sample(x, y, n, seed, replica, plan, src, dst, w, capacity, workspace, ws_bytes,
+                                  stats_host != nullptr, stream);
+    if (st != MH_OK) return st;
+    return read_counters(static_cast<const Counters*>(workspace), capacity, n_edges_host, stats_host, stream);
 }
 
 }  // namespace
@@ -608,6 +624,29 @@ mh_status mh_sample_weighted(const double* x, const double* y, int64_t n, uint64
     }
     return mh::sample_impl(x, y, n, seed, replica, plan, src, dst, w, capacity, n_edges_host, workspace, ws_bytes,
                            stats_host, stream);
+}
+
+mh_status mh_sample_unweighted_async(const double* x, int64_t n, uint64_t seed, uint32_t replica,
+                                     const mh_plan_params* plan, int32_t* src, int32_t* dst, int64_t capacity,
+                                     void* workspace, size_t ws_bytes, hipStream_t stream) {
+    return mh::enqueue_sample(x, nullptr, n, seed, replica, plan, src, dst, nullptr, capacity, workspace, ws_bytes,
+                              false, stream);
+}
+
+mh_status mh_sample_weighted_async(const double* x, const double* y, int64_t n, uint64_t seed, uint32_t replica,
+                                   const mh_plan_params* plan, int32_t* src, int32_t* dst, int32_t* w,
+                                   int64_t capacity, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    if (!y && n > 0) return MH_EINVAL;
+    return mh::enqueue_sample(x, y, n, seed, replica, plan, src, dst, w, capacity, workspace, ws_bytes, false,
+                              stream);
+}
+
+mh_status mh_sample_result(const void* workspace, size_t ws_bytes, int64_t capacity, int64_t* n_edges_host,
+                           hipStream_t stream) {
+    if (!n_edges_host || capacity < 0) return MH_EINVAL;
+    *n_edges_host = 0;
+    if (!workspace || ws_bytes < sizeof(mh::Counters)) return MH_EWORKSPACE;
+    return mh::read_counters(static_cast<const mh::Counters*>(workspace), capacity, n_edges_host, nullptr, stream);
 }
 
 size_t mh_plan_workspace_bytes(int64_t n) { return mh::plan_workspace_bytes_impl(n); }

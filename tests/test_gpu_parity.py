@@ -6,6 +6,8 @@ floating-point comparison within 1e-12 of its threshold (its near-tie trace),
 which could go either way with a 1-ulp difference between the host and device
 logarithms; such rows are excluded and counted (bound: 1 per 1e7 edges).
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -186,6 +188,37 @@ def test_capacity_retry_is_identical(mh):
     k1, _ = edge_keys(src.cpu().numpy(), dst.cpu().numpy(), len(x))
     k2, _ = edge_keys(src2.cpu().numpy(), dst2.cpu().numpy(), len(x))
     assert np.array_equal(k1, k2)
+
+
+def test_async_samples_match_sync(mh):
+    # back-to-back asynchronous samples on one stream: the last one read back
+    # equals the synchronous call (and the oracle)
+    x = workloads.cfg1_small(seed=3)
+    n = len(x)
+    xd = dev(x)
+    L = mh.lib()
+    plan = mh.PlanParams(16, 0, 0, 0, None)
+    ws = torch.empty(L.mh_workspace_bytes(n, 1, ctypes.byref(plan)), dtype=torch.uint8, device="cuda")
+    src = torch.empty(20_000, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for r in range(5):
+        mh.sample_async(xd, None, (src, dst), ws, seed=4, replica=r)
+    m = mh.sample_result(ws, src.numel())
+    ora = oracle.sample_mh(x, None, seed=4, replica=4, seg_work=16)
+    compare_edges((src[:m], dst[:m]), ora, n, ora.tie_rows)
+    rng = np.random.default_rng(5)
+    y = rng.uniform(0.1, 0.9, n)
+    w = torch.empty_like(src)
+    mh.sample_async(xd, dev(y), (src, dst, w), ws, seed=6, replica=2)
+    m = mh.sample_result(ws, src.numel())
+    ora = oracle.sample_mh(x, y, seed=6, replica=2, seg_work=16)
+    compare_edges((src[:m], dst[:m], w[:m]), ora, n, ora.tie_rows, weighted=True)
+    # too small an output: the sample's own count comes back with MH_ECAPACITY
+    small = (src[:10], dst[:10])
+    mh.sample_async(xd, None, small, ws, seed=4, replica=4)
+    with pytest.raises(mh.MHError) as ei:
+        mh.sample_result(ws, 10)
+    assert ei.value.status == mh.MH_ECAPACITY
 
 
 @pytest.mark.parametrize("bad", ["nan", "neg", "inf", "overflow", "y"])
