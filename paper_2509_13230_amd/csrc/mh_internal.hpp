@@ -65,13 +65,12 @@ mh_status scan_exclusive_u64(const uint64_t* in, uint64_t* out, int64_t n, void*
 mh_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void* ws, size_t ws_bytes,
                              hipStream_t stream);
 
-// Single-kernel variant (decoupled look-back) for sums below 2^62.  state:
-// scan_onepass_state_words(n) u64 words, all zero at launch (a caller zeroes
-// them in an earlier kernel); err (device, not null) receives MH_EHIP if a
-// look-back stalls.
-int64_t scan_onepass_state_words(int64_t n);
-mh_status scan_exclusive_u64_onepass(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* state, int32_t* err,
-                                     hipStream_t stream);
+// Single-kernel variant (decoupled look-back, mh_lookback.hpp) for sums below
+// 2^62; state: lb_tiles(n) u64 words, zero at launch (zeroed by an earlier
+// kernel); samples (optional, lb_samples(n) words): out[256 k]; err (device,
+// not null) receives MH_EHIP if a look-back stalls.
+mh_status scan_exclusive_u64_onepass(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* state,
+                                     uint64_t* samples, int32_t* err, hipStream_t stream);
 
 // ---- radix sort of (key, value) pairs ascending by key, stable ----
 // Copies of the digit histograms: enough that no address takes more than a few
@@ -103,14 +102,19 @@ struct SortedView {
 
 size_t order_workspace_bytes(int64_t n);
 // Writes the order either as packed records (node != null: z and id; nseg is
-// left for the plan) or as separate perm / zs arrays.  check_square: the
-// largest z squared must be finite (one node set, where it is the largest t).
-// extra_zero / extra_words: u64 words zeroed on the way (look-back state of
-// later steps).
+// left for the plan) or as separate perm / zs arrays.  mass_prefix (optional,
+// n + 1 entries): P[r] = sum of the column masses floor(z 2^32) (2^32 for
+// z >= 1) over ranks < r, P[n] = total; with node records this is computed in
+// the same pass, with the look-back state mass_state (lb_tiles(n) words that
+// must be zero when this call's first kernel has run: pass them inside
+// extra_zero), and then mass_samples (optional, lb_samples(n) words) receives
+// P[256 k].  check_square: the largest z squared must be finite (one node
+// set, where it is the largest t).  extra_zero / extra_words: u64 words zeroed
+// by the first kernel (look-back state of later steps).
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
-                      NodeRec* node, int32_t* status, uint64_t* mass_out, void* ws, size_t ws_bytes,
-                      hipStream_t stream, bool check_square = true, uint64_t* extra_zero = nullptr,
-                      int64_t extra_words = 0);
+                      NodeRec* node, int32_t* status, uint64_t* mass_prefix, uint64_t* mass_state,
+                      uint64_t* mass_samples, void* ws, size_t ws_bytes, hipStream_t stream,
+                      bool check_square = true, uint64_t* extra_zero = nullptr, int64_t extra_words = 0);
 
 size_t bound_workspace_bytes(int64_t n);
 mh_status bound_suffix_top2(const double* ys, int64_t n, double* c, int32_t* status, void* ws, size_t ws_bytes,

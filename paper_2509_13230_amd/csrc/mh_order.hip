@@ -3,6 +3,7 @@
 // (product of the two largest y among the ranks not yet processed).
 #include "mh_common.hpp"
 #include "mh_internal.hpp"
+#include "mh_lookback.hpp"
 #include "mh_sweep_core.hpp"
 
 namespace mh {
@@ -112,6 +113,54 @@ __global__ __launch_bounds__(kThreads) void k_finish_order(const uint64_t* __res
     if (ys) ys[r] = y[id];
     if (mass) mass[r] = mass_q(z);
     if (check_square && r == 0 && !isfinite(z * z)) raise_status(status, MH_EINVAL);
+}
+
+// The same, into node records, with the column masses scanned on the way:
+// P[r] = sum of floor(z 2^32) over ranks < r, P[n] = total (tiles of 4096
+// ranks, look-back state zero at launch).
+__global__ __launch_bounds__(kLbThreads) void k_finish_order_scan(const uint64_t* __restrict__ keys,
+                                                                  const uint32_t* __restrict__ vals, int64_t n,
+                                                                  NodeRec* __restrict__ node,
+                                                                  const double* __restrict__ y,
+                                                                  double* __restrict__ ys, uint64_t* __restrict__ P,
+                                                                  int64_t tiles, uint64_t* state,
+                                                                  uint64_t* samples, int32_t check_square,
+                                                                  int32_t* status) {
+    __shared__ LbShared sh;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t base = tile * kLbTile;
+#pragma unroll 4
+        for (int k = 0; k < kLbItems; ++k) {
+            const int idx = k * kLbThreads + threadIdx.x;
+            const int64_t r = base + idx;
+            uint64_t m = 0;
+            if (r < n) {
+                const uint32_t id = vals[r];
+                const double z = key_value(keys[r]);
+                node[r].z = z;
+                node[r].id = (int32_t)id;
+                if (ys) ys[r] = y[id];
+                m = mass_q(z);
+                if (check_square && r == 0 && !isfinite(z * z)) raise_status(status, MH_EINVAL);
+            }
+            sh.items[lb_at(idx)] = m;
+        }
+        const uint64_t end = lb_tile_scan(sh, tile, state, status);
+#pragma unroll
+        for (int k = 0; k < kLbItems; ++k) {
+            const int idx = k * kLbThreads + threadIdx.x;
+            const int64_t r = base + idx;
+            if (r < n) {
+                const uint64_t v = sh.items[lb_at(idx)];
+                P[r] = v;
+                if (samples && (r & ((1 << kSampleShift) - 1)) == 0) samples[r >> kSampleShift] = v;
+            }
+        }
+        if (threadIdx.x == 0 && base + kLbTile >= n) {
+            P[n] = end;
+            if (samples && (n & ((1 << kSampleShift) - 1)) == 0) samples[n >> kSampleShift] = end;
+        }
+    }
 }
 
 // ---- suffix top-2 of ys: the monoid keeps the two largest values (multiset) ----
@@ -248,8 +297,9 @@ size_t order_workspace_bytes(int64_t n) {
 }
 
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
-                      NodeRec* node, int32_t* status, uint64_t* mass_out, void* ws, size_t ws_bytes,
-                      hipStream_t stream, bool check_square, uint64_t* extra_zero, int64_t extra_words) {
+                      NodeRec* node, int32_t* status, uint64_t* mass_prefix, uint64_t* mass_state,
+                      uint64_t* mass_samples, void* ws, size_t ws_bytes, hipStream_t stream, bool check_square,
+                      uint64_t* extra_zero, int64_t extra_words) {
     if (n <= 0) return MH_OK;
     Arena ar(ws, ws_bytes);
     uint64_t* keys = ar.take<uint64_t>(n);
@@ -268,10 +318,22 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
     MH_HIP_TRY(hipGetLastError());
     st = radix_sort_u64(keys, vals, keys_alt, vals_alt, n, sort_ws, sort_bytes, true, status, stream);
     if (st != MH_OK) return st;
+    if (mass_prefix && node && n <= (int64_t)1 << 30) {
+        // records and the masses' prefix sums in one pass (sums stay below 2^62)
+        const int64_t tiles = lb_tiles(n);
+        const int64_t resident = resident_blocks(k_finish_order_scan, kLbThreads);
+        const int64_t grid = tiles < resident ? tiles : resident;
+        hipLaunchKernelGGL(k_finish_order_scan, dim3((unsigned)grid), dim3(kLbThreads), 0, stream,
+                           (const uint64_t*)keys, (const uint32_t*)vals, n, node, y, y ? ys : nullptr, mass_prefix,
+                           tiles, mass_state, mass_samples, (int32_t)check_square, status);
+        MH_HIP_TRY(hipGetLastError());
+        return MH_OK;
+    }
     const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_finish_order, dim3(grid), dim3(kThreads), 0, stream, keys, vals, n, perm, zs, node, y,
-                       y ? ys : nullptr, mass_out, (int32_t)check_square, status);
+                       y ? ys : nullptr, mass_prefix, (int32_t)check_square, status);
     MH_HIP_TRY(hipGetLastError());
+    if (mass_prefix) return scan_exclusive_u64(mass_prefix, mass_prefix, n, ws, ws_bytes, stream);
     return MH_OK;
 }
 

@@ -4,6 +4,7 @@
 // is the total; in == out is allowed (each tile is read before it is written).
 #include "mh_common.hpp"
 #include "mh_internal.hpp"
+#include "mh_lookback.hpp"
 
 namespace mh {
 
@@ -122,98 +123,33 @@ mh_status scan_impl(const T* in, T* out, int64_t n, Arena& ar, hipStream_t strea
 }
 
 // ---- single pass: one kernel, decoupled look-back over tiles ----
-constexpr int kOneItems = 16;
-constexpr int kOneTile = kScanThreads * kOneItems;  // 4096
-constexpr uint32_t kOneSpinLimit = 1u << 20;
-// Look-back word per tile, zero at launch: the flag in the top two bits (1 = the
-// tile's own sum, 2 = the inclusive prefix through the tile) and the value in
-// the low 62.  Flag and value travel in one relaxed atomic, so no fence is
-// needed between them.  Prefix sums must stay below 2^62 (the caller checks).
-constexpr uint64_t kOneAgg = 1ull << 62;
-constexpr uint64_t kOneInc = 2ull << 62;
-constexpr uint64_t kOneValue = kOneAgg - 1;
-
-// Blocks take tiles blockIdx, blockIdx + gridDim, ... with the whole grid
-// resident, so a tile waits only on lower tiles that are being processed.
-__global__ __launch_bounds__(kScanThreads) void k_scan_onepass(const uint64_t* in, uint64_t* out, int64_t n,
-                                                               int64_t tiles, uint64_t* state, int32_t* err) {
-    __shared__ uint64_t lds_items[kOneTile];
-    __shared__ uint64_t lds_waves[kScanThreads / kWave];
-    __shared__ uint64_t s_excl;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+__global__ __launch_bounds__(kLbThreads) void k_scan_onepass(const uint64_t* in, uint64_t* out, int64_t n,
+                                                             int64_t tiles, uint64_t* state, uint64_t* samples,
+                                                             int32_t* err) {
+    __shared__ LbShared sh;
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        const int64_t base = tile * kOneTile;
+        const int64_t base = tile * kLbTile;
 #pragma unroll
-        for (int k = 0; k < kOneItems; ++k) {
-            const int idx = k * kScanThreads + threadIdx.x;
+        for (int k = 0; k < kLbItems; ++k) {
+            const int idx = k * kLbThreads + threadIdx.x;
             const int64_t i = base + idx;
-            lds_items[idx] = (i < n) ? in[i] : 0ull;
+            sh.items[lb_at(idx)] = (i < n) ? in[i] : 0ull;
         }
-        __syncthreads();
-        uint64_t vals[kOneItems];
-        uint64_t run = 0;
+        const uint64_t end = lb_tile_scan(sh, tile, state, err);
 #pragma unroll
-        for (int k = 0; k < kOneItems; ++k) {
-            vals[k] = lds_items[threadIdx.x * kOneItems + k];
-            run += vals[k];
-        }
-        uint64_t total;
-        const uint64_t before = block_exclusive_scan(run, lds_waves, &total);
-        if (threadIdx.x == 0) {
-            __hip_atomic_store(&state[tile], (tile == 0 ? kOneInc : kOneAgg) | total, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            if (tile == 0) s_excl = 0;
-        }
-        if (wave == 0 && tile > 0) {
-            // lane l looks at tile t - l; sum published sums back to the
-            // nearest inclusive prefix, re-polling where a tile is not yet out
-            uint64_t excl = 0;
-            int64_t t = tile - 1;
-            uint32_t spins = 0;
-            for (;;) {
-                const int64_t tt = t - lane;
-                const uint64_t w =
-                    (tt >= 0) ? __hip_atomic_load(&state[tt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kOneInc;
-                const uint64_t f = w & ~kOneValue;
-                const uint64_t none = __ballot(f == 0);
-                const uint64_t incl = __ballot(f == kOneInc);
-                const int first_none = none ? (int)__ffsll((unsigned long long)none) - 1 : kWave;
-                const int first_incl = incl ? (int)__ffsll((unsigned long long)incl) - 1 : kWave;
-                const bool finish = first_incl < first_none;
-                const int used = finish ? first_incl + 1 : first_none;
-                excl += wave_sum(lane < used ? (w & kOneValue) : 0ull);
-                if (finish) break;
-                t -= used;
-                if (used == 0) {
-                    if (++spins > kOneSpinLimit) {
-                        raise_status(err, MH_EHIP);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            if (lane == 0) {
-                __hip_atomic_store(&state[tile], kOneInc | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_excl = excl;
+        for (int k = 0; k < kLbItems; ++k) {
+            const int idx = k * kLbThreads + threadIdx.x;
+            const int64_t i = base + idx;
+            if (i < n) {
+                const uint64_t v = sh.items[lb_at(idx)];
+                out[i] = v;
+                if (samples && (i & ((1 << kSampleShift) - 1)) == 0) samples[i >> kSampleShift] = v;
             }
         }
-        __syncthreads();
-        uint64_t acc = s_excl + before;
-#pragma unroll
-        for (int k = 0; k < kOneItems; ++k) {
-            lds_items[threadIdx.x * kOneItems + k] = acc;
-            acc += vals[k];
+        if (threadIdx.x == 0 && base + kLbTile >= n) {
+            out[n] = end;
+            if (samples && (n & ((1 << kSampleShift) - 1)) == 0) samples[n >> kSampleShift] = end;
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kOneItems; ++k) {
-            const int idx = k * kScanThreads + threadIdx.x;
-            const int64_t i = base + idx;
-            if (i < n) out[i] = lds_items[idx];
-        }
-        if (threadIdx.x == 0 && base + kOneTile >= n) out[n] = s_excl + total;
-        __syncthreads();  // the next tile reuses the LDS
     }
 }
 
@@ -221,16 +157,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(const uint64_t* i
 
 size_t scan_workspace_bytes(int64_t n) { return levels_bytes<uint64_t>(n); }
 
-int64_t scan_onepass_state_words(int64_t n) { return n > 0 ? (n + kOneTile - 1) / kOneTile : 1; }
-
-mh_status scan_exclusive_u64_onepass(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* state, int32_t* err,
-                                     hipStream_t stream) {
+mh_status scan_exclusive_u64_onepass(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* state,
+                                     uint64_t* samples, int32_t* err, hipStream_t stream) {
     if (n < 0) return MH_EINVAL;
-    const int64_t tiles = scan_onepass_state_words(n);
-    const int64_t resident = resident_blocks(k_scan_onepass, kScanThreads);
+    const int64_t tiles = lb_tiles(n);
+    const int64_t resident = resident_blocks(k_scan_onepass, kLbThreads);
     const int64_t grid = tiles < resident ? tiles : resident;
-    hipLaunchKernelGGL(k_scan_onepass, dim3((unsigned)grid), dim3(kScanThreads), 0, stream, in, out, n, tiles, state,
-                       err);
+    hipLaunchKernelGGL(k_scan_onepass, dim3((unsigned)grid), dim3(kLbThreads), 0, stream, in, out, n, tiles, state,
+                       samples, err);
     MH_HIP_TRY(hipGetLastError());
     return MH_OK;
 }

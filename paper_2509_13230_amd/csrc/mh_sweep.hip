@@ -3,6 +3,7 @@
 // in mh_sweep_core.hpp).
 #include "mh_common.hpp"
 #include "mh_internal.hpp"
+#include "mh_lookback.hpp"
 #include "mh_stage.hpp"
 #include "mh_sweep_core.hpp"
 #include "mh_prepare.hpp"
@@ -45,13 +46,10 @@ __global__ void k_init_counters(Counters* c) {
 // s z_j >= c_r, cut every T columns; sparse part: [J, nc) cut where the column
 // mass (prefix sums P of floor(z 2^32)) reaches multiples of
 // m = floor(T c_r / s 2^32), the mass whose expected candidate count is ~T.
-__global__ __launch_bounds__(kThreads) void k_row_plan(NodeRec* __restrict__ node, const double* __restrict__ c,
-                                                       int64_t n, const NodeRec* __restrict__ col, int64_t nc,
-                                                       int32_t bip, int32_t T, const uint64_t* __restrict__ P,
-                                                       int32_t* __restrict__ jend,
-                                                       uint64_t* __restrict__ mq, uint64_t* __restrict__ hn) {
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n) return;
+__device__ inline int64_t row_plan_one(NodeRec* __restrict__ node, const double* __restrict__ c,
+                                       const NodeRec* __restrict__ col, int64_t nc, int32_t bip, int32_t T,
+                                       const uint64_t* __restrict__ P, int32_t* __restrict__ jend,
+                                       uint64_t* __restrict__ mq, int64_t r) {
     int64_t total = 0;
     const double s = node[r].z;
     const int64_t first = bip ? 0 : r + 1;
@@ -86,27 +84,144 @@ __global__ __launch_bounds__(kThreads) void k_row_plan(NodeRec* __restrict__ nod
         }
     }
     node[r].nseg = total > 0x7FFFFFFF ? 0x7FFFFFFF : (int32_t)total;
+    return total;
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_plan(NodeRec* __restrict__ node, const double* __restrict__ c,
+                                                       int64_t n, const NodeRec* __restrict__ col, int64_t nc,
+                                                       int32_t bip, int32_t T, const uint64_t* __restrict__ P,
+                                                       int32_t* __restrict__ jend,
+                                                       uint64_t* __restrict__ mq, uint64_t* __restrict__ hn) {
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    const int64_t total = row_plan_one(node, c, col, nc, bip, T, P, jend, mq, r);
     if (hn) hn[r] = total >= 2 ? (uint64_t)total : 0ull;
 }
 
-__global__ __launch_bounds__(kThreads) void k_heavy_records(NetDesc D, HeavyRec* __restrict__ rec,
+// Records {row, segment, column range} of the first rec_cap heavy items, the
+// same as heavy_record() computes them.  Hsamp / Psamp (null: plain searches)
+// hold hoff[256 k] and P[256 k]; a block stages them in LDS (every step-th one
+// when there are more than kHrSamples), so each search takes its bracket from
+// LDS and ends with a short binary search in global memory.
+constexpr int kHrSamples = 4096;
+constexpr int kHrThreads = 1024;  // items per block round; a grid of one round per item
+
+__device__ __forceinline__ int64_t first_above_u64(const uint64_t* __restrict__ a, int64_t lo, int64_t hi, uint64_t v) {
+    while (lo < hi) {  // first index in [lo, hi) with a[i] > v (hi if none)
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] > v) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kHrThreads) void k_heavy_records(NetDesc D, HeavyRec* __restrict__ rec,
+                                                            const uint64_t* __restrict__ Hsamp,
+                                                            const uint64_t* __restrict__ Psamp,
                                                             const int32_t* status) {
+    __shared__ uint64_t s_h[kHrSamples];
+    __shared__ uint64_t s_p[kHrSamples];
     if (*status != 0) return;
     const int64_t H = heavy_items(D);
     const int64_t lim = H < D.rec_cap ? H : D.rec_cap;
-    for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < lim; it += (int64_t)gridDim.x * kThreads)
-        rec[it] = heavy_record(D, it);
+    if ((int64_t)blockIdx.x * kHrThreads >= lim) return;  // the grid is sized for rec_cap items
+    if (!Hsamp || !Psamp) {
+        for (int64_t it = (int64_t)blockIdx.x * kHrThreads + threadIdx.x; it < lim;
+             it += (int64_t)gridDim.x * kHrThreads)
+            rec[it] = heavy_record(D, it);
+        return;
+    }
+    const int64_t n = D.n, nc = D.ncol, T = D.T;
+    const bool bip = (D.flags & NET_BIPARTITE) != 0;
+    // sample strides hs, ps (multiples of 256 rows / columns) and counts
+    int64_t hstep = 1, pstep = 1;
+    while (lb_samples(n) > hstep * (kHrSamples - 1) + 1) hstep *= 2;
+    while (lb_samples(nc) > pstep * (kHrSamples - 1) + 1) pstep *= 2;
+    const int64_t nh = (lb_samples(n) - 1) / hstep + 1, np = (lb_samples(nc) - 1) / pstep + 1;
+    const int64_t hs = hstep << kSampleShift, ps = pstep << kSampleShift;
+    for (int64_t j = threadIdx.x; j < nh; j += kHrThreads) s_h[j] = Hsamp[j * hstep];
+    for (int64_t j = threadIdx.x; j < np; j += kHrThreads) s_p[j] = Psamp[j * pstep];
+    __syncthreads();
+    for (int64_t it = (int64_t)blockIdx.x * kHrThreads + threadIdx.x; it < lim;
+         it += (int64_t)gridDim.x * kHrThreads) {
+        // row: first index with hoff > it, minus one; hoff[(q-1) hs] <= it < hoff[q hs]
+        int lo = 1, hi = (int)nh;  // first sample > it (s_h[0] = 0 <= it)
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_h[mid] > (uint64_t)it) hi = mid; else lo = mid + 1;
+        }
+        const int64_t glo = (int64_t)(lo - 1) * hs + 1;
+        const int64_t ghi = lo < (int)nh ? (int64_t)lo * hs : n;
+        const int64_t r = first_above_u64(D.hoff, glo, ghi, (uint64_t)it) - 1;
+        const int64_t g = it - (int64_t)D.hoff[r];
+        const int64_t nsg = (int64_t)(D.hoff[r + 1] - D.hoff[r]);
+        const int64_t J = D.jend[r];
+        const int64_t first = bip ? 0 : r + 1;
+        const int64_t nd = (J - first + T - 1) / T;
+        int64_t a, b;
+        if (g < nd) {
+            a = first + g * T;
+            b = a + T < J ? a + T : J;
+        } else {
+            const int64_t kk = g - nd;
+            const int64_t ns = nsg - nd;
+            const uint64_t pb = D.P[J];
+            const uint64_t m = D.mq[r];
+            int64_t cut[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int64_t k2 = kk + e;
+                if ((e == 0 && k2 == 0) || (e == 1 && k2 == ns)) {
+                    cut[e] = (e == 0) ? J : nc;
+                    continue;
+                }
+                // first j in [J, nc) with P[j] >= v (nc if none); P[(q-1) ps] < v <= P[q ps]
+                const uint64_t v = pb + (uint64_t)k2 * m;
+                int ql = 0, qh = (int)np;
+                while (ql < qh) {
+                    const int mid = (ql + qh) >> 1;
+                    if (s_p[mid] >= v) qh = mid; else ql = mid + 1;
+                }
+                int64_t clo = J, chi = nc;
+                if (ql > 0 && (int64_t)(ql - 1) * ps + 1 > clo) clo = (int64_t)(ql - 1) * ps + 1;
+                if (ql < (int)np && (int64_t)ql * ps < chi) chi = (int64_t)ql * ps;
+                if (clo > nc) clo = nc;
+                if (chi < clo) chi = clo;
+                cut[e] = lower_bound_u64(D.P, clo, chi, v);
+            }
+            a = cut[0];
+            b = cut[1];
+        }
+        rec[it] = HeavyRec{(int32_t)r, (int32_t)g, (int32_t)a, (int32_t)b};
+    }
 }
 
 }  // namespace
 
-// Exclusive scan of a plan array in place: one kernel (look-back) while its
-// sums stay below 2^62, which holds for up to 2^30 entries (masses are at most
-// 2^32 each; segment counts are far smaller); three kernels beyond.
-static mh_status plan_scan(uint64_t* a, int64_t n, uint64_t* state, int32_t* status, void* scratch,
+// Blocks for the heavy records: one item per thread, up to 4 blocks per CU
+// (the item count is known only on the device; rec_cap bounds it).
+static unsigned heavy_grid(int64_t rec_cap) {
+    const int64_t want = (rec_cap + kHrThreads - 1) / kHrThreads;
+    const int64_t cap = 4 * (int64_t)device_cus();
+    return (unsigned)(want < 1 ? 1 : (want < cap ? want : cap));
+}
+
+// A3: segment counts of every row (and J, m) and, when segmented, the prefix
+// sums hoff of the heavy rows' counts (one look-back kernel while the sums stay
+// below 2^62, which holds for up to 2^30 rows; three kernels beyond).  The row
+// plan itself runs one row per thread: hub rows binary-search their dense end,
+// and a thread working through many rows would serialize those searches.
+static mh_status plan_rows(NodeRec* node, const double* c, int64_t n, const NodeRec* col, int64_t nc, int32_t bip,
+                           int32_t T, const uint64_t* P, int32_t* jend, uint64_t* mq, uint64_t* hoff,
+                           uint64_t* hoff_state, uint64_t* hoff_samples, int32_t* status, void* scratch,
                            size_t scratch_bytes, hipStream_t stream) {
-    if (n <= (int64_t)1 << 30) return scan_exclusive_u64_onepass(a, a, n, state, status, stream);
-    return scan_exclusive_u64(a, a, n, scratch, scratch_bytes, stream);
+    const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_row_plan, dim3(grid), dim3(kThreads), 0, stream, node, c, n, col, nc, bip, T, P, jend, mq,
+                       hoff);
+    MH_HIP_TRY(hipGetLastError());
+    if (!hoff) return MH_OK;
+    if (n <= (int64_t)1 << 30)
+        return scan_exclusive_u64_onepass(hoff, hoff, n, hoff_state, hoff_samples, status, stream);
+    return scan_exclusive_u64(hoff, hoff, n, scratch, scratch_bytes, stream);
 }
 
 // ---- one prepared network: buffers, sizes and preparation ----
@@ -123,10 +238,14 @@ static NetBuffers carve_network_impl(A& ar, int64_t n, bool weighted, int32_t T)
     B.hoff = ar.template take<uint64_t>(seg ? n + 1 : 0);
     B.rec_cap = seg ? n + 4096 : 0;  // records for up to this many heavy items; more are located in the sweep
     B.rec = ar.template take<HeavyRec>(B.rec_cap);
-    B.scan_words = seg ? 2 * scan_onepass_state_words(n) : 0;
+    B.scan_words = seg ? 2 * lb_tiles(n) : 0;
     B.scan_state = ar.template take<uint64_t>(B.scan_words);
+    B.Psamp = ar.template take<uint64_t>(seg ? lb_samples(n) : 0);
+    B.Hsamp = ar.template take<uint64_t>(seg ? lb_samples(n) : 0);
     if (!weighted) B.ys = B.c = nullptr;
-    if (!seg) B.P = nullptr, B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.scan_state = nullptr;
+    if (!seg)
+        B.P = nullptr, B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.scan_state = nullptr, B.Psamp = nullptr,
+        B.Hsamp = nullptr;
     B.n = n;
     B.T = T;
     B.weighted = weighted;
@@ -196,26 +315,23 @@ mh_status prepare_network(const double* x, const double* y, const NetBuffers& B,
     if (n <= 0) return MH_OK;
     const bool seg = B.T > 0;
     mh_status st = order_nodes(x, B.weighted ? y : nullptr, n, nullptr, nullptr, B.ys, B.node, status, B.P,
-                               scratch, scratch_bytes, stream, true, B.scan_state, B.scan_words);
+                               B.scan_state, B.Psamp, scratch, scratch_bytes, stream, true, B.scan_state,
+                               B.scan_words);
     if (st != MH_OK) return st;
     if (ev) MH_HIP_TRY(hipEventRecord(ev[1], stream));
     if (B.weighted) {
         st = bound_suffix_top2(B.ys, n, B.c, status, scratch, scratch_bytes, stream);
         if (st != MH_OK) return st;
     }
+    st = plan_rows(B.node, B.c, n, B.node, n, 0, B.T, B.P, B.jend, B.mq, B.hoff,
+                   seg ? B.scan_state + lb_tiles(n) : nullptr, B.Hsamp, status, scratch, scratch_bytes, stream);
+    if (st != MH_OK) return st;
     if (seg) {
-        st = plan_scan(B.P, n, B.scan_state, status, scratch, scratch_bytes, stream);
-        if (st != MH_OK) return st;
-    }
-    const unsigned rows_grid = (unsigned)((n + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_row_plan, dim3(rows_grid), dim3(kThreads), 0, stream, B.node, (const double*)B.c, n,
-                       (const NodeRec*)B.node, n, 0, B.T, (const uint64_t*)B.P, B.jend, B.mq, B.hoff);
-    MH_HIP_TRY(hipGetLastError());
-    if (seg) {
-        st = plan_scan(B.hoff, n, B.scan_state + scan_onepass_state_words(n), status, scratch, scratch_bytes, stream);
-        if (st != MH_OK) return st;
-        hipLaunchKernelGGL(k_heavy_records, dim3(512), dim3(kThreads), 0, stream, net_desc(B), B.rec,
-                           (const int32_t*)status);
+        const bool samples = n <= (int64_t)1 << 30;  // written by the one-pass scans
+        hipLaunchKernelGGL(k_heavy_records, dim3(heavy_grid(B.rec_cap)), dim3(kHrThreads), 0, stream, net_desc(B),
+                           B.rec,
+                           (const uint64_t*)(samples ? B.Hsamp : nullptr),
+                           (const uint64_t*)(samples ? B.Psamp : nullptr), (const int32_t*)status);
         MH_HIP_TRY(hipGetLastError());
     }
     return MH_OK;
@@ -428,6 +544,8 @@ struct BipBuffers {
     unsigned long long* ymax;
     uint64_t* scan_state;  // look-back state: P scan over the columns, then hoff over the rows
     int64_t scan_words;
+    uint64_t* Psamp;  // P[256 k] over the columns, hoff[256 k] over the rows
+    uint64_t* Hsamp;
 };
 
 template <typename A>
@@ -446,10 +564,14 @@ BipBuffers carve_bipartite(A& ar, int64_t nr, int64_t nc, bool weighted, int32_t
     B.ysc = ar.template take<double>(weighted ? nc : 0);
     B.P = ar.template take<uint64_t>(seg ? nc + 1 : 0);
     B.ymax = ar.template take<unsigned long long>(1);
-    B.scan_words = seg ? scan_onepass_state_words(nc) + scan_onepass_state_words(nr) : 0;
+    B.scan_words = seg ? lb_tiles(nc) + lb_tiles(nr) : 0;
     B.scan_state = ar.template take<uint64_t>(B.scan_words);
+    B.Psamp = ar.template take<uint64_t>(seg ? lb_samples(nc) : 0);
+    B.Hsamp = ar.template take<uint64_t>(seg ? lb_samples(nr) : 0);
     if (!weighted) B.ysr = B.c = B.ysc = nullptr;
-    if (!seg) B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.P = nullptr, B.scan_state = nullptr;
+    if (!seg)
+        B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.P = nullptr, B.scan_state = nullptr, B.Psamp = nullptr,
+        B.Hsamp = nullptr;
     return B;
 }
 
@@ -517,11 +639,12 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
     mh_status st = init_counters(ctr, stream);
     if (st != MH_OK) return st;
     // A1: each set sorted by its own z; the column masses for the plan
-    st = order_nodes(xr, yr, nr, nullptr, nullptr, B.ysr, B.rows, status, nullptr, scratch, scratch_bytes, stream,
-                     false, B.scan_state, B.scan_words);
+    // (the rows' first kernel zeroes the look-back state of both plan scans)
+    st = order_nodes(xr, yr, nr, nullptr, nullptr, B.ysr, B.rows, status, nullptr, nullptr, nullptr, scratch,
+                     scratch_bytes, stream, false, B.scan_state, B.scan_words);
     if (st != MH_OK) return st;
-    st = order_nodes(xc, yc, nc, nullptr, nullptr, B.ysc, B.cols, status, B.P, scratch, scratch_bytes, stream,
-                     false);
+    st = order_nodes(xc, yc, nc, nullptr, nullptr, B.ysc, B.cols, status, B.P, B.scan_state, B.Psamp, scratch,
+                     scratch_bytes, stream, false);
     if (st != MH_OK) return st;
     if (ev) MH_HIP_TRY(hipEventRecord(ev[1], stream));
     // A2: row bounds and the joint checks
@@ -540,19 +663,15 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
                        (const unsigned long long*)B.ymax, B.c, status);
     MH_HIP_TRY(hipGetLastError());
     // A3: plan over the columns
-    if (seg) {
-        st = plan_scan(B.P, nc, B.scan_state, status, scratch, scratch_bytes, stream);
-        if (st != MH_OK) return st;
-    }
-    hipLaunchKernelGGL(k_row_plan, dim3(rows_grid), dim3(kThreads), 0, stream, B.rows, (const double*)B.c, nr,
-                       (const NodeRec*)B.cols, nc, 1, T, (const uint64_t*)B.P, B.jend, B.mq, B.hoff);
-    MH_HIP_TRY(hipGetLastError());
+    st = plan_rows(B.rows, B.c, nr, B.cols, nc, 1, T, B.P, B.jend, B.mq, B.hoff,
+                   seg ? B.scan_state + lb_tiles(nc) : nullptr, B.Hsamp, status, scratch, scratch_bytes, stream);
+    if (st != MH_OK) return st;
     const NetDesc D = bip_desc(B, nr, nc, T, flags);
     if (seg) {
-        st = plan_scan(B.hoff, nr, B.scan_state + scan_onepass_state_words(nc), status, scratch, scratch_bytes,
-                       stream);
-        if (st != MH_OK) return st;
-        hipLaunchKernelGGL(k_heavy_records, dim3(512), dim3(kThreads), 0, stream, D, B.rec, (const int32_t*)status);
+        const bool samples = nr <= (int64_t)1 << 30 && nc <= (int64_t)1 << 30;  // written by the one-pass scans
+        hipLaunchKernelGGL(k_heavy_records, dim3(heavy_grid(B.rec_cap)), dim3(kHrThreads), 0, stream, D, B.rec,
+                           (const uint64_t*)(samples ? B.Hsamp : nullptr),
+                           (const uint64_t*)(samples ? B.Psamp : nullptr), (const int32_t*)status);
         MH_HIP_TRY(hipGetLastError());
     }
     if (ev) MH_HIP_TRY(hipEventRecord(ev[2], stream));
