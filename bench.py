@@ -181,7 +181,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--seg-work", type=int, default=16)
+    ap.add_argument("--seg-work", type=int, default=8)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--grid-blocks", type=int, default=0, help="sweep grid (0 = all resident blocks)")
     ap.add_argument("--seed", type=int, default=1)

@@ -86,7 +86,7 @@ size_t mh_workspace_bytes(int64_t n, int weighted, const mh_plan_params* plan);
  *   x[n]          parameters, device, float64.
  *   seed, replica Philox key and counter word: different replicas are
  *                 independent samples.
- *   plan          NULL = {seg_work = 16, grid_blocks = 0}.
+ *   plan          NULL = {seg_work = 8, grid_blocks = 0}.
  *   src, dst      device int32[capacity]: edge endpoints (src has the larger
  *                 x; each undirected edge once, no self-loops; order
  *                 unspecified).

@@ -28,7 +28,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmh.so")
 
-DEFAULT_SEG_WORK = 16
+DEFAULT_SEG_WORK = 8
 
 MH_OK, MH_EINVAL, MH_ECAPACITY, MH_EHIP, MH_EWORKSPACE = 0, -1, -2, -3, -4
 

@@ -10,6 +10,10 @@
 
 namespace mh {
 
+// seg_work when no plan is given: the measured optimum on N = 1e6 power-law
+// networks (whole sample, sweep and plan together)
+constexpr int32_t kDefaultSegWork = 8;
+
 namespace {
 
 constexpr int kThreads = kSweepThreads;
@@ -393,7 +397,7 @@ mh_status enqueue_sample(const double* x, const double* y, int64_t n, uint64_t s
     if (n < 0 || n > 0x7FFFFFFFll || capacity < 0) return MH_EINVAL;
     if (!x && n > 0) return MH_EINVAL;
     if (capacity > 0 && (!src || !dst || (weighted && !w))) return MH_EINVAL;
-    const int32_t T = plan ? plan->seg_work : 16;
+    const int32_t T = plan ? plan->seg_work : kDefaultSegWork;
     if (T < 0 || (plan && (plan->flags != 0 || plan->grid_blocks < 0))) return MH_EINVAL;
     if (!workspace || ws_bytes < sample_workspace_bytes(n, weighted, T)) return MH_EWORKSPACE;
 
@@ -617,7 +621,7 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
     if ((yr == nullptr) != (yc == nullptr) || (flags & ~MH_BIP_NO_SELF) != 0) return MH_EINVAL;
     if ((!xr && nr > 0) || (!xc && nc > 0)) return MH_EINVAL;
     if (capacity > 0 && (!src || !dst || (weighted && !w))) return MH_EINVAL;
-    const int32_t T = plan ? plan->seg_work : 16;
+    const int32_t T = plan ? plan->seg_work : kDefaultSegWork;
     if (T < 0 || (plan && (plan->flags != 0 || plan->grid_blocks < 0))) return MH_EINVAL;
     *n_edges_host = 0;
     if (stats_host) *stats_host = mh_stats{0, 0, 0, 0, 0, 0};
@@ -719,7 +723,7 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
 extern "C" {
 
 size_t mh_workspace_bytes(int64_t n, int weighted, const mh_plan_params* plan) {
-    return mh::sample_workspace_bytes(n, weighted != 0, plan ? plan->seg_work : 16);
+    return mh::sample_workspace_bytes(n, weighted != 0, plan ? plan->seg_work : kDefaultSegWork);
 }
 
 mh_status mh_sample_unweighted(const double* x, int64_t n, uint64_t seed, uint32_t replica,
@@ -780,7 +784,7 @@ mh_status mh_plan_counts(const double* zs, const double* c, int64_t n, int32_t s
 extern "C" {
 
 size_t mh_bipartite_workspace_bytes(int64_t n_rows, int64_t n_cols, int weighted, const mh_plan_params* plan) {
-    return mh::bipartite_workspace_bytes(n_rows, n_cols, weighted != 0, plan ? plan->seg_work : 16);
+    return mh::bipartite_workspace_bytes(n_rows, n_cols, weighted != 0, plan ? plan->seg_work : kDefaultSegWork);
 }
 
 mh_status mh_sample_bipartite(const double* x_rows, const double* y_rows, int64_t n_rows, const double* x_cols,

@@ -160,16 +160,17 @@ def test_invalid_parameters(mh, bad):
 
 def test_full_size_bipartite(mh):
     # 1,000,000 rows (degrees power law 2.1) x 500,000 columns (2.5), the
-    # default launch configuration
+    # default segment size
     xr, xc, _, _ = workloads.bipartite_params()
-    res = mh.sample_bipartite(dev(xr), dev(xc), seed=1, replica=3, stats=True)
-    ora = oracle.sample_bipartite(xr, xc, seed=1, replica=3, seg_work=16, capacity=6_000_000)
+    res = mh.sample_bipartite(dev(xr), dev(xc), seed=1, replica=3, seg_work=8, stats=True)
+    ora = oracle.sample_bipartite(xr, xc, seed=1, replica=3, seg_work=8, capacity=6_000_000)
     compare(res, ora, len(xc))
 
 
 def test_full_size_directed_weighted(mh):
     xo, xi, yo, yi = workloads.directed_params(n=300_000, weighted=True)
-    res = mh.sample_bipartite(dev(xo), dev(xi), dev(yo), dev(yi), exclude_self=True, seed=2, replica=0, stats=True)
+    res = mh.sample_bipartite(dev(xo), dev(xi), dev(yo), dev(yi), exclude_self=True, seed=2, replica=0,
+                              seg_work=16, stats=True)
     ora = oracle.sample_bipartite(xo, xi, yo, yi, exclude_self=True, seed=2, replica=0, seg_work=16,
                                   capacity=4_000_000)
     compare(res, ora, len(xi), weighted=True)

@@ -202,16 +202,16 @@ def test_async_samples_match_sync(mh):
     src = torch.empty(20_000, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
     for r in range(5):
-        mh.sample_async(xd, None, (src, dst), ws, seed=4, replica=r)
+        mh.sample_async(xd, None, (src, dst), ws, seed=4, replica=r, seg_work=8)
     m = mh.sample_result(ws, src.numel())
-    ora = oracle.sample_mh(x, None, seed=4, replica=4, seg_work=16)
+    ora = oracle.sample_mh(x, None, seed=4, replica=4, seg_work=8)
     compare_edges((src[:m], dst[:m]), ora, n, ora.tie_rows)
     rng = np.random.default_rng(5)
     y = rng.uniform(0.1, 0.9, n)
     w = torch.empty_like(src)
-    mh.sample_async(xd, dev(y), (src, dst, w), ws, seed=6, replica=2)
+    mh.sample_async(xd, dev(y), (src, dst, w), ws, seed=6, replica=2, seg_work=8)
     m = mh.sample_result(ws, src.numel())
-    ora = oracle.sample_mh(x, y, seed=6, replica=2, seg_work=16)
+    ora = oracle.sample_mh(x, y, seed=6, replica=2, seg_work=8)
     compare_edges((src[:m], dst[:m], w[:m]), ora, n, ora.tie_rows, weighted=True)
     # too small an output: the sample's own count comes back with MH_ECAPACITY
     small = (src[:10], dst[:10])
@@ -299,12 +299,12 @@ def test_expected_degree_grad_matches_oracle(mh, weighted):
 # ------------------------------------------------------------------ full sizes
 def test_full_size_unweighted_matches_oracle(mh):
     # N = 1,000,000, power-law targets (exponent 2.1, k in [1, 1e4]); the bench's
-    # launch configuration (seg_work 16, default grid).  x follows the
+    # launch configuration (seg_work 8, default grid).  x follows the
     # sparse-limit recipe of the targets (inputs never come from the device).
     x = workloads.chung_lu_scale(workloads.cfg2_degrees())
     for replica in (1000, 1001):
-        src, dst = mh.sample_unweighted(dev(x), seed=1, replica=replica, seg_work=16)
-        ora = oracle.sample_mh(x, None, seed=1, replica=replica, seg_work=16, capacity=3_000_000)
+        src, dst = mh.sample_unweighted(dev(x), seed=1, replica=replica, seg_work=8)
+        ora = oracle.sample_mh(x, None, seed=1, replica=replica, seg_work=8, capacity=3_000_000)
         compare_edges((src, dst), ora, len(x), ora.tie_rows)
 
 
