@@ -723,7 +723,7 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
 extern "C" {
 
 size_t mh_workspace_bytes(int64_t n, int weighted, const mh_plan_params* plan) {
-    return mh::sample_workspace_bytes(n, weighted != 0, plan ? plan->seg_work : kDefaultSegWork);
+    return mh::sample_workspace_bytes(n, weighted != 0, plan ? plan->seg_work : mh::kDefaultSegWork);
 }
 
 mh_status mh_sample_unweighted(const double* x, int64_t n, uint64_t seed, uint32_t replica,
@@ -784,7 +784,8 @@ mh_status mh_plan_counts(const double* zs, const double* c, int64_t n, int32_t s
 extern "C" {
 
 size_t mh_bipartite_workspace_bytes(int64_t n_rows, int64_t n_cols, int weighted, const mh_plan_params* plan) {
-    return mh::bipartite_workspace_bytes(n_rows, n_cols, weighted != 0, plan ? plan->seg_work : kDefaultSegWork);
+    return mh::bipartite_workspace_bytes(n_rows, n_cols, weighted != 0,
+                                         plan ? plan->seg_work : mh::kDefaultSegWork);
 }
 
 mh_status mh_sample_bipartite(const double* x_rows, const double* y_rows, int64_t n_rows, const double* x_cols,
