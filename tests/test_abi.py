@@ -52,6 +52,18 @@ def test_workspace_sizes_grow_with_n(L):
     assert L.mh_bruteforce_workspace_bytes(50_000) > 0
 
 
+def test_null_plan_means_documented_default(L):
+    import paper_2509_13230_amd as mh
+
+    p = mh.PlanParams(mh.DEFAULT_SEG_WORK, 0, 0, 0, None)
+    for n in (1000, 1_000_000):
+        assert L.mh_workspace_bytes(n, 1, None) == L.mh_workspace_bytes(n, 1, ctypes.byref(p))
+        assert L.mh_bipartite_workspace_bytes(n, 777, 1, None) == L.mh_bipartite_workspace_bytes(
+            n, 777, 1, ctypes.byref(p))
+    assert mh.DEFAULT_SEG_WORK == 8  # the value include/mh.h documents for a NULL plan
+    assert "NULL = {seg_work = 8" in open(HEADER).read()
+
+
 def test_argument_errors_return_before_device_work(L):
     n = ctypes.c_int64(0)
     # missing n_edges_host
