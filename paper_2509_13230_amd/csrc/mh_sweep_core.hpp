@@ -185,13 +185,26 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
     const NodeRec* col = BIP ? A.net.col : nullptr;
     const double* ysc = BIP ? A.net.ysc : nullptr;
     int32_t* deg = nullptr;
-    // values in flight from the previous iteration's loads
-    double ld_s = 0.0, ld_z = 0.0, ld_c = 1.0, ld_y = 0.0;
-    int32_t ld_id = 0, ld_n = 1;
-    HeavyRec ld_rec{0, 0, 0, 0};
+    // Values in flight from the previous iteration's loads.  The steps below
+    // only choose addresses; each value is then loaded at one place at the end
+    // of the iteration and read in the next, so its latency overlaps the next
+    // draw (a value merged from several loads would need a copy, and the copy
+    // a wait for the load).
+    NodeRec ra{0.0, 0, 1};     // the candidate (z, id), or the row being set up (z, id, nseg)
+    double rb = 0.0;           // z of the column before a segment's chain (heavy segments, light rows of two sets)
+    HeavyRec rc{0, 0, 0, 0};   // a heavy segment's record
+    double ry = 0.0, rcc = 1.0;  // weighted: y of the candidate or of the row; the row's bound
+    bool start_rb = false;     // the chain of the row being set up starts at rb, else at the row itself
+    bool rec_direct = false;   // rc is beyond the stored records: computed in S_REC from rc_it
+    int64_t rc_it = 0;
     int64_t kbase = 0;
 
     for (;;) {
+        const NodeRec* pa = nullptr;
+        const double* pb = nullptr;
+        const double* py = nullptr;
+        const double* pc = nullptr;
+        const HeavyRec* prc = nullptr;
         // 1. the next draw of every lane that will draw this iteration
         const bool draws = (state == S_STEP) || (state == S_LOAD);
         double E = 0.0, U2n = 0.0;
@@ -204,10 +217,10 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
         bool acc = false, go = false;
         int32_t dst_id = 0, wt = 0;
         if (state == S_STEP) {
-            const double t = s * ld_z;
+            const double t = s * ra.z;
             double lhs, rhs;
             if (WEIGHTED) {
-                const double e = 1.0 - ysr * ld_y;
+                const double e = 1.0 - ysr * ry;
                 lhs = (U2 * tq) * (e + t);
                 rhs = t * (cr + tq);
             } else {
@@ -215,12 +228,12 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
                 rhs = t * (1.0 + tq);
             }
             ++st_props;
-            if (lhs < rhs && !(BIP && no_self && ld_id == id)) {
+            if (lhs < rhs && !(BIP && no_self && ra.id == id)) {
                 acc = true;
                 ++st_acc;
-                dst_id = ld_id;
+                dst_id = ra.id;
                 if (WEIGHTED) {
-                    const double bb = ysr * ld_y;
+                    const double bb = ysr * ry;
                     if (bb == 0.0) {
                         wt = 1;
                     } else {
@@ -239,36 +252,45 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
             pos = jc;
             go = true;
         } else if (state == S_LOAD) {
-            if (check_light && ld_n != 1) {
+            if (check_light && ra.nseg != 1) {
                 state = S_IDLE;
             } else {
-                s = ld_s;
-                id = ld_id;
-                tq = s * ld_z;
-                cr = WEIGHTED ? ld_c : 1.0;
-                ysr = WEIGHTED ? ld_y : 0.0;
+                s = ra.z;
+                id = ra.id;
+                tq = s * (start_rb ? rb : ra.z);
+                cr = WEIGHTED ? rcc : 1.0;
+                ysr = WEIGHTED ? ry : 0.0;
                 ++st_segs;
                 go = true;
             }
         } else if (state == S_REC) {
-            r = ld_rec.r;
-            pos = ld_rec.a - 1;
-            end = ld_rec.b;
-            tag = (uint32_t)ld_rec.g << 1;
+            const NetDesc& D = BATCH ? A.batch.nets[A.batch.sample_net[sample]] : A.net;
+            HeavyRec hr = rc;
+            if (rec_direct) {
+                hr = heavy_record(D, rc_it);
+                // Some of heavy_record's loads go unused on some paths; left
+                // outstanding, they would make the compiler wait for all loads
+                // (the counter is in order) at the top of the next iteration,
+                // in front of this iteration's candidate loads.  vmcnt(0) here
+                // (expcnt and lgkmcnt at their no-wait maxima) settles them.
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+            }
+            r = hr.r;
+            pos = hr.a - 1;
+            end = hr.b;
+            tag = (uint32_t)hr.g << 1;
             step = 0;
             check_light = false;
-            if (ld_rec.a >= ld_rec.b) {
+            if (hr.a >= hr.b) {
                 state = S_IDLE;
             } else {
-                const NetDesc& D = BATCH ? A.batch.nets[A.batch.sample_net[sample]] : A.net;
-                const NodeRec nr = node[r];
-                ld_s = nr.z;
-                ld_id = nr.id;
-                ld_z = BIP ? col[ld_rec.a].z : node[pos].z;
+                pa = &node[r];
+                pb = BIP ? &col[hr.a].z : &node[pos].z;
                 if (WEIGHTED) {
-                    ld_c = D.c[r];
-                    ld_y = ys[r];
+                    pc = &D.c[r];
+                    py = &ys[r];
                 }
+                start_rb = true;
                 state = S_LOAD;
             }
         }
@@ -290,10 +312,8 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
                     U2 = U2n;
                     scand = step;
                     ++step;
-                    const NodeRec nj = (BIP ? col : node)[jc];
-                    ld_z = nj.z;
-                    ld_id = nj.id;
-                    if (WEIGHTED) ld_y = (BIP ? ysc : ys)[jc];
+                    pa = &(BIP ? col : node)[jc];
+                    if (WEIGHTED) py = &(BIP ? ysc : ys)[jc];
                     state = S_STEP;
                 }
             }
@@ -329,7 +349,9 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
                         if (OUT == OUT_DEGREES) deg = A.batch.degrees + A.batch.deg_off[lo];
                     }
                     if (it < H) {
-                        ld_rec = (it < Dp->rec_cap) ? Dp->rec[it] : heavy_record(*Dp, it);
+                        rec_direct = it >= Dp->rec_cap;
+                        rc_it = it;
+                        if (!rec_direct) prc = &Dp->rec[it];
                         state = S_REC;
                     } else {
                         r = (int32_t)(it - H);
@@ -338,20 +360,26 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
                         tag = 0;
                         step = 0;
                         check_light = true;
-                        const NodeRec nr = node[r];
-                        ld_n = nr.nseg;
-                        ld_s = nr.z;
-                        ld_z = BIP ? col[0].z : nr.z;
-                        ld_id = nr.id;
+                        pa = &node[r];
+                        if (BIP) pb = &col[0].z;
+                        start_rb = BIP;
                         if (WEIGHTED) {
-                            ld_c = Dp->c[r];
-                            ld_y = ys[r];
+                            pc = &Dp->c[r];
+                            py = &ys[r];
                         }
                         state = S_LOAD;
                     }
                 }
             }
             kbase += __popcll(idle);
+        }
+        // 5. this iteration's loads, read in the next
+        if (pa) ra = *pa;
+        if (pb) rb = *pb;
+        if (prc) rc = *prc;
+        if (WEIGHTED) {
+            if (py) ry = *py;
+            if (pc) rcc = *pc;
         }
         if (OUT == OUT_EDGES) stage.push_sid(acc, id, dst_id, wt, sample, s_sid, A.out, A.sid);
         if (__ballot(state != S_DONE) == 0) break;
