@@ -33,6 +33,10 @@ constexpr uint64_t kFlagAggregate = 1ull << 32;
 constexpr uint64_t kFlagPrefix = 2ull << 32;
 constexpr uint32_t kSpinLimit = 1u << 20;
 constexpr int kLookWindow = 8;
+// Column exchange: a column of at most kXchgTiles tiles per 256 threads, so a
+// block scans kXchgCols digit columns at once.
+constexpr int kXchgTiles = 256;
+constexpr int kXchgCols = kSortThreads / kXchgTiles;
 // The counting kernel adds its block histograms into kHistCopies copies (block
 // b into copy b % kHistCopies); readers sum the copies.
 constexpr int kHistCopies = kRadixHistCopies;
@@ -91,6 +95,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
         if (h[i]) atomicAdd(&copy[i], h[i]);
 }
 
+template <bool XCHG>
 __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __restrict__ kin,
                                                            const uint32_t* __restrict__ vin,
                                                            uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -102,6 +107,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     __shared__ uint32_t cnt[kSortWaves][kRadix];
     __shared__ uint32_t s_bstart[kRadix];
     __shared__ uint32_t s_goff[kRadix];
+    __shared__ uint32_t s_dstart[kRadix];
     __shared__ uint32_t s_scan[kSortWaves];
     __shared__ uint32_t s_tile;
 
@@ -155,16 +161,73 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
             cnt[w][d] = total;  // becomes the wave's offset inside the block's digit run
             total += c;
         }
-        __hip_atomic_store(st, (tile == 0 ? kFlagPrefix : kFlagAggregate) | total, __ATOMIC_RELAXED,
+        __hip_atomic_store(st, (tile == 0 && !XCHG ? kFlagPrefix : kFlagAggregate) | total, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
         for (int c = 0; c < kHistCopies; ++c) dtotal += ghist[c * kPasses * kRadix + d];
     }
     const uint32_t bstart = block_exclusive(total, s_scan);
     const uint32_t dstart = block_exclusive(dtotal, s_scan);
-    // look back over the preceding tiles, kLookWindow words in flight at a time
     uint32_t excl = 0;
-    if (dig && tile > 0) {
+    if (XCHG) {
+        // Every tile is resident (at most kXchgTiles): instead of a chain of
+        // look-backs, block b scans the digit columns b, b + G, b + 2G, ...
+        // (G blocks; kXchgCols columns at once, 256 threads each, one tile per
+        // thread) over all tiles' published counts, and writes each tile its
+        // start for that digit (flag 2 over the count word, which only this
+        // block reads); then every tile reads its 256 starts back.  Two round
+        // trips per pass when G >= 256 / kXchgCols.
+        if (dig) s_dstart[d] = dstart;
+        const int nt = (int)gridDim.x;
+        const int tcol = threadIdx.x & (kXchgTiles - 1);  // this thread's tile in the column
+        for (int c0 = blockIdx.x; c0 < kRadix; c0 += kXchgCols * nt) {
+            const int col = c0 + (int)(threadIdx.x / kXchgTiles) * nt;
+            const bool mine = tcol < nt && col < kRadix;
+            uint64_t* cw = status + (int64_t)tcol * kRadix + col;
+            uint32_t c = 0;
+            if (mine) {
+                uint32_t spins = 0;
+                for (;;) {
+                    const uint64_t w = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (w & ~0xFFFFFFFFull) {
+                        c = (uint32_t)w;
+                        break;
+                    }
+                    if (++spins > kSpinLimit) {
+                        raise_status(err, MH_EHIP);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            // exclusive scan over each column's 256 threads (4 waves)
+            const uint32_t inc = wave_inclusive_scan(c);
+            if (lane == 63) s_scan[wave] = inc;
+            __syncthreads();  // also orders the s_dstart writes
+            uint32_t before = inc - c;
+            for (int w = wave & ~(kXchgTiles / kWave - 1); w < wave; ++w) before += s_scan[w];
+            if (mine)
+                __hip_atomic_store(cw, kFlagPrefix | (s_dstart[col] + before), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+        }
+        if (dig) {
+            uint32_t spins = 0;
+            for (;;) {
+                const uint64_t w = __hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((w & ~0xFFFFFFFFull) == kFlagPrefix) {
+                    excl = (uint32_t)w - dstart;  // earlier tiles' keys with digit d
+                    break;
+                }
+                if (++spins > kSpinLimit) {
+                    raise_status(err, MH_EHIP);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+    } else if (dig && tile > 0) {
+        // look back over the preceding tiles, kLookWindow words in flight at a time
         int64_t t = tile - 1;
         uint32_t spins = 0;
         bool done = false;
@@ -250,15 +313,19 @@ mh_status radix_sort_u64_hist(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, keys, n, hist);
         MH_HIP_TRY(hipGetLastError());
     }
-    const bool use_ticket = nb > resident_blocks(k_onesweep, kSortThreads);
+    // One tile per CU at most: the column exchange (all tiles resident, with a
+    // CU to spare for each); otherwise the look-back, by ticket unless the
+    // whole grid is resident.
+    const bool xchg = nb <= kXchgTiles && nb <= device_cus();
+    const bool use_ticket = !xchg && nb > resident_blocks(k_onesweep<false>, kSortThreads);
     uint64_t* kin = keys;
     uint32_t* vin = vals;
     uint64_t* kout = keys_alt;
     uint32_t* vout = vals_alt;
     for (int pass = 0; pass < kPasses; ++pass) {
-        hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n,
-                           pass * 8, hist + pass * kRadix, status + (int64_t)pass * nb * kRadix, tickets + pass,
-                           use_ticket, err);
+        hipLaunchKernelGGL(xchg ? k_onesweep<true> : k_onesweep<false>, dim3((unsigned)nb), dim3(kSortThreads), 0,
+                           stream, kin, vin, kout, vout, n, pass * 8, hist + pass * kRadix,
+                           status + (int64_t)pass * nb * kRadix, tickets + pass, use_ticket, err);
         MH_HIP_TRY(hipGetLastError());
         uint64_t* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;

@@ -68,7 +68,9 @@ def compare_edges(gpu, ora, n, tie_rows, weighted=False):
 
 
 # ------------------------------------------------------------------ order / bound / plan
-@pytest.mark.parametrize("n", [1, 2, 3, 1000, 4097, 70_001])
+# 256 tiles of 4096 keys or fewer: the sort's column exchange; 300 tiles: the
+# look-back with every block resident
+@pytest.mark.parametrize("n", [1, 2, 3, 1000, 4097, 70_001, 1 << 20, 300 * 4096 + 77])
 def test_order_matches_oracle(mh, n):
     rng = np.random.default_rng(n)
     x = np.round(rng.lognormal(-2, 1.5, n), 3)  # ties
