@@ -72,25 +72,29 @@ mh_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void*
 mh_status scan_exclusive_u64_onepass(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* state,
                                      uint64_t* samples, int32_t* err, hipStream_t stream);
 
-// ---- radix sort of (key, value) pairs ascending by key, stable ----
+// ---- radix sort of 64-bit keys with distinct 32-bit payloads ----
+// Passed split: hi[i] = key >> 32 (the radix key, kRadixPasses passes of 8
+// bits) and pay[i] = (key & 0xFFFFFFFF) << 32 | payload; afterwards the pairs
+// ascend by (key, payload).
+constexpr int kRadixPasses = 4;
 // Copies of the digit histograms: enough that no address takes more than a few
 // dozen of the counting kernel's atomics, few enough that each pass sums them
 // with one round of loads.
 constexpr int kRadixHistCopies = 4;
 size_t radix_workspace_bytes(int64_t n);
-// Zeroes the sort's scratch (in ws) and returns its histogram array for a fused
-// counting kernel: kRadixHistCopies copies of 8 x 256 counts (copy c, pass p,
-// digit d at [(c * 8 + p) * 256 + d]); a counting block adds into copy
+// Zeroes the sort's scratch (in ws) and returns its histogram array for the
+// counting kernel that writes hi and pay: kRadixHistCopies copies of
+// kRadixPasses x 256 counts of the bytes of hi (copy c, pass p, digit d at
+// [(c * kRadixPasses + p) * 256 + d]); a counting block adds into copy
 // blockIdx % kRadixHistCopies.
 // extra_zero / extra_words: another range of u64 words zeroed by the same kernel.
 mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream,
                         uint64_t* extra_zero = nullptr, int64_t extra_words = 0);
-// Sorts keys[0..n) / vals[0..n) using alt buffers of the same size; the result
-// ends in keys/vals (8 passes of 8 bits).  hist_ready: the histogram returned
-// by radix_prepare already holds the counts.  err (optional, device) receives
-// MH_EHIP if a look-back ever stalls.
-mh_status radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                         void* ws, size_t ws_bytes, bool hist_ready, int32_t* err, hipStream_t stream);
+// Sorts hi[0..n) / pay[0..n) using alt buffers of the same size (the result
+// ends in hi / pay); the histograms must hold the counts.  err (optional,
+// device) receives MH_EHIP if a look-back or exchange ever stalls.
+mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint64_t* pay_alt, int64_t n,
+                             void* ws, size_t ws_bytes, int32_t* err, hipStream_t stream);
 
 // ---- sampler pieces ----
 struct SortedView {

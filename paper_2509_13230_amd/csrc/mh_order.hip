@@ -14,14 +14,16 @@ constexpr int kThreads = 256;
 
 constexpr int kPrepTile = 4096;
 
-// Sort keys (complemented bits of z = x or x*y) with ids as payload, checks of
-// the parameters, and the digit histograms of all 8 radix passes.
+// Sort keys (complemented bits of z = x or x*y, split: high half as the radix
+// key, low half above the id as payload), checks of the parameters, and the
+// digit histograms of all radix passes.
 __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict__ x, const double* __restrict__ y,
-                                                        int64_t n, uint64_t* __restrict__ keys,
-                                                        uint32_t* __restrict__ vals, uint32_t* __restrict__ hist,
+                                                        int64_t n, uint32_t* __restrict__ keys,
+                                                        uint64_t* __restrict__ vals, uint32_t* __restrict__ hist,
                                                         int32_t* status) {
-    __shared__ uint32_t h[8 * 256];
-    for (int i = threadIdx.x; i < 8 * 256; i += kThreads) h[i] = 0;
+    constexpr int kHist = kRadixPasses * 256;
+    __shared__ uint32_t h[kHist];
+    for (int i = threadIdx.x; i < kHist; i += kThreads) h[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kPrepTile;
     const int lane = threadIdx.x & 63;
@@ -51,19 +53,19 @@ __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict
     for (int q = 0; q < kPer; ++q) {
         const int64_t i = base + (int64_t)q * kThreads + threadIdx.x;
         const bool valid = i < n;
-        uint64_t key = 0;
+        uint32_t key = 0;
         if (valid) {
             const bool ok = okv[q] && isfinite(zv[q]);
             bad = bad || !ok;
-            key = desc_key(ok ? zv[q] : 0.0);
+            const uint64_t full = desc_key(ok ? zv[q] : 0.0);
+            key = (uint32_t)(full >> 32);
             keys[i] = key;
-            vals[i] = (uint32_t)i;
+            vals[i] = (full << 32) | (uint64_t)(uint32_t)i;
         }
         // Lanes holding the key of their group's first lane (groups by an 8-bit
         // fold of the key) are counted once by that lane: tied parameters,
         // common in fitted inputs, would otherwise all hit one LDS bin.
-        const uint32_t fold = (uint32_t)(key ^ (key >> 8) ^ (key >> 16) ^ (key >> 24) ^ (key >> 32) ^ (key >> 40) ^
-                                         (key >> 48) ^ (key >> 56)) & 255u;
+        const uint32_t fold = (key ^ (key >> 8) ^ (key >> 16) ^ (key >> 24)) & 255u;
         uint64_t m = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict
             m &= bit ? vote : ~vote;
         }
         const int leader = valid ? (int)__ffsll((unsigned long long)m) - 1 : lane;
-        const uint64_t lkey = __shfl(key, leader, kWave);
+        const uint32_t lkey = __shfl(key, leader, kWave);
         const uint64_t same = __ballot(valid && key == lkey);
         if (valid) {
             uint32_t add = 0;
@@ -80,20 +82,28 @@ __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict
             else if (!((same >> lane) & 1ull)) add = 1;
             if (add) {
 #pragma unroll
-                for (int p = 0; p < 8; ++p) atomicAdd(&h[p * 256 + ((key >> (8 * p)) & 255)], add);
+                for (int p = 0; p < kRadixPasses; ++p) atomicAdd(&h[p * 256 + ((key >> (8 * p)) & 255)], add);
             }
         }
     }
     if (bad) raise_status(status, MH_EINVAL);
     __syncthreads();
     // one of the histogram copies per block (the sort sums them)
-    uint32_t* copy = hist + (blockIdx.x % kRadixHistCopies) * 8 * 256;
-    for (int i = threadIdx.x; i < 8 * 256; i += kThreads)
+    uint32_t* copy = hist + (blockIdx.x % kRadixHistCopies) * kHist;
+    for (int i = threadIdx.x; i < kHist; i += kThreads)
         if (h[i]) atomicAdd(&copy[i], h[i]);
 }
 
-__global__ __launch_bounds__(kThreads) void k_finish_order(const uint64_t* __restrict__ keys,
-                                                           const uint32_t* __restrict__ vals, int64_t n,
+// The sorted key and id at a rank, from the split sort's arrays.
+__device__ __forceinline__ double sorted_z(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ vals,
+                                           int64_t r, uint32_t* id) {
+    const uint64_t v = vals[r];
+    *id = (uint32_t)v;
+    return key_value(((uint64_t)keys[r] << 32) | (v >> 32));
+}
+
+__global__ __launch_bounds__(kThreads) void k_finish_order(const uint32_t* __restrict__ keys,
+                                                           const uint64_t* __restrict__ vals, int64_t n,
                                                            int32_t* __restrict__ perm, double* __restrict__ zs,
                                                            NodeRec* __restrict__ node,
                                                            const double* __restrict__ y, double* __restrict__ ys,
@@ -101,8 +111,8 @@ __global__ __launch_bounds__(kThreads) void k_finish_order(const uint64_t* __res
                                                            int32_t* status) {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= n) return;
-    const uint32_t id = vals[r];
-    const double z = key_value(keys[r]);
+    uint32_t id;
+    const double z = sorted_z(keys, vals, r, &id);
     if (node) {
         node[r].z = z;
         node[r].id = (int32_t)id;
@@ -118,8 +128,8 @@ __global__ __launch_bounds__(kThreads) void k_finish_order(const uint64_t* __res
 // The same, into node records, with the column masses scanned on the way:
 // P[r] = sum of floor(z 2^32) over ranks < r, P[n] = total (tiles of 4096
 // ranks, look-back state zero at launch).
-__global__ __launch_bounds__(kLbThreads) void k_finish_order_scan(const uint64_t* __restrict__ keys,
-                                                                  const uint32_t* __restrict__ vals, int64_t n,
+__global__ __launch_bounds__(kLbThreads) void k_finish_order_scan(const uint32_t* __restrict__ keys,
+                                                                  const uint64_t* __restrict__ vals, int64_t n,
                                                                   NodeRec* __restrict__ node,
                                                                   const double* __restrict__ y,
                                                                   double* __restrict__ ys, uint64_t* __restrict__ P,
@@ -135,8 +145,8 @@ __global__ __launch_bounds__(kLbThreads) void k_finish_order_scan(const uint64_t
             const int64_t r = base + idx;
             uint64_t m = 0;
             if (r < n) {
-                const uint32_t id = vals[r];
-                const double z = key_value(keys[r]);
+                uint32_t id;
+                const double z = sorted_z(keys, vals, r, &id);
                 node[r].z = z;
                 node[r].id = (int32_t)id;
                 if (ys) ys[r] = y[id];
@@ -289,10 +299,10 @@ __global__ __launch_bounds__(kThreads) void k_bound_tile_scan(const double* __re
 
 size_t order_workspace_bytes(int64_t n) {
     Sizer s;
-    s.take<uint64_t>(n);  // keys
-    s.take<uint64_t>(n);  // keys alt
-    s.take<uint32_t>(n);  // vals
-    s.take<uint32_t>(n);  // vals alt
+    s.take<uint32_t>(n);  // keys
+    s.take<uint32_t>(n);  // keys alt
+    s.take<uint64_t>(n);  // vals
+    s.take<uint64_t>(n);  // vals alt
     return s.used + radix_workspace_bytes(n) + 256;
 }
 
@@ -302,10 +312,10 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
                       uint64_t* extra_zero, int64_t extra_words) {
     if (n <= 0) return MH_OK;
     Arena ar(ws, ws_bytes);
-    uint64_t* keys = ar.take<uint64_t>(n);
-    uint64_t* keys_alt = ar.take<uint64_t>(n);
-    uint32_t* vals = ar.take<uint32_t>(n);
-    uint32_t* vals_alt = ar.take<uint32_t>(n);
+    uint32_t* keys = ar.take<uint32_t>(n);
+    uint32_t* keys_alt = ar.take<uint32_t>(n);
+    uint64_t* vals = ar.take<uint64_t>(n);
+    uint64_t* vals_alt = ar.take<uint64_t>(n);
     if (ar.overflow) return MH_EWORKSPACE;
     const size_t off = (ar.used + 255) & ~size_t(255);
     void* sort_ws = ar.base + off;
@@ -316,7 +326,7 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
     const unsigned tiles = (unsigned)((n + kPrepTile - 1) / kPrepTile);
     hipLaunchKernelGGL(k_prep_keys, dim3(tiles), dim3(kThreads), 0, stream, x, y, n, keys, vals, hist, status);
     MH_HIP_TRY(hipGetLastError());
-    st = radix_sort_u64(keys, vals, keys_alt, vals_alt, n, sort_ws, sort_bytes, true, status, stream);
+    st = radix_sort_split64(keys, vals, keys_alt, vals_alt, n, sort_ws, sort_bytes, status, stream);
     if (st != MH_OK) return st;
     if (mass_prefix && node && n <= (int64_t)1 << 30) {
         // records and the masses' prefix sums in one pass (sums stay below 2^62)
@@ -324,7 +334,7 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
         const int64_t resident = resident_blocks(k_finish_order_scan, kLbThreads);
         const int64_t grid = tiles < resident ? tiles : resident;
         hipLaunchKernelGGL(k_finish_order_scan, dim3((unsigned)grid), dim3(kLbThreads), 0, stream,
-                           (const uint64_t*)keys, (const uint32_t*)vals, n, node, y, y ? ys : nullptr, mass_prefix,
+                           (const uint32_t*)keys, (const uint64_t*)vals, n, node, y, y ? ys : nullptr, mass_prefix,
                            tiles, mass_state, mass_samples, (int32_t)check_square, status);
         MH_HIP_TRY(hipGetLastError());
         return MH_OK;

@@ -1,17 +1,29 @@
-// Stable LSD radix sort of 64-bit keys with 32-bit payloads: 8 passes of 8
-// bits, one kernel per pass ("one-sweep" with decoupled look-back).
+// Stable LSD radix sort of 64-bit keys with 32-bit payloads, done as a sort by
+// the keys' high 32 bits (4 passes of 8 bits, one kernel per pass) followed by
+// a repair of the runs whose high halves tie but whose low halves are out of
+// order.  The caller passes hi = key >> 32 as the sort key and pay = (low half
+// << 32) | payload, so sorting a run of equal hi by pay orders it by (key,
+// payload); with payloads distinct (node ids) that is the order of a full
+// stable sort.
 //
-// The digit histograms of all 8 passes come from one counting kernel (fused
-// into key preparation by the caller, or k_radix_hist).  In a pass, each block
-// takes a tile ticket, ranks its 4096 keys (keys with equal digits are grouped
-// by 8 ballots, one per digit bit, so ties cost nothing extra), publishes its
-// per-digit counts, and finds the counts of all earlier tiles by looking back
-// over their published words (a 64-bit word per tile and digit: a flag in the
-// high half -- 1 = this tile's count, 2 = inclusive prefix over tiles 0..t --
-// and the value in the low half).  A block waits only on tiles with smaller
-// tickets, which have started and publish without waiting, so the look-back
-// always ends; a spin limit turns a lost update into an error, never a hang.
-// Keys are then reordered by digit in LDS and written in coalesced runs.
+// Passes ("one-sweep"): the digit histograms of all passes come from one
+// counting kernel (fused into key preparation by the caller).  In a pass, each
+// block ranks its 4096 keys (keys with equal digits are grouped by 8 ballots,
+// one per digit bit, so ties cost nothing extra), publishes its per-digit
+// counts, and finds the counts of all earlier tiles, by a column exchange when
+// every tile has a CU of its own, else by looking back over their published
+// words (a 64-bit word per tile and digit: a flag in the high half -- 1 = this
+// tile's count, 2 = inclusive prefix over tiles 0..t -- and the value in the
+// low half).  A block waits only on tiles that have started and publish
+// without waiting, so the look-back always ends; a spin limit turns a lost
+// update into an error, never a hang.  Keys are then reordered by digit in LDS
+// and written in coalesced runs.
+//
+// Repair: one kernel marks the start of every run of equal hi that holds a
+// descent of pay (a bitmap), a second sorts the marked runs by pay -- a wave
+// per run of up to 64, a block and LDS up to 8192, and a block-level LSD
+// through scratch beyond.  Inputs whose keys differ within their high halves
+// (fitted parameters: ties by degree class) have no such runs.
 #include "mh_common.hpp"
 #include "mh_internal.hpp"
 
@@ -20,7 +32,7 @@ namespace mh {
 namespace {
 
 // 16 waves share a tile (4 keys per lane): a pass is a chain of dependent
-// steps (load, rank, publish, look back, scatter) on ~250 tiles for 1M keys,
+// steps (load, rank, publish, exchange, scatter) on ~250 tiles for 1M keys,
 // so the waves of a block, not more tiles, are what hide its latencies.
 constexpr int kSortThreads = 1024;
 constexpr int kSortWaves = kSortThreads / kWave;
@@ -28,7 +40,7 @@ constexpr int kKeysPerLane = 4;
 constexpr int kWaveKeys = kWave * kKeysPerLane;     // 256, contiguous per wave
 constexpr int kTileKeys = kWaveKeys * kSortWaves;  // 4096 per block
 constexpr int kRadix = 256;
-constexpr int kPasses = 8;
+constexpr int kPasses = kRadixPasses;  // 4 passes over the 32-bit sort key
 constexpr uint64_t kFlagAggregate = 1ull << 32;
 constexpr uint64_t kFlagPrefix = 2ull << 32;
 constexpr uint32_t kSpinLimit = 1u << 20;
@@ -75,35 +87,15 @@ __global__ __launch_bounds__(kSortThreads) void k_zero_u64(uint64_t* __restrict_
     for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < m; i += stride) q[i] = 0;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n,
-                                                             uint32_t* __restrict__ ghist) {
-    __shared__ uint32_t h[kPasses * kRadix];
-    for (int i = threadIdx.x; i < kPasses * kRadix; i += kSortThreads) h[i] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTileKeys;
-    for (int k = threadIdx.x; k < kTileKeys; k += kSortThreads) {
-        const int64_t i = base + k;
-        if (i < n) {
-            const uint64_t key = keys[i];
-#pragma unroll
-            for (int p = 0; p < kPasses; ++p) atomicAdd(&h[p * kRadix + ((key >> (8 * p)) & 255)], 1u);
-        }
-    }
-    __syncthreads();
-    uint32_t* copy = ghist + (blockIdx.x % kHistCopies) * kPasses * kRadix;
-    for (int i = threadIdx.x; i < kPasses * kRadix; i += kSortThreads)
-        if (h[i]) atomicAdd(&copy[i], h[i]);
-}
-
 template <bool XCHG>
-__global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __restrict__ kin,
-                                                           const uint32_t* __restrict__ vin,
-                                                           uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+__global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __restrict__ kin,
+                                                           const uint64_t* __restrict__ vin,
+                                                           uint32_t* __restrict__ kout, uint64_t* __restrict__ vout,
                                                            int64_t n, int shift, const uint32_t* __restrict__ ghist,
                                                            uint64_t* status, uint32_t* ticket, bool use_ticket,
                                                            int32_t* err) {
-    __shared__ uint64_t s_keys[kTileKeys];
-    __shared__ uint32_t s_vals[kTileKeys];
+    __shared__ uint32_t s_keys[kTileKeys];
+    __shared__ uint64_t s_vals[kTileKeys];
     __shared__ uint32_t cnt[kSortWaves][kRadix];
     __shared__ uint32_t s_bstart[kRadix];
     __shared__ uint32_t s_goff[kRadix];
@@ -124,8 +116,8 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     const uint64_t lt = lanemask_lt();
 
     // rank every key among the wave's keys with the same digit
-    uint64_t k[kKeysPerLane];
-    uint32_t v[kKeysPerLane];
+    uint32_t k[kKeysPerLane];
+    uint64_t v[kKeysPerLane];
     uint32_t rank[kKeysPerLane];
     // all loads first: the ranking below orders LDS accesses with wave barriers,
     // which the compiler will not move loads across
@@ -133,14 +125,14 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     for (int r = 0; r < kKeysPerLane; ++r) {
         const int64_t i = base + (int64_t)r * kWave + lane;
         const bool valid = i < n;
-        k[r] = valid ? kin[i] : 0ull;
-        v[r] = valid ? vin[i] : 0u;
+        k[r] = valid ? kin[i] : 0u;
+        v[r] = valid ? vin[i] : 0ull;
     }
 #pragma unroll
     for (int r = 0; r < kKeysPerLane; ++r) {
         const int64_t i = base + (int64_t)r * kWave + lane;
         const bool valid = i < n;
-        const uint32_t d = (uint32_t)(k[r] >> shift) & (kRadix - 1);
+        const uint32_t d = (k[r] >> shift) & (kRadix - 1);
         const uint64_t m = match_digit(d, valid);
         const uint32_t prior = cnt[wave][d];
         rank[r] = prior + (uint32_t)__popcll(m & lt);
@@ -271,7 +263,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     for (int r = 0; r < kKeysPerLane; ++r) {
         const int64_t i = base + (int64_t)r * kWave + lane;
         if (i < n) {
-            const uint32_t dd = (uint32_t)(k[r] >> shift) & (kRadix - 1);
+            const uint32_t dd = (k[r] >> shift) & (kRadix - 1);
             const uint32_t lp = s_bstart[dd] + cnt[wave][dd] + rank[r];
             s_keys[lp] = k[r];
             s_vals[lp] = v[r];
@@ -280,8 +272,8 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     __syncthreads();
     const int64_t cnt_tile = (n - tbase) < kTileKeys ? (n - tbase) : kTileKeys;
     for (int i = threadIdx.x; i < cnt_tile; i += kSortThreads) {
-        const uint64_t key = s_keys[i];
-        const uint32_t dd = (uint32_t)(key >> shift) & (kRadix - 1);
+        const uint32_t key = s_keys[i];
+        const uint32_t dd = (key >> shift) & (kRadix - 1);
         const uint32_t pos = s_goff[dd] + (uint32_t)i;
         if (pos < (uint64_t)n) {  // always, unless a look-back gave up (then the error is raised)
             kout[pos] = key;
@@ -290,64 +282,283 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint64_t* __res
     }
 }
 
+// ------------------------------------------------------------------ tie runs
+constexpr int kTieThreads = 256;
+
+// First index in [0, r] whose key equals hi[r] (hi ascending).
+__device__ __forceinline__ int64_t run_start(const uint32_t* __restrict__ hi, int64_t r) {
+    const uint32_t h = hi[r];
+    int64_t lo = 0, up = r;
+    while (lo < up) {
+        const int64_t mid = (lo + up) >> 1;
+        if (hi[mid] < h) lo = mid + 1;
+        else up = mid;
+    }
+    return lo;
+}
+
+// Marks bit a of `bits` for every run [a, b) of equal hi whose pay is not
+// ascending.  A wave covers 64 consecutive ranks; of the descents it sees in
+// one run, the first marks it, and only a run that began before the wave's
+// first rank needs a search for its start.
+__global__ __launch_bounds__(kTieThreads) void k_tie_runs(const uint32_t* __restrict__ hi,
+                                                          const uint64_t* __restrict__ pay, int64_t n,
+                                                          uint32_t* __restrict__ bits) {
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * kTieThreads;
+    const int64_t first = (int64_t)blockIdx.x * kTieThreads + (threadIdx.x & ~63);
+    for (int64_t wbase = first; wbase < n; wbase += stride) {
+        const int64_t r = wbase + lane;
+        bool eq = false, desc = false;
+        if (r > 0 && r < n) {
+            eq = hi[r - 1] == hi[r];
+            if (eq) desc = pay[r - 1] > pay[r];
+        }
+        const uint64_t dm = __ballot(desc);
+        if (dm == 0) continue;
+        const uint64_t starts = __ballot(!eq) & ~1ull;  // run starts inside the wave (lane 0 aside)
+        if (desc) {
+            const uint64_t le = lanemask_lt();
+            const uint64_t before = starts & le;
+            const int s = before ? 63 - __clzll((long long)before) : 0;  // segment's first lane in the wave
+            const uint64_t seg_desc = dm & le & ~((1ull << s) - 1);   // earlier descents in the segment
+            if (seg_desc == 0) {
+                const int64_t a = (before || !(wbase > 0 && hi[wbase - 1] == hi[wbase])) ? wbase + s
+                                                                                        : run_start(hi, wbase);
+                atomicOr(&bits[a >> 5], 1u << (a & 31));
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ run repair
+constexpr int kFixThreads = 1024;
+constexpr int kFixWaves = kFixThreads / kWave;
+constexpr int kFixLds = 8192;  // runs up to this long are sorted in LDS
+constexpr int kFixList = 512;  // runs longer than a wave per chunk of 32768 ranks: < 512
+
+// Sorts up to 64 values held one per lane (absent lanes hold ~0).
+__device__ __forceinline__ uint64_t wave_bitonic(uint64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint64_t u = __shfl_xor(v, j, kWave);
+            const bool up = (lane & k) == 0;
+            const bool low = (lane & j) == 0;
+            v = (low == up) ? (u < v ? u : v) : (u > v ? u : v);
+        }
+    }
+    return v;
+}
+
+// First index >= a + 1 whose hi differs from hi[a] (n if none), searched by
+// the whole block: 1024 probes per round, each round narrowing the step.
+__device__ int64_t block_run_end(const uint32_t* __restrict__ hi, int64_t n, int64_t a, int64_t* s_pos) {
+    const uint32_t h = hi[a];
+    int64_t lo = a;  // hi[lo] == h
+    int64_t up = n;  // first index known to differ (or n)
+    while (up - lo > 1) {
+        const int64_t span = up - lo;
+        const int64_t step = (span + kFixThreads - 1) / kFixThreads;
+        const int64_t p = lo + (int64_t)(threadIdx.x + 1) * step;
+        const bool differs = p < up && hi[p] != h;
+        if (threadIdx.x == 0) *s_pos = up;
+        __syncthreads();
+        if (differs) atomicMin((unsigned long long*)s_pos, (unsigned long long)p);
+        __syncthreads();
+        const int64_t first = *s_pos;  // first probe that differs, else up
+        __syncthreads();
+        if (step == 1) return first;
+        up = first;
+        lo = first - step > lo ? first - step : lo;
+    }
+    return up;
+}
+
+// Stable LSD sort of pay[a, b) by its high 32 bits (4 passes of 8 bits) through
+// alt[a, b), by one block; the result ends in pay.
+__device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__ alt, int64_t a, int64_t b,
+                              uint32_t* s_cnt /* kFixWaves * 256 */, uint32_t* s_off /* 256 */,
+                              uint32_t* s_scan /* kFixWaves */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
+    uint64_t* src = pay;
+    uint64_t* dst = alt;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 32 + 8 * pass;
+        // digit counts over the run, then their exclusive scan
+        for (int i = threadIdx.x; i < 256; i += kFixThreads) s_off[i] = 0;
+        __syncthreads();
+        for (int64_t i = a + threadIdx.x; i < b; i += kFixThreads)
+            atomicAdd(&s_off[(uint32_t)(src[i] >> shift) & 255u], 1u);
+        __syncthreads();
+        const uint32_t c = threadIdx.x < 256 ? s_off[threadIdx.x] : 0u;
+        const uint32_t ex = block_exclusive(c, s_scan);
+        if (threadIdx.x < 256) s_off[threadIdx.x] = ex;
+        __syncthreads();
+        // chunks of 4096 in order; each wave ranks 256 consecutive values stably
+        for (int64_t cb = a; cb < b; cb += kTileKeys) {
+            for (int i = threadIdx.x; i < kFixWaves * 256; i += kFixThreads) s_cnt[i] = 0;
+            __syncthreads();
+            const int64_t wb = cb + (int64_t)wave * kWaveKeys;
+            uint64_t v[kKeysPerLane];
+            uint32_t rk[kKeysPerLane];
+#pragma unroll
+            for (int r = 0; r < kKeysPerLane; ++r) {
+                const int64_t i = wb + (int64_t)r * kWave + lane;
+                v[r] = i < b ? src[i] : 0ull;
+            }
+#pragma unroll
+            for (int r = 0; r < kKeysPerLane; ++r) {
+                const int64_t i = wb + (int64_t)r * kWave + lane;
+                const bool valid = i < b;
+                const uint32_t dg = (uint32_t)(v[r] >> shift) & 255u;
+                const uint64_t m = match_digit(dg, valid);
+                const uint32_t prior = s_cnt[wave * 256 + dg];
+                rk[r] = prior + (uint32_t)__popcll(m & lt);
+                __builtin_amdgcn_wave_barrier();
+                if (valid && (m & lt) == 0) s_cnt[wave * 256 + dg] = prior + (uint32_t)__popcll(m);
+                __builtin_amdgcn_wave_barrier();
+            }
+            __syncthreads();
+            // per digit: waves' offsets inside the chunk, then advance the run offset
+            if (threadIdx.x < 256) {
+                uint32_t run = 0;
+                for (int w = 0; w < kFixWaves; ++w) {
+                    const uint32_t t = s_cnt[w * 256 + threadIdx.x];
+                    s_cnt[w * 256 + threadIdx.x] = run + s_off[threadIdx.x];
+                    run += t;
+                }
+                s_off[threadIdx.x] += run;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kKeysPerLane; ++r) {
+                const int64_t i = wb + (int64_t)r * kWave + lane;
+                if (i < b) {
+                    const uint32_t dg = (uint32_t)(v[r] >> shift) & 255u;
+                    dst[a + s_cnt[wave * 256 + dg] + rk[r]] = v[r];
+                }
+            }
+            __syncthreads();
+        }
+        uint64_t* t = src;
+        src = dst;
+        dst = t;
+    }
+}
+
+// Sorts by pay every run whose start bit is set.  Blocks take chunks of
+// 32768 ranks (1024 bitmap words, 64 per wave); a wave sorts the runs of at
+// most 64 that start in its words at once, and hands longer ones to the block,
+// which sorts them after the chunk's small runs, in LDS up to kFixLds, else
+// through alt.
+__global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __restrict__ hi,
+                                                          uint64_t* __restrict__ pay, uint64_t* __restrict__ alt,
+                                                          int64_t n, const uint32_t* __restrict__ bits) {
+    __shared__ uint64_t s_run[kFixLds];
+    __shared__ int64_t s_list[kFixList];
+    __shared__ int64_t s_pos;
+    __shared__ uint32_t s_nlist;
+    __shared__ uint32_t s_off[256];
+    __shared__ uint32_t s_scan[kFixWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t words = (n + 31) >> 5;
+    constexpr int64_t kChunkWords = (int64_t)kFixWaves * kWave;
+    for (int64_t cw = (int64_t)blockIdx.x * kChunkWords; cw < words; cw += (int64_t)gridDim.x * kChunkWords) {
+        if (threadIdx.x == 0) s_nlist = 0;
+        __syncthreads();
+        const int64_t wi = cw + (int64_t)wave * kWave + lane;
+        uint32_t word = wi < words ? bits[wi] : 0u;
+        uint64_t pending = __ballot(word != 0);
+        while (pending) {
+            const int src_lane = __ffsll((unsigned long long)pending) - 1;
+            uint32_t wsrc = __shfl(word, src_lane, kWave);
+            const int64_t wbase = (cw + (int64_t)wave * kWave + src_lane) << 5;
+            while (wsrc) {
+                const int bit = __ffs(wsrc) - 1;
+                wsrc &= wsrc - 1;
+                const int64_t a = wbase + bit;
+                const uint32_t h = hi[a];
+                const int64_t r = a + lane;
+                const bool in = r < n && hi[r] == h;
+                const uint64_t inm = __ballot(in);
+                if (inm == ~0ull) {
+                    if (lane == 0) {
+                        const uint32_t slot = atomicAdd(&s_nlist, 1u);
+                        if (slot < kFixList) s_list[slot] = a;
+                    }
+                } else {
+                    // run of length < 64: lanes below the first differing lane
+                    const int len = __ffsll((unsigned long long)~inm) - 1;
+                    const bool mine = lane < len;
+                    uint64_t v = mine ? pay[r] : ~0ull;
+                    v = wave_bitonic(v);
+                    if (mine) pay[r] = v;
+                }
+            }
+            pending &= pending - 1;
+        }
+        __syncthreads();
+        const uint32_t nl = s_nlist < kFixList ? s_nlist : kFixList;
+        for (uint32_t q = 0; q < nl; ++q) {
+            const int64_t a = s_list[q];
+            const int64_t b = block_run_end(hi, n, a, &s_pos);
+            const int64_t len = b - a;
+            if (len <= kFixLds) {
+                int p2 = 128;
+                while (p2 < len) p2 <<= 1;
+                for (int i = threadIdx.x; i < p2; i += kFixThreads) s_run[i] = i < len ? pay[a + i] : ~0ull;
+                __syncthreads();
+                for (int k = 2; k <= p2; k <<= 1) {
+                    for (int j = k >> 1; j > 0; j >>= 1) {
+                        for (int i = threadIdx.x; i < p2; i += kFixThreads) {
+                            const int l = i ^ j;
+                            if (l > i) {
+                                const uint64_t x = s_run[i], y = s_run[l];
+                                const bool up = (i & k) == 0;
+                                if ((x > y) == up) {
+                                    s_run[i] = y;
+                                    s_run[l] = x;
+                                }
+                            }
+                        }
+                        __syncthreads();
+                    }
+                }
+                for (int i = threadIdx.x; i < len; i += kFixThreads) pay[a + i] = s_run[i];
+                __syncthreads();
+            } else {
+                block_lsd_run(pay, alt, a, b, reinterpret_cast<uint32_t*>(s_run), s_off, s_scan);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 int64_t sort_blocks(int64_t n) { return (n + kTileKeys - 1) / kTileKeys; }
+int64_t tie_words(int64_t n) { return ((n + 31) >> 5) + 2; }  // u32 bitmap words (even)
 
-}  // namespace
-
-size_t radix_workspace_bytes(int64_t n) {
-    const int64_t nb = sort_blocks(n);
-    Sizer s;
-    s.take<uint64_t>((size_t)kPasses * nb * kRadix + kHistCopies * kPasses * kRadix / 2 + kPasses);
-    s.take<int32_t>(1);
-    return s.used + 256;
-}
-
-// Zeroes the look-back words, histograms and tickets (one kernel), counts all
-// passes' digits (unless the caller already did, hist_ready), then runs the
-// 8 passes.  The result ends in keys/vals.
-mh_status radix_sort_u64_hist(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                              uint32_t* hist, uint64_t* status, uint32_t* tickets, int32_t* err,
-                              bool hist_ready, hipStream_t stream) {
-    const int64_t nb = sort_blocks(n);
-    if (!hist_ready) {
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, keys, n, hist);
-        MH_HIP_TRY(hipGetLastError());
-    }
-    // One tile per CU at most: the column exchange (all tiles resident, with a
-    // CU to spare for each); otherwise the look-back, by ticket unless the
-    // whole grid is resident.
-    const bool xchg = nb <= kXchgTiles && nb <= device_cus();
-    const bool use_ticket = !xchg && nb > resident_blocks(k_onesweep<false>, kSortThreads);
-    uint64_t* kin = keys;
-    uint32_t* vin = vals;
-    uint64_t* kout = keys_alt;
-    uint32_t* vout = vals_alt;
-    for (int pass = 0; pass < kPasses; ++pass) {
-        hipLaunchKernelGGL(xchg ? k_onesweep<true> : k_onesweep<false>, dim3((unsigned)nb), dim3(kSortThreads), 0,
-                           stream, kin, vin, kout, vout, n, pass * 8, hist + pass * kRadix,
-                           status + (int64_t)pass * nb * kRadix, tickets + pass, use_ticket, err);
-        MH_HIP_TRY(hipGetLastError());
-        uint64_t* tk = kin; kin = kout; kout = tk;
-        uint32_t* tv = vin; vin = vout; vout = tv;
-    }
-    return MH_OK;
-}
-
-// Layout of the sort's scratch: look-back words, then histograms and tickets.
+// Layout of the sort's scratch: look-back words, histograms and tickets, then
+// the tie-run bitmap (all zeroed by radix_prepare).
 struct SortScratch {
     uint64_t* status;
     uint32_t* hist;
     uint32_t* tickets;
+    uint32_t* bits;
     int32_t* err;
-    int64_t words;  // u64 words to zero (status + hist + tickets)
+    int64_t words;  // u64 words to zero
 };
 
-static SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) {
+SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) {
     const int64_t nb = sort_blocks(n);
     Arena ar(ws, ws_bytes);
     const int64_t status_words = (int64_t)kPasses * nb * kRadix;
-    const int64_t extra_words = kHistCopies * kPasses * kRadix / 2 + kPasses;
-    uint64_t* block = ar.take<uint64_t>(status_words + extra_words);
+    const int64_t hist_words = kHistCopies * kPasses * kRadix / 2 + kPasses;
+    const int64_t bit_words = tie_words(n) / 2;
+    uint64_t* block = ar.take<uint64_t>(status_words + hist_words + bit_words);
     int32_t* err = ar.take<int32_t>(1);
     *ok = !ar.overflow;
     SortScratch s{};
@@ -355,9 +566,20 @@ static SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) 
     s.status = block;
     s.hist = reinterpret_cast<uint32_t*>(block + status_words);
     s.tickets = s.hist + kHistCopies * kPasses * kRadix;
+    s.bits = reinterpret_cast<uint32_t*>(block + status_words + hist_words);
     s.err = err;
-    s.words = status_words + extra_words;
+    s.words = status_words + hist_words + bit_words;
     return s;
+}
+
+}  // namespace
+
+size_t radix_workspace_bytes(int64_t n) {
+    Sizer s;
+    s.take<uint64_t>((size_t)kPasses * sort_blocks(n) * kRadix + kHistCopies * kPasses * kRadix / 2 + kPasses +
+                     tie_words(n) / 2);
+    s.take<int32_t>(1);
+    return s.used + 256;
 }
 
 mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream,
@@ -376,15 +598,46 @@ mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, h
     return MH_OK;
 }
 
-mh_status radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                         void* ws, size_t ws_bytes, bool hist_ready, int32_t* err, hipStream_t stream) {
+mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint64_t* pay_alt, int64_t n,
+                             void* ws, size_t ws_bytes, int32_t* err, hipStream_t stream) {
     if (n <= 1) return MH_OK;
     if (n > (int64_t)0xFFFFFFFFll) return MH_EINVAL;
     bool ok = false;
     SortScratch s = sort_scratch(ws, ws_bytes, n, &ok);
     if (!ok) return MH_EWORKSPACE;
-    return radix_sort_u64_hist(keys, vals, keys_alt, vals_alt, n, s.hist, s.status, s.tickets, err ? err : s.err,
-                               hist_ready, stream);
+    if (!err) err = s.err;
+    const int64_t nb = sort_blocks(n);
+    // One tile per CU at most: the column exchange (all tiles resident, with a
+    // CU to spare for each); otherwise the look-back, by ticket unless the
+    // whole grid is resident.
+    const bool xchg = nb <= kXchgTiles && nb <= device_cus();
+    const bool use_ticket = !xchg && nb > resident_blocks(k_onesweep<false>, kSortThreads);
+    uint32_t* kin = hi;
+    uint64_t* vin = pay;
+    uint32_t* kout = hi_alt;
+    uint64_t* vout = pay_alt;
+    for (int pass = 0; pass < kPasses; ++pass) {
+        hipLaunchKernelGGL(xchg ? k_onesweep<true> : k_onesweep<false>, dim3((unsigned)nb), dim3(kSortThreads), 0,
+                           stream, kin, vin, kout, vout, n, pass * 8, s.hist + pass * kRadix,
+                           s.status + (int64_t)pass * nb * kRadix, s.tickets + pass, use_ticket, err);
+        MH_HIP_TRY(hipGetLastError());
+        uint32_t* tk = kin; kin = kout; kout = tk;
+        uint64_t* tv = vin; vin = vout; vout = tv;
+    }
+    static_assert(kPasses % 2 == 0, "the passes end in the input arrays");
+    // runs of equal high halves out of order by the low halves
+    const int64_t tie_grid_need = (n + kTieThreads - 1) / kTieThreads;
+    const int64_t tie_grid = tie_grid_need < 4096 ? tie_grid_need : 4096;
+    hipLaunchKernelGGL(k_tie_runs, dim3((unsigned)tie_grid), dim3(kTieThreads), 0, stream, (const uint32_t*)hi,
+                       (const uint64_t*)pay, n, s.bits);
+    MH_HIP_TRY(hipGetLastError());
+    const int64_t chunks = (((n + 31) >> 5) + (int64_t)kFixWaves * kWave - 1) / ((int64_t)kFixWaves * kWave);
+    const int64_t cus = device_cus();
+    const int64_t fix_grid = chunks < cus ? chunks : cus;
+    hipLaunchKernelGGL(k_fix_runs, dim3((unsigned)fix_grid), dim3(kFixThreads), 0, stream, (const uint32_t*)hi, pay,
+                       pay_alt, n, (const uint32_t*)s.bits);
+    MH_HIP_TRY(hipGetLastError());
+    return MH_OK;
 }
 
 }  // namespace mh

@@ -93,6 +93,44 @@ def test_order_beyond_count_tiles_matches_oracle(mh):
     assert np.array_equal(perm.cpu().numpy(), oracle.order(x))
 
 
+def _cluster(rng, base, count, dups=0):
+    # distinct values base * (1 + k 2^-52), k < 2^32, base a power of two: they
+    # share the high half of their sort key; `dups` of them repeated (ties of
+    # the whole key)
+    v = base * (1.0 + rng.choice(1 << 32, size=count, replace=False).astype(np.float64) * 2.0**-52)
+    if dups:
+        v = np.concatenate([v, rng.choice(v, size=dups)])
+    return v
+
+
+@pytest.mark.parametrize("case", ["small", "lds", "giant", "edges", "mixed"])
+def test_order_high_half_ties_matches_oracle(mh, case):
+    # keys that tie in their high 32 bits but not in their low ones: the sort
+    # passes order only the high halves, the repair kernel the rest (a wave per
+    # run of at most 64, LDS up to 8192, a block's LSD beyond)
+    rng = np.random.default_rng(["small", "lds", "giant", "edges", "mixed"].index(case) + 40)
+    if case == "small":
+        x = rng.lognormal(-4, 1.5, 300_000)  # tens of thousands of short runs
+    elif case == "lds":
+        x = np.concatenate([_cluster(rng, 0.5, 5000, 300), rng.lognormal(-3, 1, 60_000)])
+    elif case == "giant":
+        x = np.concatenate([_cluster(rng, 0.25, 50_000, 2000), rng.lognormal(-3, 1, 150_000),
+                            _cluster(rng, 2.0, 9000)])
+    elif case == "edges":
+        # run lengths around the wave and LDS limits, one run at each end
+        parts = [_cluster(rng, 2.0 ** (4 - i), c) for i, c in enumerate([64, 65, 63, 8192, 8193, 2, 8191])]
+        x = np.concatenate(parts + [np.full(1000, 1e-3), _cluster(rng, 2.0**-12, 100)])
+    else:
+        x = np.concatenate([rng.lognormal(-4, 1.5, 100_000), _cluster(rng, 0.5, 3000, 3000),
+                            np.round(rng.lognormal(-2, 1, 100_000), 4), _cluster(rng, 0.125, 20_000)])
+    x = x[rng.permutation(len(x))]
+    perm, zs, _, status = mh.order(dev(x))
+    assert int(status.item()) == 0
+    ref = oracle.order(x)
+    assert np.array_equal(perm.cpu().numpy(), ref)
+    assert np.array_equal(zs.cpu().numpy(), x[ref])
+
+
 def test_order_weighted_key_is_rounded_product(mh):
     rng = np.random.default_rng(3)
     n = 20_000
