@@ -9,7 +9,9 @@ The timed samples are issued back to back on one stream through the
 asynchronous entry point (no host round trip between samples) and the clock
 stops after the stream has drained; their edge counts come from an untimed
 repeat of the same samples, which are identical (counter-based randomness; the
-last one is checked against the timed run's own count).
+last one is checked against the timed run's own count).  The timed samples
+record events only around the sweep; the order and plan stage times come from
+the repeat.
 
 Prints one JSON line (rank 0, one GPU).
 """
@@ -44,17 +46,26 @@ SWEEP_VALU_PER_STEP = 313
 
 
 class HipEvents:
-    def __init__(self, n: int):
+    """Timing events without the system-scope fence at record time (the stream
+    is synchronised before they are read), so that recording one does not
+    write back and invalidate the caches between the kernels it separates."""
+
+    DISABLE_SYSTEM_FENCE = 0x20000000
+
+    def __init__(self, n: int, present=None):
+        """n slots; present(i) false leaves slot i NULL (a stage not timed)."""
         self.rt = ctypes.CDLL("libamdhip64.so")
-        self.rt.hipEventCreate.argtypes = [ctypes.c_void_p]
+        self.rt.hipEventCreateWithFlags.argtypes = [ctypes.c_void_p, ctypes.c_uint]
         self.rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
         self.rt.hipEventSynchronize.argtypes = [ctypes.c_void_p]
         self.arr = (ctypes.c_void_p * n)()
         for i in range(n):
+            if present is not None and not present(i):
+                continue
             ev = ctypes.c_void_p()
-            rc = self.rt.hipEventCreate(ctypes.byref(ev))
+            rc = self.rt.hipEventCreateWithFlags(ctypes.byref(ev), self.DISABLE_SYSTEM_FENCE)
             if rc != 0:
-                raise RuntimeError("hipEventCreate failed")
+                raise RuntimeError("hipEventCreateWithFlags failed")
             self.arr[i] = ev.value
 
     @property
@@ -232,8 +243,12 @@ def main():
     cap = int(len(s0) * 1.05) + 65536
     src = torch.empty(cap, dtype=torch.int32, device=dev)
     dst = torch.empty(cap, dtype=torch.int32, device=dev)
-    ev = HipEvents(4 * args.steps)
+    # Timed samples record 2 events each, around the sweep (the kernel the
+    # roofline is taken on); the order and plan stages are timed on the
+    # untimed repeat below, so that their events cost the timed run nothing.
+    ev = HipEvents(4 * args.steps, present=lambda i: i % 4 >= 2)
     ev_size = ctypes.sizeof(ctypes.c_void_p)
+    ev_stage = HipEvents(4 * args.steps)
 
     def step(replica, events=None):
         mh.sample_async(x, None, (src, dst), ws, seed=args.seed, replica=replica, seg_work=args.seg_work,
@@ -249,24 +264,25 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     last_edges = mh.sample_result(ws, cap)
-    stage = np.zeros(3)
-    for i in range(args.steps):
-        stage += [ev.elapsed_ms(4 * i, 4 * i + 1), ev.elapsed_ms(4 * i + 1, 4 * i + 2),
-                  ev.elapsed_ms(4 * i + 2, 4 * i + 3)]
+    sweep_ms = sum(ev.elapsed_ms(4 * i + 2, 4 * i + 3) for i in range(args.steps)) / args.steps
     ms_per_step = elapsed / args.steps * 1e3
 
-    # edges and algorithmic work of the timed samples (the same samples again, untimed)
+    # edges and algorithmic work of the timed samples (the same samples again,
+    # untimed), and the stage times of the order and plan steps
     steps_total = 0
     edges = 0
-    for r in replicas:
+    stage = np.zeros(3)
+    for i, r in enumerate(replicas):
         _, _, st = mh.sample_unweighted(x, seed=args.seed, replica=r, seg_work=args.seg_work, stats=True,
-                                        out=(src, dst), workspace=ws, grid_blocks=args.grid_blocks)
+                                        out=(src, dst), workspace=ws, grid_blocks=args.grid_blocks,
+                                        stage_events=ev_stage.address + 4 * i * ev_size)
+        stage += [ev_stage.elapsed_ms(4 * i, 4 * i + 1), ev_stage.elapsed_ms(4 * i + 1, 4 * i + 2),
+                  ev_stage.elapsed_ms(4 * i + 2, 4 * i + 3)]
         steps_total += st["steps"]
         edges += st["n_edges"]
     if st["n_edges"] != last_edges:
         raise RuntimeError(f"timed and repeated sample differ: {last_edges} vs {st['n_edges']} edges")
     value = edges / elapsed
-    sweep_ms = stage[2] / args.steps
     achieved_lane_ops = steps_total / args.steps * SWEEP_VALU_PER_STEP / (sweep_ms * 1e-3)
     roof = {"bound": "alu", "kernel": "k_sweep (unweighted)",
             "achieved": achieved_lane_ops / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
@@ -292,8 +308,7 @@ def main():
                                "back to back on one stream",
                    "n": n, "seg_work": args.seg_work, "mean_edges_per_sample": edges / args.steps,
                    "fit_residual": fit.residual},
-        "stages_ms": {"order": stage[0] / args.steps, "bound_plan": stage[1] / args.steps,
-                      "sweep": stage[2] / args.steps},
+        "stages_ms": {"order": stage[0] / args.steps, "bound_plan": stage[1] / args.steps, "sweep": sweep_ms},
         "sweep_steps_per_sample": steps_total / args.steps,
         "roofline": roof,
     }

@@ -64,7 +64,7 @@ typedef struct {
     /* Optional stage timing: NULL, or an array of MH_STAGE_EVENTS events made
      * by the caller (hipEventCreate).  The samplers record them on `stream` at
      * the start, after the order step, after the bound and plan steps, and after
-     * the sweep.  Recording adds no synchronisation. */
+     * the sweep; NULL entries are skipped.  Recording adds no synchronisation. */
     hipEvent_t* stage_events;
 } mh_plan_params;
 

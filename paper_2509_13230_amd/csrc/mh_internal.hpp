@@ -42,6 +42,12 @@ struct Sizer {
     }
 };
 
+// A range of u64 words for a zeroing kernel to clear (n = 0: none).
+struct ZeroRange {
+    uint64_t* p = nullptr;
+    int64_t n = 0;
+};
+
 #define MH_HIP_TRY(expr)                              \
     do {                                              \
         hipError_t e_ = (expr);                       \
@@ -87,9 +93,9 @@ size_t radix_workspace_bytes(int64_t n);
 // kRadixPasses x 256 counts of the bytes of hi (copy c, pass p, digit d at
 // [(c * kRadixPasses + p) * 256 + d]); a counting block adds into copy
 // blockIdx % kRadixHistCopies.
-// extra_zero / extra_words: another range of u64 words zeroed by the same kernel.
+// e1, e2: further ranges of u64 words zeroed by the same kernel.
 mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream,
-                        uint64_t* extra_zero = nullptr, int64_t extra_words = 0);
+                        ZeroRange e1 = {}, ZeroRange e2 = {});
 // Sorts hi[0..n) / pay[0..n) using alt buffers of the same size (the result
 // ends in hi / pay); the histograms must hold the counts.  err (optional,
 // device) receives MH_EHIP if a look-back or exchange ever stalls.
@@ -110,15 +116,15 @@ size_t order_workspace_bytes(int64_t n);
 // n + 1 entries): P[r] = sum of the column masses floor(z 2^32) (2^32 for
 // z >= 1) over ranks < r, P[n] = total; with node records this is computed in
 // the same pass, with the look-back state mass_state (lb_tiles(n) words that
-// must be zero when this call's first kernel has run: pass them inside
-// extra_zero), and then mass_samples (optional, lb_samples(n) words) receives
+// must be zero when this call's first kernel has run: pass them as e1 or
+// e2), and then mass_samples (optional, lb_samples(n) words) receives
 // P[256 k].  check_square: the largest z squared must be finite (one node
-// set, where it is the largest t).  extra_zero / extra_words: u64 words zeroed
-// by the first kernel (look-back state of later steps).
+// set, where it is the largest t).  e1, e2: u64 words zeroed by the first
+// kernel (look-back state of later steps, counters).
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
                       NodeRec* node, int32_t* status, uint64_t* mass_prefix, uint64_t* mass_state,
                       uint64_t* mass_samples, void* ws, size_t ws_bytes, hipStream_t stream,
-                      bool check_square = true, uint64_t* extra_zero = nullptr, int64_t extra_words = 0);
+                      bool check_square = true, ZeroRange e1 = {}, ZeroRange e2 = {});
 
 size_t bound_workspace_bytes(int64_t n);
 mh_status bound_suffix_top2(const double* ys, int64_t n, double* c, int32_t* status, void* ws, size_t ws_bytes,

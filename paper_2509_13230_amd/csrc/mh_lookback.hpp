@@ -17,18 +17,18 @@
 
 namespace mh {
 
-constexpr int kLbThreads = 256;
-constexpr int kLbItems = 16;
+constexpr int kLbThreads = 1024;
+constexpr int kLbItems = 4;
 constexpr int kLbTile = kLbThreads * kLbItems;  // 4096
 constexpr uint64_t kLbAgg = 1ull << 62;
 constexpr uint64_t kLbInc = 2ull << 62;
 constexpr uint64_t kLbValue = kLbAgg - 1;
 constexpr uint32_t kLbSpinLimit = 1u << 20;
 
-// Element i of a tile lives at items[lb_at(i)]: one padding word per 16
-// elements, so that threads reading their 16 consecutive elements (a run of
-// 128 bytes each) hit distinct LDS banks.
-__host__ __device__ constexpr int lb_at(int i) { return i + (i >> 4); }
+// Element i of a tile lives at items[lb_at(i)]: one padding word per 4
+// elements, so that threads reading their 4 consecutive elements (a stride of
+// 5 words, 10 banks) hit distinct LDS banks.
+__host__ __device__ constexpr int lb_at(int i) { return i + (i >> 2); }
 
 struct LbShared {
     uint64_t items[lb_at(kLbTile)];

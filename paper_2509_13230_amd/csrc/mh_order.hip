@@ -13,27 +13,30 @@ namespace {
 constexpr int kThreads = 256;
 
 constexpr int kPrepTile = 4096;
+// 16 waves per tile of keys: the kernel is a chain of loads, histogram atomics
+// and stores with little arithmetic, which only more waves per CU overlap.
+constexpr int kPrepThreads = 1024;
 
 // Sort keys (complemented bits of z = x or x*y, split: high half as the radix
 // key, low half above the id as payload), checks of the parameters, and the
 // digit histograms of all radix passes.
-__global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict__ x, const double* __restrict__ y,
+__global__ __launch_bounds__(kPrepThreads) void k_prep_keys(const double* __restrict__ x, const double* __restrict__ y,
                                                         int64_t n, uint32_t* __restrict__ keys,
                                                         uint64_t* __restrict__ vals, uint32_t* __restrict__ hist,
                                                         int32_t* status) {
     constexpr int kHist = kRadixPasses * 256;
     __shared__ uint32_t h[kHist];
-    for (int i = threadIdx.x; i < kHist; i += kThreads) h[i] = 0;
+    for (int i = threadIdx.x; i < kHist; i += kPrepThreads) h[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kPrepTile;
     const int lane = threadIdx.x & 63;
-    constexpr int kPer = kPrepTile / kThreads;
+    constexpr int kPer = kPrepTile / kPrepThreads;
     // all loads first, then the keys and their counts
     double zv[kPer];
     bool okv[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        const int64_t i = base + (int64_t)q * kThreads + threadIdx.x;
+        const int64_t i = base + (int64_t)q * kPrepThreads + threadIdx.x;
         zv[q] = 0.0;
         okv[q] = true;
         if (i < n) {
@@ -51,7 +54,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict
     bool bad = false;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        const int64_t i = base + (int64_t)q * kThreads + threadIdx.x;
+        const int64_t i = base + (int64_t)q * kPrepThreads + threadIdx.x;
         const bool valid = i < n;
         uint32_t key = 0;
         if (valid) {
@@ -90,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_keys(const double* __restrict
     __syncthreads();
     // one of the histogram copies per block (the sort sums them)
     uint32_t* copy = hist + (blockIdx.x % kRadixHistCopies) * kHist;
-    for (int i = threadIdx.x; i < kHist; i += kThreads)
+    for (int i = threadIdx.x; i < kHist; i += kPrepThreads)
         if (h[i]) atomicAdd(&copy[i], h[i]);
 }
 
@@ -309,7 +312,7 @@ size_t order_workspace_bytes(int64_t n) {
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
                       NodeRec* node, int32_t* status, uint64_t* mass_prefix, uint64_t* mass_state,
                       uint64_t* mass_samples, void* ws, size_t ws_bytes, hipStream_t stream, bool check_square,
-                      uint64_t* extra_zero, int64_t extra_words) {
+                      ZeroRange e1, ZeroRange e2) {
     if (n <= 0) return MH_OK;
     Arena ar(ws, ws_bytes);
     uint32_t* keys = ar.take<uint32_t>(n);
@@ -321,10 +324,10 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
     void* sort_ws = ar.base + off;
     const size_t sort_bytes = ws_bytes > off ? ws_bytes - off : 0;
     uint32_t* hist = nullptr;
-    mh_status st = radix_prepare(sort_ws, sort_bytes, n, &hist, stream, extra_zero, extra_words);
+    mh_status st = radix_prepare(sort_ws, sort_bytes, n, &hist, stream, e1, e2);
     if (st != MH_OK) return st;
     const unsigned tiles = (unsigned)((n + kPrepTile - 1) / kPrepTile);
-    hipLaunchKernelGGL(k_prep_keys, dim3(tiles), dim3(kThreads), 0, stream, x, y, n, keys, vals, hist, status);
+    hipLaunchKernelGGL(k_prep_keys, dim3(tiles), dim3(kPrepThreads), 0, stream, x, y, n, keys, vals, hist, status);
     MH_HIP_TRY(hipGetLastError());
     st = radix_sort_split64(keys, vals, keys_alt, vals_alt, n, sort_ws, sort_bytes, status, stream);
     if (st != MH_OK) return st;

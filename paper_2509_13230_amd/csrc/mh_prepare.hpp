@@ -33,7 +33,8 @@ size_t prepare_scratch_bytes(int64_t n);
 NetDesc net_desc(const NetBuffers& B);
 mh_status init_counters(Counters* c, hipStream_t stream);
 // Records ev[1] after the order step when ev is non-null.
+// counters: u64 words (the sample's counters) for the first kernel to clear.
 mh_status prepare_network(const double* x, const double* y, const NetBuffers& B, int32_t* status, void* scratch,
-                          size_t scratch_bytes, hipStream_t stream, hipEvent_t* ev);
+                          size_t scratch_bytes, hipStream_t stream, hipEvent_t* ev, ZeroRange counters = {});
 
 }  // namespace mh

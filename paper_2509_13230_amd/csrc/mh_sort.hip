@@ -79,12 +79,13 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* lds_wa
     return before + inc - v;
 }
 
-// Zeroes two ranges of u64 words (the second may be empty).
-__global__ __launch_bounds__(kSortThreads) void k_zero_u64(uint64_t* __restrict__ p, int64_t n,
-                                                           uint64_t* __restrict__ q, int64_t m) {
+// Zeroes three ranges of u64 words (any may be empty).
+__global__ __launch_bounds__(kSortThreads) void k_zero_u64(ZeroRange a, ZeroRange b, ZeroRange c) {
     const int64_t stride = (int64_t)gridDim.x * kSortThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n; i += stride) p[i] = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < m; i += stride) q[i] = 0;
+    const int64_t t = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    for (int64_t i = t; i < a.n; i += stride) a.p[i] = 0;
+    for (int64_t i = t; i < b.n; i += stride) b.p[i] = 0;
+    for (int64_t i = t; i < c.n; i += stride) c.p[i] = 0;
 }
 
 template <bool XCHG>
@@ -583,16 +584,18 @@ size_t radix_workspace_bytes(int64_t n) {
 }
 
 mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream,
-                        uint64_t* extra_zero, int64_t extra_words) {
+                        ZeroRange e1, ZeroRange e2) {
     bool ok = false;
     SortScratch s = sort_scratch(ws, ws_bytes, n, &ok);
     if (!ok) return MH_EWORKSPACE;
-    if (!extra_zero) extra_words = 0;
-    const int64_t most = s.words > extra_words ? s.words : extra_words;
+    if (!e1.p) e1.n = 0;
+    if (!e2.p) e2.n = 0;
+    int64_t most = s.words > e1.n ? s.words : e1.n;
+    most = most > e2.n ? most : e2.n;
     int64_t blocks = (most + kSortThreads - 1) / kSortThreads;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), dim3(kSortThreads), 0, stream, s.status, s.words,
-                       extra_zero, extra_words);
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), dim3(kSortThreads), 0, stream,
+                       ZeroRange{s.status, s.words}, e1, e2);
     MH_HIP_TRY(hipGetLastError());
     *hist = s.hist;
     return MH_OK;

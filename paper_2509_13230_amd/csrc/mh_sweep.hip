@@ -314,15 +314,15 @@ mh_status init_counters(Counters* c, hipStream_t stream) {
 
 // Order (A1), bound (A2, weighted) and plan (A3) of one network into B.
 mh_status prepare_network(const double* x, const double* y, const NetBuffers& B, int32_t* status, void* scratch,
-                          size_t scratch_bytes, hipStream_t stream, hipEvent_t* ev) {
+                          size_t scratch_bytes, hipStream_t stream, hipEvent_t* ev, ZeroRange counters) {
     const int64_t n = B.n;
     if (n <= 0) return MH_OK;
     const bool seg = B.T > 0;
     mh_status st = order_nodes(x, B.weighted ? y : nullptr, n, nullptr, nullptr, B.ys, B.node, status, B.P,
-                               B.scan_state, B.Psamp, scratch, scratch_bytes, stream, true, B.scan_state,
-                               B.scan_words);
+                               B.scan_state, B.Psamp, scratch, scratch_bytes, stream, true,
+                               ZeroRange{B.scan_state, B.scan_words}, counters);
     if (st != MH_OK) return st;
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[1], stream));
+    if (ev && ev[1]) MH_HIP_TRY(hipEventRecord(ev[1], stream));
     if (B.weighted) {
         st = bound_suffix_top2(B.ys, n, B.c, status, scratch, scratch_bytes, stream);
         if (st != MH_OK) return st;
@@ -410,12 +410,14 @@ mh_status enqueue_sample(const double* x, const double* y, int64_t n, uint64_t s
     const size_t scratch_bytes = ws_bytes - off;
 
     hipEvent_t* ev = plan ? plan->stage_events : nullptr;
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[0], stream));
-    mh_status st = init_counters(ctr, stream);
-    if (st != MH_OK || n == 0) return st;
-    st = prepare_network(x, y, B, &ctr->status, scratch, scratch_bytes, stream, ev);
+    if (ev && ev[0]) MH_HIP_TRY(hipEventRecord(ev[0], stream));
+    // the counters are cleared by the order's first kernel (n > 0)
+    if (n == 0) return init_counters(ctr, stream);
+    static_assert(sizeof(Counters) % sizeof(uint64_t) == 0, "counters clear as u64 words");
+    mh_status st = prepare_network(x, y, B, &ctr->status, scratch, scratch_bytes, stream, ev,
+                                   ZeroRange{reinterpret_cast<uint64_t*>(ctr), (int64_t)(sizeof(Counters) / 8)});
     if (st != MH_OK) return st;
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[2], stream));
+    if (ev && ev[2]) MH_HIP_TRY(hipEventRecord(ev[2], stream));
 
     SweepLaunch A{};
     A.net = net_desc(B);
@@ -434,7 +436,7 @@ mh_status enqueue_sample(const double* x, const double* y, int64_t n, uint64_t s
         else launch_sweep<false, false>(A, n, gb, stream);
     }
     MH_HIP_TRY(hipGetLastError());
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[3], stream));
+    if (ev && ev[3]) MH_HIP_TRY(hipEventRecord(ev[3], stream));
     return MH_OK;
 }
 
@@ -639,18 +641,18 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
     const bool seg = T > 0;
 
     hipEvent_t* ev = plan ? plan->stage_events : nullptr;
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[0], stream));
+    if (ev && ev[0]) MH_HIP_TRY(hipEventRecord(ev[0], stream));
     mh_status st = init_counters(ctr, stream);
     if (st != MH_OK) return st;
     // A1: each set sorted by its own z; the column masses for the plan
     // (the rows' first kernel zeroes the look-back state of both plan scans)
     st = order_nodes(xr, yr, nr, nullptr, nullptr, B.ysr, B.rows, status, nullptr, nullptr, nullptr, scratch,
-                     scratch_bytes, stream, false, B.scan_state, B.scan_words);
+                     scratch_bytes, stream, false, ZeroRange{B.scan_state, B.scan_words});
     if (st != MH_OK) return st;
     st = order_nodes(xc, yc, nc, nullptr, nullptr, B.ysc, B.cols, status, B.P, B.scan_state, B.Psamp, scratch,
                      scratch_bytes, stream, false);
     if (st != MH_OK) return st;
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[1], stream));
+    if (ev && ev[1]) MH_HIP_TRY(hipEventRecord(ev[1], stream));
     // A2: row bounds and the joint checks
     if (weighted) {
         hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, stream, B.ymax);
@@ -678,7 +680,7 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
                            (const uint64_t*)(samples ? B.Psamp : nullptr), (const int32_t*)status);
         MH_HIP_TRY(hipGetLastError());
     }
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[2], stream));
+    if (ev && ev[2]) MH_HIP_TRY(hipEventRecord(ev[2], stream));
 
     SweepLaunch A{};
     A.net = D;
@@ -697,7 +699,7 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
         else launch_sweep<false, false, true>(A, nr, gb, stream);
     }
     MH_HIP_TRY(hipGetLastError());
-    if (ev) MH_HIP_TRY(hipEventRecord(ev[3], stream));
+    if (ev && ev[3]) MH_HIP_TRY(hipEventRecord(ev[3], stream));
 
     Counters hc;
     MH_HIP_TRY(hipMemcpyAsync(&hc, ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
