@@ -38,11 +38,12 @@ METRIC = "sampled edges/s (unweighted, N=1M) + replicas/s batched vs plain, same
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
-# VALU instructions of one step of the sweep on its common path (Philox block,
-# the two uniforms, log and log1p, the skip division, the candidate load and
-# the acceptance test), counted in the gfx950 code of k_sweep<false,false>;
-# loop, refill and staging instructions are not counted as work.
-SWEEP_VALU_PER_STEP = 313
+# VALU instructions of one step of the sweep on its common path, counted in the
+# gfx950 code of k_sweep<false,false>: the draw (Philox block, the two
+# uniforms, the log of U1) 126, the acceptance test 15, the skip (log1p, the
+# division, the next candidate's address) 76, the candidate load 1; loop,
+# refill and staging instructions are not counted as work.
+SWEEP_VALU_PER_STEP = 218
 
 
 class HipEvents:

@@ -121,7 +121,13 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
     uint64_t v[kKeysPerLane];
     uint32_t rank[kKeysPerLane];
     // all loads first: the ranking below orders LDS accesses with wave barriers,
-    // which the compiler will not move loads across
+    // which the compiler will not move loads across.  With them, this digit's
+    // count over all keys (the histogram copies): its latency hides under the
+    // keys' instead of stalling the digit step after the ranking.
+    uint32_t hc[kHistCopies];
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c)
+        hc[c] = threadIdx.x < kRadix ? ghist[c * kPasses * kRadix + threadIdx.x] : 0u;
 #pragma unroll
     for (int r = 0; r < kKeysPerLane; ++r) {
         const int64_t i = base + (int64_t)r * kWave + lane;
@@ -157,7 +163,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
         __hip_atomic_store(st, (tile == 0 && !XCHG ? kFlagPrefix : kFlagAggregate) | total, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
-        for (int c = 0; c < kHistCopies; ++c) dtotal += ghist[c * kPasses * kRadix + d];
+        for (int c = 0; c < kHistCopies; ++c) dtotal += hc[c];
     }
     const uint32_t bstart = block_exclusive(total, s_scan);
     const uint32_t dstart = block_exclusive(dtotal, s_scan);

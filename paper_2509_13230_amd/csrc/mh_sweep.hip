@@ -170,30 +170,47 @@ __global__ __launch_bounds__(kHrThreads) void k_heavy_records(NetDesc D, HeavyRe
             const int64_t ns = nsg - nd;
             const uint64_t pb = D.P[J];
             const uint64_t m = D.mq[r];
-            int64_t cut[2];
+            // The segment's two cuts: first j in [J, nc) with P[j] >= v (nc if
+            // none), v = pb + k m for k = kk, kk + 1; the first cut of the row
+            // is J and the last nc.  Both searches advance in lockstep, so
+            // their dependent loads overlap: bracket from the LDS samples,
+            // P[(q-1) ps] < v <= P[q ps], then binary search in global memory.
+            int64_t lo[2], hi[2];
+            uint64_t v[2];
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const int64_t k2 = kk + e;
+                v[e] = pb + (uint64_t)k2 * m;
                 if ((e == 0 && k2 == 0) || (e == 1 && k2 == ns)) {
-                    cut[e] = (e == 0) ? J : nc;
+                    lo[e] = hi[e] = (e == 0) ? J : nc;
                     continue;
                 }
-                // first j in [J, nc) with P[j] >= v (nc if none); P[(q-1) ps] < v <= P[q ps]
-                const uint64_t v = pb + (uint64_t)k2 * m;
                 int ql = 0, qh = (int)np;
                 while (ql < qh) {
                     const int mid = (ql + qh) >> 1;
-                    if (s_p[mid] >= v) qh = mid; else ql = mid + 1;
+                    if (s_p[mid] >= v[e]) qh = mid; else ql = mid + 1;
                 }
                 int64_t clo = J, chi = nc;
                 if (ql > 0 && (int64_t)(ql - 1) * ps + 1 > clo) clo = (int64_t)(ql - 1) * ps + 1;
                 if (ql < (int)np && (int64_t)ql * ps < chi) chi = (int64_t)ql * ps;
                 if (clo > nc) clo = nc;
                 if (chi < clo) chi = clo;
-                cut[e] = lower_bound_u64(D.P, clo, chi, v);
+                lo[e] = clo;
+                hi[e] = chi;
             }
-            a = cut[0];
-            b = cut[1];
+            while (lo[0] < hi[0] || lo[1] < hi[1]) {
+                const int64_t m0 = lo[0] + (hi[0] - lo[0]) / 2, m1 = lo[1] + (hi[1] - lo[1]) / 2;
+                const bool a0 = lo[0] < hi[0], a1 = lo[1] < hi[1];
+                const uint64_t p0 = a0 ? D.P[m0] : 0, p1 = a1 ? D.P[m1] : 0;
+                if (a0) {
+                    if (p0 >= v[0]) hi[0] = m0; else lo[0] = m0 + 1;
+                }
+                if (a1) {
+                    if (p1 >= v[1]) hi[1] = m1; else lo[1] = m1 + 1;
+                }
+            }
+            a = lo[0];
+            b = lo[1];
         }
         rec[it] = HeavyRec{(int32_t)r, (int32_t)g, (int32_t)a, (int32_t)b};
     }

@@ -210,7 +210,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
         double E = 0.0, U2n = 0.0;
         if (draws) {
             const u32x4 R = philox4x32_10(step, (uint32_t)r, replica, tag, A.key0, A.key1);
-            E = -log(uniform53(R.v0, R.v1));
+            E = -log_fast(uniform53(R.v0, R.v1));
             U2n = uniform53(R.v2, R.v3);
         }
         // 2. consume the loads of the previous iteration
@@ -238,7 +238,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
                         wt = 1;
                     } else {
                         const u32x4 V = philox4x32_10(scand, (uint32_t)r, replica, tag | 1u, A.key0, A.key1);
-                        const double ratio = log(uniform53(V.v0, V.v1)) / log(bb);
+                        const double ratio = log_fast(uniform53(V.v0, V.v1)) / log_fast(bb);
                         if (ratio >= 2147483646.0) {
                             wt = 0x7FFFFFFF;
                             ++st_sat;
@@ -303,7 +303,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
             bool ended = true;
             if (tq != 0.0) {
                 ++st_steps;
-                const double lq = WEIGHTED ? log1p(tq / cr) : log1p(tq);
+                const double lq = WEIGHTED ? log1p_fast(tq / cr) : log1p_fast(tq);
                 const double d = E / lq;
                 const double room = (double)(end - 1 - pos);
                 if (d < room) {
