@@ -20,8 +20,8 @@ struct NetBuffers {
     int64_t rec_cap;
     uint64_t* scan_state;  // look-back state of the two plan scans (P, then hoff)
     int64_t scan_words;
-    uint64_t* Psamp;       // P[256 k] and hoff[256 k] (written by the one-pass scans)
-    uint64_t* Hsamp;
+    uint64_t* Psamp;       // P[256 k] (written by the order's one-pass scan)
+    int32_t* hbrow;        // first row of every round of heavy items (written by the plan's scan)
     int64_t n;
     int32_t T;
     bool weighted;

@@ -102,14 +102,53 @@ __global__ __launch_bounds__(kThreads) void k_row_plan(NodeRec* __restrict__ nod
     if (hn) hn[r] = total >= 2 ? (uint64_t)total : 0ull;
 }
 
-// Records {row, segment, column range} of the first rec_cap heavy items, the
-// same as heavy_record() computes them.  Hsamp / Psamp (null: plain searches)
-// hold hoff[256 k] and P[256 k]; a block stages them in LDS (every step-th one
-// when there are more than kHrSamples), so each search takes its bracket from
-// LDS and ends with a short binary search in global memory.
-constexpr int kHrSamples = 4096;
-constexpr int kHrThreads = 1024;  // items per block round; a grid of one round per item
+// Heavy items are recorded in rounds of kHrThreads, one item per thread.
+constexpr int kHrThreads = 1024;
+constexpr int kHrSamples = 4096;  // P samples a block stages in LDS
+constexpr int kHrRows = 4096;     // rows of hoff a block stages in LDS
 
+// Prefix sums hoff of the heavy-item counts (one look-back pass, as
+// k_scan_onepass).  For every round of kHrThreads stored items, the row that
+// holds the round's first item goes to hbrow[round] (each row writes the
+// rounds that begin inside it: at most a few stores per row).
+__global__ __launch_bounds__(kLbThreads) void k_scan_heavy(uint64_t* hoff, int64_t n, int64_t tiles,
+                                                           uint64_t* state, int32_t* __restrict__ hbrow,
+                                                           int64_t rec_cap, int32_t* err) {
+    __shared__ LbShared sh;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t base = tile * kLbTile;
+        uint64_t cnt[kLbItems];
+#pragma unroll
+        for (int k = 0; k < kLbItems; ++k) {
+            const int idx = k * kLbThreads + threadIdx.x;
+            const int64_t i = base + idx;
+            cnt[k] = (i < n) ? hoff[i] : 0ull;
+            sh.items[lb_at(idx)] = cnt[k];
+        }
+        const uint64_t end = lb_tile_scan(sh, tile, state, err);
+#pragma unroll
+        for (int k = 0; k < kLbItems; ++k) {
+            const int idx = k * kLbThreads + threadIdx.x;
+            const int64_t i = base + idx;
+            if (i < n) {
+                const uint64_t v = sh.items[lb_at(idx)];
+                hoff[i] = v;
+                const uint64_t stop = v + cnt[k] < (uint64_t)rec_cap ? v + cnt[k] : (uint64_t)rec_cap;
+                for (uint64_t b = (v + kHrThreads - 1) / kHrThreads; b * kHrThreads < stop; ++b)
+                    hbrow[b] = (int32_t)i;
+            }
+        }
+        if (threadIdx.x == 0 && base + kLbTile >= n) hoff[n] = end;
+    }
+}
+
+// Row and column range of the first rec_cap heavy items, the same as
+// heavy_record() computes them.  With hbrow and Psamp (P[256 k]): a block takes
+// a round of items, stages hoff over the rows from the round's first row on
+// (one contiguous load) and the P samples (every step-th one when there are
+// more than kHrSamples) in LDS, so each item finds its row in LDS and each cut
+// search takes its bracket from LDS and ends with a short binary search in
+// global memory.  Otherwise each record is computed whole by plain searches.
 __device__ __forceinline__ int64_t first_above_u64(const uint64_t* __restrict__ a, int64_t lo, int64_t hi, uint64_t v) {
     while (lo < hi) {  // first index in [lo, hi) with a[i] > v (hi if none)
         const int64_t mid = lo + (hi - lo) / 2;
@@ -119,16 +158,16 @@ __device__ __forceinline__ int64_t first_above_u64(const uint64_t* __restrict__ 
 }
 
 __global__ __launch_bounds__(kHrThreads) void k_heavy_records(NetDesc D, HeavyRec* __restrict__ rec,
-                                                            const uint64_t* __restrict__ Hsamp,
                                                             const uint64_t* __restrict__ Psamp,
+                                                            const int32_t* __restrict__ hbrow,
                                                             const int32_t* status) {
-    __shared__ uint64_t s_h[kHrSamples];
     __shared__ uint64_t s_p[kHrSamples];
+    __shared__ uint64_t s_h[kHrRows + 1];
     if (*status != 0) return;
     const int64_t H = heavy_items(D);
     const int64_t lim = H < D.rec_cap ? H : D.rec_cap;
     if ((int64_t)blockIdx.x * kHrThreads >= lim) return;  // the grid is sized for rec_cap items
-    if (!Hsamp || !Psamp) {
+    if (!hbrow || !Psamp) {
         for (int64_t it = (int64_t)blockIdx.x * kHrThreads + threadIdx.x; it < lim;
              it += (int64_t)gridDim.x * kHrThreads)
             rec[it] = heavy_record(D, it);
@@ -136,28 +175,36 @@ __global__ __launch_bounds__(kHrThreads) void k_heavy_records(NetDesc D, HeavyRe
     }
     const int64_t n = D.n, nc = D.ncol, T = D.T;
     const bool bip = (D.flags & NET_BIPARTITE) != 0;
-    // sample strides hs, ps (multiples of 256 rows / columns) and counts
-    int64_t hstep = 1, pstep = 1;
-    while (lb_samples(n) > hstep * (kHrSamples - 1) + 1) hstep *= 2;
+    // sample stride ps (a multiple of 256 columns) and count
+    int64_t pstep = 1;
     while (lb_samples(nc) > pstep * (kHrSamples - 1) + 1) pstep *= 2;
-    const int64_t nh = (lb_samples(n) - 1) / hstep + 1, np = (lb_samples(nc) - 1) / pstep + 1;
-    const int64_t hs = hstep << kSampleShift, ps = pstep << kSampleShift;
-    for (int64_t j = threadIdx.x; j < nh; j += kHrThreads) s_h[j] = Hsamp[j * hstep];
+    const int64_t np = (lb_samples(nc) - 1) / pstep + 1;
+    const int64_t ps = pstep << kSampleShift;
     for (int64_t j = threadIdx.x; j < np; j += kHrThreads) s_p[j] = Psamp[j * pstep];
-    __syncthreads();
-    for (int64_t it = (int64_t)blockIdx.x * kHrThreads + threadIdx.x; it < lim;
-         it += (int64_t)gridDim.x * kHrThreads) {
-        // row: first index with hoff > it, minus one; hoff[(q-1) hs] <= it < hoff[q hs]
-        int lo = 1, hi = (int)nh;  // first sample > it (s_h[0] = 0 <= it)
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_h[mid] > (uint64_t)it) hi = mid; else lo = mid + 1;
+    for (int64_t round = blockIdx.x; round * kHrThreads < lim; round += gridDim.x) {
+        const int64_t R0 = hbrow[round];
+        __syncthreads();  // s_h of the previous round is no longer read
+        for (int j = threadIdx.x; j <= kHrRows; j += kHrThreads)
+            s_h[j] = R0 + j <= n ? D.hoff[R0 + j] : ~0ull;
+        __syncthreads();
+        const int64_t it = round * kHrThreads + threadIdx.x;
+        if (it >= lim) continue;
+        // row: hoff[r] <= it < hoff[r + 1], from the staged rows R0 .. R0 + kHrRows
+        int rl = 1, ru = kHrRows + 1;  // first staged index with hoff > it (s_h[0] <= it)
+        while (rl < ru) {
+            const int mid = (rl + ru) >> 1;
+            if (s_h[mid] > (uint64_t)it) ru = mid; else rl = mid + 1;
         }
-        const int64_t glo = (int64_t)(lo - 1) * hs + 1;
-        const int64_t ghi = lo < (int)nh ? (int64_t)lo * hs : n;
-        const int64_t r = first_above_u64(D.hoff, glo, ghi, (uint64_t)it) - 1;
-        const int64_t g = it - (int64_t)D.hoff[r];
-        const int64_t nsg = (int64_t)(D.hoff[r + 1] - D.hoff[r]);
+        int64_t r, g, nsg;
+        if (rl <= kHrRows) {
+            r = R0 + rl - 1;
+            g = it - (int64_t)s_h[rl - 1];
+            nsg = (int64_t)(s_h[rl] - s_h[rl - 1]);
+        } else {  // a round spread over more rows than staged (rows without items in between)
+            r = first_above_u64(D.hoff, R0 + kHrRows, n + 1, (uint64_t)it) - 1;
+            g = it - (int64_t)D.hoff[r];
+            nsg = (int64_t)(D.hoff[r + 1] - D.hoff[r]);
+        }
         const int64_t J = D.jend[r];
         const int64_t first = bip ? 0 : r + 1;
         const int64_t nd = (J - first + T - 1) / T;
@@ -227,21 +274,31 @@ static unsigned heavy_grid(int64_t rec_cap) {
 }
 
 // A3: segment counts of every row (and J, m) and, when segmented, the prefix
-// sums hoff of the heavy rows' counts (one look-back kernel while the sums stay
-// below 2^62, which holds for up to 2^30 rows; three kernels beyond).  The row
-// plan itself runs one row per thread: hub rows binary-search their dense end,
-// and a thread working through many rows would serialize those searches.
+// sums hoff of the heavy rows' counts.  While the sums stay below 2^62 (up to
+// 2^30 rows) one look-back kernel scans them and writes the first row of every
+// round of stored heavy items to hbrow (rows_known); beyond, three scan kernels.  The row plan itself
+// runs one row per thread: hub rows binary-search their dense end, and a
+// thread working through many rows would serialize those searches.
 static mh_status plan_rows(NodeRec* node, const double* c, int64_t n, const NodeRec* col, int64_t nc, int32_t bip,
                            int32_t T, const uint64_t* P, int32_t* jend, uint64_t* mq, uint64_t* hoff,
-                           uint64_t* hoff_state, uint64_t* hoff_samples, int32_t* status, void* scratch,
-                           size_t scratch_bytes, hipStream_t stream) {
+                           uint64_t* hoff_state, int32_t* hbrow, int64_t rec_cap, int32_t* status, void* scratch,
+                           size_t scratch_bytes, bool* rows_known, hipStream_t stream) {
+    *rows_known = false;
     const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_row_plan, dim3(grid), dim3(kThreads), 0, stream, node, c, n, col, nc, bip, T, P, jend, mq,
                        hoff);
     MH_HIP_TRY(hipGetLastError());
     if (!hoff) return MH_OK;
-    if (n <= (int64_t)1 << 30)
-        return scan_exclusive_u64_onepass(hoff, hoff, n, hoff_state, hoff_samples, status, stream);
+    if (n <= (int64_t)1 << 30) {
+        const int64_t tiles = lb_tiles(n);
+        const int64_t resident = resident_blocks(k_scan_heavy, kLbThreads);
+        const int64_t sgrid = tiles < resident ? tiles : resident;
+        hipLaunchKernelGGL(k_scan_heavy, dim3((unsigned)sgrid), dim3(kLbThreads), 0, stream, hoff, n, tiles,
+                           hoff_state, hbrow, rec_cap, status);
+        MH_HIP_TRY(hipGetLastError());
+        *rows_known = true;
+        return MH_OK;
+    }
     return scan_exclusive_u64(hoff, hoff, n, scratch, scratch_bytes, stream);
 }
 
@@ -262,11 +319,11 @@ static NetBuffers carve_network_impl(A& ar, int64_t n, bool weighted, int32_t T)
     B.scan_words = seg ? 2 * lb_tiles(n) : 0;
     B.scan_state = ar.template take<uint64_t>(B.scan_words);
     B.Psamp = ar.template take<uint64_t>(seg ? lb_samples(n) : 0);
-    B.Hsamp = ar.template take<uint64_t>(seg ? lb_samples(n) : 0);
+    B.hbrow = ar.template take<int32_t>(seg ? B.rec_cap / kHrThreads + 2 : 0);
     if (!weighted) B.ys = B.c = nullptr;
     if (!seg)
         B.P = nullptr, B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.scan_state = nullptr, B.Psamp = nullptr,
-        B.Hsamp = nullptr;
+        B.hbrow = nullptr;
     B.n = n;
     B.T = T;
     B.weighted = weighted;
@@ -344,15 +401,16 @@ mh_status prepare_network(const double* x, const double* y, const NetBuffers& B,
         st = bound_suffix_top2(B.ys, n, B.c, status, scratch, scratch_bytes, stream);
         if (st != MH_OK) return st;
     }
+    bool rows_known = false;
     st = plan_rows(B.node, B.c, n, B.node, n, 0, B.T, B.P, B.jend, B.mq, B.hoff,
-                   seg ? B.scan_state + lb_tiles(n) : nullptr, B.Hsamp, status, scratch, scratch_bytes, stream);
+                   seg ? B.scan_state + lb_tiles(n) : nullptr, B.hbrow, B.rec_cap, status, scratch,
+                   scratch_bytes, &rows_known, stream);
     if (st != MH_OK) return st;
     if (seg) {
-        const bool samples = n <= (int64_t)1 << 30;  // written by the one-pass scans
+        // P's samples come from the one-pass scan of the order (up to 2^30 nodes), as rows_known
         hipLaunchKernelGGL(k_heavy_records, dim3(heavy_grid(B.rec_cap)), dim3(kHrThreads), 0, stream, net_desc(B),
-                           B.rec,
-                           (const uint64_t*)(samples ? B.Hsamp : nullptr),
-                           (const uint64_t*)(samples ? B.Psamp : nullptr), (const int32_t*)status);
+                           B.rec, (const uint64_t*)(rows_known ? B.Psamp : nullptr),
+                           (const int32_t*)(rows_known ? B.hbrow : nullptr), (const int32_t*)status);
         MH_HIP_TRY(hipGetLastError());
     }
     return MH_OK;
@@ -567,8 +625,8 @@ struct BipBuffers {
     unsigned long long* ymax;
     uint64_t* scan_state;  // look-back state: P scan over the columns, then hoff over the rows
     int64_t scan_words;
-    uint64_t* Psamp;  // P[256 k] over the columns, hoff[256 k] over the rows
-    uint64_t* Hsamp;
+    uint64_t* Psamp;  // P[256 k] over the columns
+    int32_t* hbrow;   // first row of every round of heavy items over the rows
 };
 
 template <typename A>
@@ -590,11 +648,11 @@ BipBuffers carve_bipartite(A& ar, int64_t nr, int64_t nc, bool weighted, int32_t
     B.scan_words = seg ? lb_tiles(nc) + lb_tiles(nr) : 0;
     B.scan_state = ar.template take<uint64_t>(B.scan_words);
     B.Psamp = ar.template take<uint64_t>(seg ? lb_samples(nc) : 0);
-    B.Hsamp = ar.template take<uint64_t>(seg ? lb_samples(nr) : 0);
+    B.hbrow = ar.template take<int32_t>(seg ? B.rec_cap / kHrThreads + 2 : 0);
     if (!weighted) B.ysr = B.c = B.ysc = nullptr;
     if (!seg)
         B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.P = nullptr, B.scan_state = nullptr, B.Psamp = nullptr,
-        B.Hsamp = nullptr;
+        B.hbrow = nullptr;
     return B;
 }
 
@@ -686,15 +744,17 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
                        (const unsigned long long*)B.ymax, B.c, status);
     MH_HIP_TRY(hipGetLastError());
     // A3: plan over the columns
+    bool rows_known = false;
     st = plan_rows(B.rows, B.c, nr, B.cols, nc, 1, T, B.P, B.jend, B.mq, B.hoff,
-                   seg ? B.scan_state + lb_tiles(nc) : nullptr, B.Hsamp, status, scratch, scratch_bytes, stream);
+                   seg ? B.scan_state + lb_tiles(nc) : nullptr, B.hbrow, B.rec_cap, status, scratch,
+                   scratch_bytes, &rows_known, stream);
     if (st != MH_OK) return st;
     const NetDesc D = bip_desc(B, nr, nc, T, flags);
     if (seg) {
-        const bool samples = nr <= (int64_t)1 << 30 && nc <= (int64_t)1 << 30;  // written by the one-pass scans
+        const bool samples = nc <= (int64_t)1 << 30;  // P's samples: the columns' one-pass scan
         hipLaunchKernelGGL(k_heavy_records, dim3(heavy_grid(B.rec_cap)), dim3(kHrThreads), 0, stream, D, B.rec,
-                           (const uint64_t*)(samples ? B.Hsamp : nullptr),
-                           (const uint64_t*)(samples ? B.Psamp : nullptr), (const int32_t*)status);
+                           (const uint64_t*)(samples ? B.Psamp : nullptr),
+                           (const int32_t*)(rows_known ? B.hbrow : nullptr), (const int32_t*)status);
         MH_HIP_TRY(hipGetLastError());
     }
     if (ev && ev[2]) MH_HIP_TRY(hipEventRecord(ev[2], stream));
