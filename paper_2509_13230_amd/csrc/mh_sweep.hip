@@ -50,27 +50,55 @@ __global__ void k_init_counters(Counters* c) {
 // s z_j >= c_r, cut every T columns; sparse part: [J, nc) cut where the column
 // mass (prefix sums P of floor(z 2^32)) reaches multiples of
 // m = floor(T c_r / s 2^32), the mass whose expected candidate count is ~T.
-__device__ inline int64_t row_plan_one(NodeRec* __restrict__ node, const double* __restrict__ c,
-                                       const NodeRec* __restrict__ col, int64_t nc, int32_t bip, int32_t T,
-                                       const uint64_t* __restrict__ P, int32_t* __restrict__ jend,
-                                       uint64_t* __restrict__ mq, int64_t r) {
+// J and m are stored for rows of two or more segments only (no other row reads
+// them).  One row per thread; a block that holds a row with a dense part (the
+// hubs, a few blocks at most) stages z of every zstep-th column in LDS, so the
+// search for J takes its bracket from LDS and ends with log2(zstep) loads.
+constexpr int kPlanThreads = 1024;
+constexpr int kPlanSamples = 4096;
+
+// z of every zstep-th column into LDS (zstep: the smallest power of two >= 256
+// that leaves at most kPlanSamples samples); returns zstep, sets *nz.
+__device__ __forceinline__ int64_t stage_col_samples(const NodeRec* __restrict__ col, int64_t nc, double* s_z,
+                                                     int64_t* nz) {
+    int64_t zstep = 256;
+    while ((nc - 1) / zstep + 1 > kPlanSamples) zstep *= 2;
+    *nz = (nc - 1) / zstep + 1;
+    for (int64_t q = threadIdx.x; q < *nz; q += blockDim.x) s_z[q] = col[q * zstep].z;
+    return zstep;
+}
+
+// J of a row with a dense part: first j in [first + 1, nc) with s z_j < cr
+// (nc if none), bracketed by the LDS samples, then a binary search.
+__device__ __forceinline__ int64_t dense_end(const NodeRec* __restrict__ col, int64_t nc, double s, double cr,
+                                             int64_t first, const double* s_z, int64_t nz, int64_t zstep) {
+    int ql = 0, qh = (int)nz;  // first sample where s z < cr
+    while (ql < qh) {
+        const int mid = (ql + qh) >> 1;
+        if (s * s_z[mid] < cr) qh = mid; else ql = mid + 1;
+    }
+    int64_t lo = first + 1;
+    if (ql > 0 && (int64_t)(ql - 1) * zstep + 1 > lo) lo = (int64_t)(ql - 1) * zstep + 1;
+    int64_t hi = nc;  // s z < cr holds at hi (or hi = nc)
+    if (ql < (int)nz) hi = (int64_t)ql * zstep > lo ? (int64_t)ql * zstep : lo;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (s * col[mid].z < cr) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Plan of row r given J: segment count (0 for an empty row), J and m stored
+// for rows of two or more segments, nseg into the record.
+__device__ __forceinline__ int64_t plan_row(NodeRec* __restrict__ node, int64_t r, double s, double cr,
+                                            int64_t first, int64_t J, bool active, int64_t nc, int32_t T,
+                                            const uint64_t* __restrict__ P, int32_t* __restrict__ jend,
+                                            uint64_t* __restrict__ mq) {
     int64_t total = 0;
-    const double s = node[r].z;
-    const int64_t first = bip ? 0 : r + 1;
-    if (first < nc && s != 0.0) {
+    if (active) {
         if (T <= 0) {
             total = 1;
         } else {
-            const double cr = c ? c[r] : 1.0;
-            int64_t J = first;
-            if (s * col[first].z >= cr) {
-                int64_t lo = first + 1, hi = nc;  // first j in [lo, nc] with s*z_j < cr (nc if none)
-                while (lo < hi) {
-                    const int64_t mid = lo + (hi - lo) / 2;
-                    if (s * col[mid].z < cr) hi = mid; else lo = mid + 1;
-                }
-                J = lo;
-            }
             const int64_t nd = (J - first + T - 1) / T;
             int64_t ns = 0;
             uint64_t m = 0;
@@ -83,46 +111,111 @@ __device__ inline int64_t row_plan_one(NodeRec* __restrict__ node, const double*
                 ns = (mass == 0) ? 1 : (int64_t)((mass + m - 1) / m);
             }
             total = nd + ns;
-            jend[r] = (int32_t)J;
-            mq[r] = m;
+            if (total >= 2) {
+                jend[r] = (int32_t)J;
+                mq[r] = m;
+            }
         }
     }
     node[r].nseg = total > 0x7FFFFFFF ? 0x7FFFFFFF : (int32_t)total;
     return total;
 }
 
-__global__ __launch_bounds__(kThreads) void k_row_plan(NodeRec* __restrict__ node, const double* __restrict__ c,
-                                                       int64_t n, const NodeRec* __restrict__ col, int64_t nc,
-                                                       int32_t bip, int32_t T, const uint64_t* __restrict__ P,
-                                                       int32_t* __restrict__ jend,
-                                                       uint64_t* __restrict__ mq, uint64_t* __restrict__ hn) {
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n) return;
-    const int64_t total = row_plan_one(node, c, col, nc, bip, T, P, jend, mq, r);
+// One row per thread.  A block that holds a row with a dense part (the hubs,
+// a few blocks at most) stages column samples in LDS first.
+__global__ __launch_bounds__(kPlanThreads) void k_row_plan(NodeRec* __restrict__ node, const double* __restrict__ c,
+                                                           int64_t n, const NodeRec* __restrict__ col, int64_t nc,
+                                                           int32_t bip, int32_t T, const uint64_t* __restrict__ P,
+                                                           int32_t* __restrict__ jend, uint64_t* __restrict__ mq,
+                                                           uint64_t* __restrict__ hn) {
+    __shared__ double s_z[kPlanSamples];
+    const int64_t r = (int64_t)blockIdx.x * kPlanThreads + threadIdx.x;
+    const bool in = r < n;
+    double s = 0.0, cr = 1.0;
+    int64_t first = 0;
+    bool dense = false, active = false;
+    if (in) {
+        s = node[r].z;
+        first = bip ? 0 : r + 1;
+        active = first < nc && s != 0.0;
+        if (active && T > 0) {
+            cr = c ? c[r] : 1.0;
+            dense = s * col[first].z >= cr;
+        }
+    }
+    int64_t J = first;
+    if (__syncthreads_or(dense)) {
+        int64_t nz;
+        const int64_t zstep = stage_col_samples(col, nc, s_z, &nz);
+        __syncthreads();
+        if (dense) J = dense_end(col, nc, s, cr, first, s_z, nz, zstep);
+    }
+    if (!in) return;
+    const int64_t total = plan_row(node, r, s, cr, first, J, active, nc, T, P, jend, mq);
     if (hn) hn[r] = total >= 2 ? (uint64_t)total : 0ull;
 }
 
-// Heavy items are recorded in rounds of kHrThreads, one item per thread.
-constexpr int kHrThreads = 1024;
-constexpr int kHrSamples = 4096;  // P samples a block stages in LDS
-constexpr int kHrRows = 4096;     // rows of hoff a block stages in LDS
+// The row plan and the prefix sums hoff of the heavy-item counts in one
+// look-back pass over tiles of 4096 rows (counts below 2^62: up to 2^30 rows).
+// For every round of kHrThreads stored items, the row that holds the round's
+// first item goes to hbrow[round] (each row writes the rounds that begin inside
+// it: at most a few stores per row).  The tile of hub rows stages column
+// samples for its dense searches; the other tiles publish their sums at once.
+constexpr int kHrThreads = 1024;  // heavy items per round of k_heavy_records
 
-// Prefix sums hoff of the heavy-item counts (one look-back pass, as
-// k_scan_onepass).  For every round of kHrThreads stored items, the row that
-// holds the round's first item goes to hbrow[round] (each row writes the
-// rounds that begin inside it: at most a few stores per row).
-__global__ __launch_bounds__(kLbThreads) void k_scan_heavy(uint64_t* hoff, int64_t n, int64_t tiles,
-                                                           uint64_t* state, int32_t* __restrict__ hbrow,
-                                                           int64_t rec_cap, int32_t* err) {
+__global__ __launch_bounds__(kLbThreads) void k_row_plan_scan(NodeRec* __restrict__ node,
+                                                              const double* __restrict__ c, int64_t n,
+                                                              const NodeRec* __restrict__ col, int64_t nc,
+                                                              int32_t bip, int32_t T, const uint64_t* __restrict__ P,
+                                                              int32_t* __restrict__ jend, uint64_t* __restrict__ mq,
+                                                              uint64_t* __restrict__ hoff, int64_t tiles,
+                                                              uint64_t* state, int32_t* __restrict__ hbrow,
+                                                              int64_t rec_cap, int32_t* err) {
     __shared__ LbShared sh;
+    __shared__ double s_z[kPlanSamples];
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int64_t base = tile * kLbTile;
+        double s[kLbItems], cr[kLbItems];
+        int64_t J[kLbItems];
+        bool dense[kLbItems], active[kLbItems];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kLbItems; ++k) {
+            const int64_t r = base + k * kLbThreads + threadIdx.x;
+            s[k] = 0.0;
+            cr[k] = 1.0;
+            dense[k] = active[k] = false;
+            const int64_t first = bip ? 0 : r + 1;
+            J[k] = first;
+            if (r < n) {
+                s[k] = node[r].z;
+                active[k] = first < nc && s[k] != 0.0;
+                if (active[k] && T > 0) {
+                    cr[k] = c ? c[r] : 1.0;
+                    dense[k] = s[k] * col[first].z >= cr[k];
+                }
+            }
+            any = any || dense[k];
+        }
+        if (__syncthreads_or(any)) {
+            int64_t nz;
+            const int64_t zstep = stage_col_samples(col, nc, s_z, &nz);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kLbItems; ++k)
+                if (dense[k]) J[k] = dense_end(col, nc, s[k], cr[k], J[k], s_z, nz, zstep);
+        }
         uint64_t cnt[kLbItems];
 #pragma unroll
         for (int k = 0; k < kLbItems; ++k) {
             const int idx = k * kLbThreads + threadIdx.x;
-            const int64_t i = base + idx;
-            cnt[k] = (i < n) ? hoff[i] : 0ull;
+            const int64_t r = base + idx;
+            cnt[k] = 0;
+            if (r < n) {
+                const int64_t first = bip ? 0 : r + 1;
+                const int64_t total = plan_row(node, r, s[k], cr[k], first, J[k], active[k], nc, T, P, jend, mq);
+                cnt[k] = total >= 2 ? (uint64_t)total : 0ull;
+            }
             sh.items[lb_at(idx)] = cnt[k];
         }
         const uint64_t end = lb_tile_scan(sh, tile, state, err);
@@ -141,6 +234,19 @@ __global__ __launch_bounds__(kLbThreads) void k_scan_heavy(uint64_t* hoff, int64
         if (threadIdx.x == 0 && base + kLbTile >= n) hoff[n] = end;
     }
 }
+
+static mh_status launch_row_plan(NodeRec* node, const double* c, int64_t n, const NodeRec* col, int64_t nc,
+                                 int32_t bip, int32_t T, const uint64_t* P, int32_t* jend, uint64_t* mq,
+                                 uint64_t* hn, hipStream_t stream) {
+    const unsigned grid = (unsigned)((n + kPlanThreads - 1) / kPlanThreads);
+    hipLaunchKernelGGL(k_row_plan, dim3(grid), dim3(kPlanThreads), 0, stream, node, c, n, col, nc, bip, T, P, jend,
+                       mq, hn);
+    MH_HIP_TRY(hipGetLastError());
+    return MH_OK;
+}
+
+constexpr int kHrSamples = 4096;  // P samples a block of k_heavy_records stages in LDS
+constexpr int kHrRows = 4096;     // rows of hoff a block of k_heavy_records stages in LDS
 
 // Row and column range of the first rec_cap heavy items, the same as
 // heavy_record() computes them.  With hbrow and Psamp (P[256 k]): a block takes
@@ -275,30 +381,26 @@ static unsigned heavy_grid(int64_t rec_cap) {
 
 // A3: segment counts of every row (and J, m) and, when segmented, the prefix
 // sums hoff of the heavy rows' counts.  While the sums stay below 2^62 (up to
-// 2^30 rows) one look-back kernel scans them and writes the first row of every
-// round of stored heavy items to hbrow (rows_known); beyond, three scan kernels.  The row plan itself
-// runs one row per thread: hub rows binary-search their dense end, and a
-// thread working through many rows would serialize those searches.
+// 2^30 rows) one look-back kernel plans the rows, scans the counts and writes
+// the first row of every round of stored heavy items to hbrow (rows_known);
+// beyond, the row plan and three scan kernels.
 static mh_status plan_rows(NodeRec* node, const double* c, int64_t n, const NodeRec* col, int64_t nc, int32_t bip,
                            int32_t T, const uint64_t* P, int32_t* jend, uint64_t* mq, uint64_t* hoff,
                            uint64_t* hoff_state, int32_t* hbrow, int64_t rec_cap, int32_t* status, void* scratch,
                            size_t scratch_bytes, bool* rows_known, hipStream_t stream) {
     *rows_known = false;
-    const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_row_plan, dim3(grid), dim3(kThreads), 0, stream, node, c, n, col, nc, bip, T, P, jend, mq,
-                       hoff);
-    MH_HIP_TRY(hipGetLastError());
-    if (!hoff) return MH_OK;
-    if (n <= (int64_t)1 << 30) {
+    if (hoff && n <= (int64_t)1 << 30) {
         const int64_t tiles = lb_tiles(n);
-        const int64_t resident = resident_blocks(k_scan_heavy, kLbThreads);
-        const int64_t sgrid = tiles < resident ? tiles : resident;
-        hipLaunchKernelGGL(k_scan_heavy, dim3((unsigned)sgrid), dim3(kLbThreads), 0, stream, hoff, n, tiles,
-                           hoff_state, hbrow, rec_cap, status);
+        const int64_t resident = resident_blocks(k_row_plan_scan, kLbThreads);
+        const int64_t grid = tiles < resident ? tiles : resident;
+        hipLaunchKernelGGL(k_row_plan_scan, dim3((unsigned)grid), dim3(kLbThreads), 0, stream, node, c, n, col, nc,
+                           bip, T, P, jend, mq, hoff, tiles, hoff_state, hbrow, rec_cap, status);
         MH_HIP_TRY(hipGetLastError());
         *rows_known = true;
         return MH_OK;
     }
+    mh_status st = launch_row_plan(node, c, n, col, nc, bip, T, P, jend, mq, hoff, stream);
+    if (st != MH_OK || !hoff) return st;
     return scan_exclusive_u64(hoff, hoff, n, scratch, scratch_bytes, stream);
 }
 
@@ -559,9 +661,8 @@ mh_status plan_counts_impl(const double* zs, const double* c, int64_t n, int32_t
         mh_status st = scan_exclusive_u64(P, P, n, ar.base + off, ws_bytes - off, stream);
         if (st != MH_OK) return st;
     }
-    hipLaunchKernelGGL(k_row_plan, dim3(grid), dim3(kThreads), 0, stream, node, c, n, (const NodeRec*)node, n, 0,
-                       T, (const uint64_t*)P, jend, mq, (uint64_t*)nullptr);
-    MH_HIP_TRY(hipGetLastError());
+    mh_status pst = launch_row_plan(node, c, n, node, n, 0, T, P, jend, mq, nullptr, stream);
+    if (pst != MH_OK) return pst;
     hipLaunchKernelGGL(k_unpack_nseg, dim3(grid), dim3(kThreads), 0, stream, node, n, nseg);
     MH_HIP_TRY(hipGetLastError());
     return MH_OK;
