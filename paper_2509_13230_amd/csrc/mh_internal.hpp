@@ -99,8 +99,14 @@ mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, h
 // Sorts hi[0..n) / pay[0..n) using alt buffers of the same size (the result
 // ends in hi / pay); the histograms must hold the counts.  err (optional,
 // device) receives MH_EHIP if a look-back or exchange ever stalls.
+// x (and y) non-null: the first pass makes the keys itself from the node
+// parameters (z = x or x y, checks raising MH_EINVAL into err) and counts the
+// later passes' digits, so hi / pay need no preparation and the histograms
+// only need to be zero; allowed when radix_prepares_keys(n).
+bool radix_prepares_keys(int64_t n);
 mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint64_t* pay_alt, int64_t n,
-                             void* ws, size_t ws_bytes, int32_t* err, hipStream_t stream);
+                             void* ws, size_t ws_bytes, int32_t* err, hipStream_t stream,
+                             const double* x = nullptr, const double* y = nullptr);
 
 // ---- sampler pieces ----
 struct SortedView {

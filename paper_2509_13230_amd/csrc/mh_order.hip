@@ -3,6 +3,7 @@
 // (product of the two largest y among the ranks not yet processed).
 #include "mh_common.hpp"
 #include "mh_internal.hpp"
+#include "mh_keys.hpp"
 #include "mh_lookback.hpp"
 #include "mh_sweep_core.hpp"
 
@@ -29,26 +30,17 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_keys(const double* __rest
     for (int i = threadIdx.x; i < kHist; i += kPrepThreads) h[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kPrepTile;
-    const int lane = threadIdx.x & 63;
     constexpr int kPer = kPrepTile / kPrepThreads;
     // all loads first, then the keys and their counts
-    double zv[kPer];
-    bool okv[kPer];
+    double xv[kPer], yv[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int64_t i = base + (int64_t)q * kPrepThreads + threadIdx.x;
-        zv[q] = 0.0;
-        okv[q] = true;
+        xv[q] = 0.0;
+        yv[q] = 0.0;
         if (i < n) {
-            const double xi = x[i];
-            if (y) {
-                const double yi = y[i];
-                okv[q] = (yi >= 0.0) && isfinite(yi) && (xi >= 0.0) && isfinite(xi);
-                zv[q] = xi * yi;
-            } else {
-                okv[q] = (xi >= 0.0) && isfinite(xi);
-                zv[q] = xi;
-            }
+            xv[q] = x[i];
+            if (y) yv[q] = y[i];
         }
     }
     bool bad = false;
@@ -58,36 +50,15 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_keys(const double* __rest
         const bool valid = i < n;
         uint32_t key = 0;
         if (valid) {
-            const bool ok = okv[q] && isfinite(zv[q]);
+            bool ok;
+            const double z = node_z(xv[q], y != nullptr, yv[q], &ok);
             bad = bad || !ok;
-            const uint64_t full = desc_key(ok ? zv[q] : 0.0);
-            key = (uint32_t)(full >> 32);
+            uint64_t pay;
+            split_key(z, i, &key, &pay);
             keys[i] = key;
-            vals[i] = (full << 32) | (uint64_t)(uint32_t)i;
+            vals[i] = pay;
         }
-        // Lanes holding the key of their group's first lane (groups by an 8-bit
-        // fold of the key) are counted once by that lane: tied parameters,
-        // common in fitted inputs, would otherwise all hit one LDS bin.
-        const uint32_t fold = (key ^ (key >> 8) ^ (key >> 16) ^ (key >> 24)) & 255u;
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (fold >> b) & 1u;
-            const uint64_t vote = __ballot(bit);
-            m &= bit ? vote : ~vote;
-        }
-        const int leader = valid ? (int)__ffsll((unsigned long long)m) - 1 : lane;
-        const uint32_t lkey = __shfl(key, leader, kWave);
-        const uint64_t same = __ballot(valid && key == lkey);
-        if (valid) {
-            uint32_t add = 0;
-            if (lane == leader) add = (uint32_t)__popcll(same & m);
-            else if (!((same >> lane) & 1ull)) add = 1;
-            if (add) {
-#pragma unroll
-                for (int p = 0; p < kRadixPasses; ++p) atomicAdd(&h[p * 256 + ((key >> (8 * p)) & 255)], add);
-            }
-        }
+        count_key_digits(h, key, valid, 0, kRadixPasses);
     }
     if (bad) raise_status(status, MH_EINVAL);
     __syncthreads();
@@ -326,10 +297,17 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
     uint32_t* hist = nullptr;
     mh_status st = radix_prepare(sort_ws, sort_bytes, n, &hist, stream, e1, e2);
     if (st != MH_OK) return st;
-    const unsigned tiles = (unsigned)((n + kPrepTile - 1) / kPrepTile);
-    hipLaunchKernelGGL(k_prep_keys, dim3(tiles), dim3(kPrepThreads), 0, stream, x, y, n, keys, vals, hist, status);
-    MH_HIP_TRY(hipGetLastError());
-    st = radix_sort_split64(keys, vals, keys_alt, vals_alt, n, sort_ws, sort_bytes, status, stream);
+    // keys and histograms: made by the first radix pass itself when the sort
+    // exchanges digit counts between resident tiles, else by k_prep_keys
+    const bool fused = radix_prepares_keys(n);
+    if (!fused) {
+        const unsigned tiles = (unsigned)((n + kPrepTile - 1) / kPrepTile);
+        hipLaunchKernelGGL(k_prep_keys, dim3(tiles), dim3(kPrepThreads), 0, stream, x, y, n, keys, vals, hist,
+                           status);
+        MH_HIP_TRY(hipGetLastError());
+    }
+    st = radix_sort_split64(keys, vals, keys_alt, vals_alt, n, sort_ws, sort_bytes, status, stream,
+                            fused ? x : nullptr, y);
     if (st != MH_OK) return st;
     if (mass_prefix && node && n <= (int64_t)1 << 30) {
         // records and the masses' prefix sums in one pass (sums stay below 2^62)

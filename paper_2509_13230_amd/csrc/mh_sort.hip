@@ -26,6 +26,7 @@
 // (fitted parameters: ties by degree class) have no such runs.
 #include "mh_common.hpp"
 #include "mh_internal.hpp"
+#include "mh_keys.hpp"
 
 namespace mh {
 
@@ -88,20 +89,27 @@ __global__ __launch_bounds__(kSortThreads) void k_zero_u64(ZeroRange a, ZeroRang
     for (int64_t i = t; i < c.n; i += stride) c.p[i] = 0;
 }
 
-template <bool XCHG>
+// FROMX (first pass, column exchange only): the pass prepares its own keys from
+// the parameters x (and y) as the key-preparation kernel would, adds the digit
+// histograms of the later passes to hist_all, and takes its own digit totals
+// from the exchange (column owners publish them in dtot) instead of ghist.
+template <bool XCHG, bool FROMX>
 __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __restrict__ kin,
                                                            const uint64_t* __restrict__ vin,
                                                            uint32_t* __restrict__ kout, uint64_t* __restrict__ vout,
                                                            int64_t n, int shift, const uint32_t* __restrict__ ghist,
                                                            uint64_t* status, uint32_t* ticket, bool use_ticket,
-                                                           int32_t* err) {
+                                                           int32_t* err, const double* __restrict__ x,
+                                                           const double* __restrict__ y,
+                                                           uint32_t* __restrict__ hist_all, uint64_t* dtot) {
+    static_assert(!FROMX || XCHG, "a pass preparing its keys takes its digit totals from the exchange");
     __shared__ uint32_t s_keys[kTileKeys];
     __shared__ uint64_t s_vals[kTileKeys];
     __shared__ uint32_t cnt[kSortWaves][kRadix];
     __shared__ uint32_t s_bstart[kRadix];
     __shared__ uint32_t s_goff[kRadix];
-    __shared__ uint32_t s_dstart[kRadix];
     __shared__ uint32_t s_scan[kSortWaves];
+    __shared__ uint32_t s_later[FROMX ? (kPasses - 1) * kRadix : 1];
     __shared__ uint32_t s_tile;
 
     // Tiles are taken in ticket order unless the whole grid is resident at once
@@ -109,6 +117,8 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
     // per block on one address).
     if (threadIdx.x == 0) s_tile = use_ticket ? atomicAdd(ticket, 1u) : blockIdx.x;
     for (int i = threadIdx.x; i < kSortWaves * kRadix; i += kSortThreads) (&cnt[0][0])[i] = 0;
+    if (FROMX)
+        for (int i = threadIdx.x; i < (kPasses - 1) * kRadix; i += kSortThreads) s_later[i] = 0;
     __syncthreads();
     const int64_t tile = s_tile;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -127,13 +137,39 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
     uint32_t hc[kHistCopies];
 #pragma unroll
     for (int c = 0; c < kHistCopies; ++c)
-        hc[c] = threadIdx.x < kRadix ? ghist[c * kPasses * kRadix + threadIdx.x] : 0u;
+        hc[c] = (!FROMX && threadIdx.x < kRadix) ? ghist[c * kPasses * kRadix + threadIdx.x] : 0u;
+    if (FROMX) {
+        double xv[kKeysPerLane], yv[kKeysPerLane];
 #pragma unroll
-    for (int r = 0; r < kKeysPerLane; ++r) {
-        const int64_t i = base + (int64_t)r * kWave + lane;
-        const bool valid = i < n;
-        k[r] = valid ? kin[i] : 0u;
-        v[r] = valid ? vin[i] : 0ull;
+        for (int r = 0; r < kKeysPerLane; ++r) {
+            const int64_t i = base + (int64_t)r * kWave + lane;
+            xv[r] = i < n ? x[i] : 0.0;
+            yv[r] = (y && i < n) ? y[i] : 0.0;
+        }
+        bool bad = false;
+#pragma unroll
+        for (int r = 0; r < kKeysPerLane; ++r) {
+            const int64_t i = base + (int64_t)r * kWave + lane;
+            const bool valid = i < n;
+            k[r] = 0u;
+            v[r] = 0ull;
+            if (valid) {
+                bool ok;
+                const double z = node_z(xv[r], y != nullptr, yv[r], &ok);
+                bad = bad || !ok;
+                split_key(z, i, &k[r], &v[r]);
+            }
+            count_key_digits(s_later, k[r], valid, 1, kPasses);
+        }
+        if (bad) raise_status(err, MH_EINVAL);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kKeysPerLane; ++r) {
+            const int64_t i = base + (int64_t)r * kWave + lane;
+            const bool valid = i < n;
+            k[r] = valid ? kin[i] : 0u;
+            v[r] = valid ? vin[i] : 0ull;
+        }
     }
 #pragma unroll
     for (int r = 0; r < kKeysPerLane; ++r) {
@@ -148,6 +184,12 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
+    if (FROMX) {
+        // the later passes' histograms, into this block's copy
+        uint32_t* copy = hist_all + ((blockIdx.x % kHistCopies) * kPasses + 1) * kRadix;
+        for (int i = threadIdx.x; i < (kPasses - 1) * kRadix; i += kSortThreads)
+            if (s_later[i]) atomicAdd(&copy[i], s_later[i]);
+    }
 
     const int d = threadIdx.x;  // one digit per thread of the first kRadix
     const bool dig = d < kRadix;
@@ -166,17 +208,17 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
         for (int c = 0; c < kHistCopies; ++c) dtotal += hc[c];
     }
     const uint32_t bstart = block_exclusive(total, s_scan);
-    const uint32_t dstart = block_exclusive(dtotal, s_scan);
+    uint32_t dstart = FROMX ? 0u : block_exclusive(dtotal, s_scan);
     uint32_t excl = 0;
     if (XCHG) {
         // Every tile is resident (at most kXchgTiles): instead of a chain of
         // look-backs, block b scans the digit columns b, b + G, b + 2G, ...
         // (G blocks; kXchgCols columns at once, 256 threads each, one tile per
-        // thread) over all tiles' published counts, and writes each tile its
-        // start for that digit (flag 2 over the count word, which only this
-        // block reads); then every tile reads its 256 starts back.  Two round
-        // trips per pass when G >= 256 / kXchgCols.
-        if (dig) s_dstart[d] = dstart;
+        // thread) over all tiles' published counts, and writes each tile the
+        // count of that digit in the tiles before it (flag 2 over the count
+        // word, which only this block reads) and, when the pass has no digit
+        // totals of its own, the column's total to dtot; then every tile reads
+        // its 256 words back.  Two round trips per pass when G >= 256 / kXchgCols.
         const int nt = (int)gridDim.x;
         const int tcol = threadIdx.x & (kXchgTiles - 1);  // this thread's tile in the column
         for (int c0 = blockIdx.x; c0 < kRadix; c0 += kXchgCols * nt) {
@@ -202,22 +244,37 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
             // exclusive scan over each column's 256 threads (4 waves)
             const uint32_t inc = wave_inclusive_scan(c);
             if (lane == 63) s_scan[wave] = inc;
-            __syncthreads();  // also orders the s_dstart writes
+            __syncthreads();
+            const int w0 = wave & ~(kXchgTiles / kWave - 1);
             uint32_t before = inc - c;
-            for (int w = wave & ~(kXchgTiles / kWave - 1); w < wave; ++w) before += s_scan[w];
-            if (mine)
-                __hip_atomic_store(cw, kFlagPrefix | (s_dstart[col] + before), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            for (int w = w0; w < wave; ++w) before += s_scan[w];
+            if (mine) __hip_atomic_store(cw, kFlagPrefix | before, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (FROMX && tcol == 0 && col < kRadix) {
+                uint32_t coltotal = 0;
+                for (int w = w0; w < w0 + kXchgTiles / kWave; ++w) coltotal += s_scan[w];
+                __hip_atomic_store(dtot + col, kFlagPrefix | coltotal, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             __syncthreads();
         }
         if (dig) {
             uint32_t spins = 0;
-            for (;;) {
-                const uint64_t w = __hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if ((w & ~0xFFFFFFFFull) == kFlagPrefix) {
-                    excl = (uint32_t)w - dstart;  // earlier tiles' keys with digit d
-                    break;
+            bool need_excl = true, need_total = FROMX;
+            while (need_excl || need_total) {
+                if (need_excl) {
+                    const uint64_t w = __hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((w & ~0xFFFFFFFFull) == kFlagPrefix) {
+                        excl = (uint32_t)w;  // earlier tiles' keys with digit d
+                        need_excl = false;
+                    }
                 }
+                if (FROMX && need_total) {
+                    const uint64_t w = __hip_atomic_load(dtot + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((w & ~0xFFFFFFFFull) == kFlagPrefix) {
+                        dtotal = (uint32_t)w;  // keys with digit d over all tiles
+                        need_total = false;
+                    }
+                }
+                if (!(need_excl || need_total)) break;
                 if (++spins > kSpinLimit) {
                     raise_status(err, MH_EHIP);
                     break;
@@ -225,6 +282,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
                 __builtin_amdgcn_s_sleep(1);
             }
         }
+        if (FROMX) dstart = block_exclusive(dtotal, s_scan);
     } else if (dig && tile > 0) {
         // look back over the preceding tiles, kLookWindow words in flight at a time
         int64_t t = tile - 1;
@@ -555,6 +613,7 @@ struct SortScratch {
     uint32_t* hist;
     uint32_t* tickets;
     uint32_t* bits;
+    uint64_t* dtot;  // the first pass's digit totals when it prepares its own keys
     int32_t* err;
     int64_t words;  // u64 words to zero
 };
@@ -565,7 +624,7 @@ SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) {
     const int64_t status_words = (int64_t)kPasses * nb * kRadix;
     const int64_t hist_words = kHistCopies * kPasses * kRadix / 2 + kPasses;
     const int64_t bit_words = tie_words(n) / 2;
-    uint64_t* block = ar.take<uint64_t>(status_words + hist_words + bit_words);
+    uint64_t* block = ar.take<uint64_t>(status_words + hist_words + bit_words + kRadix);
     int32_t* err = ar.take<int32_t>(1);
     *ok = !ar.overflow;
     SortScratch s{};
@@ -574,9 +633,17 @@ SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) {
     s.hist = reinterpret_cast<uint32_t*>(block + status_words);
     s.tickets = s.hist + kHistCopies * kPasses * kRadix;
     s.bits = reinterpret_cast<uint32_t*>(block + status_words + hist_words);
+    s.dtot = block + status_words + hist_words + bit_words;
     s.err = err;
-    s.words = status_words + hist_words + bit_words;
+    s.words = status_words + hist_words + bit_words + kRadix;
     return s;
+}
+
+// One tile per CU at most: the column exchange (all tiles resident, with a CU
+// to spare for each).
+bool use_exchange(int64_t n) {
+    const int64_t nb = sort_blocks(n);
+    return nb <= kXchgTiles && nb <= device_cus();
 }
 
 }  // namespace
@@ -584,7 +651,7 @@ SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) {
 size_t radix_workspace_bytes(int64_t n) {
     Sizer s;
     s.take<uint64_t>((size_t)kPasses * sort_blocks(n) * kRadix + kHistCopies * kPasses * kRadix / 2 + kPasses +
-                     tie_words(n) / 2);
+                     tie_words(n) / 2 + kRadix);
     s.take<int32_t>(1);
     return s.used + 256;
 }
@@ -607,8 +674,11 @@ mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, h
     return MH_OK;
 }
 
+bool radix_prepares_keys(int64_t n) { return n > 1 && n <= (int64_t)0xFFFFFFFFll && use_exchange(n); }
+
 mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint64_t* pay_alt, int64_t n,
-                             void* ws, size_t ws_bytes, int32_t* err, hipStream_t stream) {
+                             void* ws, size_t ws_bytes, int32_t* err, hipStream_t stream, const double* x,
+                             const double* y) {
     if (n <= 1) return MH_OK;
     if (n > (int64_t)0xFFFFFFFFll) return MH_EINVAL;
     bool ok = false;
@@ -616,19 +686,21 @@ mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint
     if (!ok) return MH_EWORKSPACE;
     if (!err) err = s.err;
     const int64_t nb = sort_blocks(n);
-    // One tile per CU at most: the column exchange (all tiles resident, with a
-    // CU to spare for each); otherwise the look-back, by ticket unless the
-    // whole grid is resident.
-    const bool xchg = nb <= kXchgTiles && nb <= device_cus();
-    const bool use_ticket = !xchg && nb > resident_blocks(k_onesweep<false>, kSortThreads);
+    // the column exchange when every tile has a CU; otherwise the look-back, by
+    // ticket unless the whole grid is resident
+    const bool xchg = use_exchange(n);
+    if (x && !xchg) return MH_EINVAL;  // keys from x need the exchange (radix_prepares_keys)
+    const bool use_ticket = !xchg && nb > resident_blocks(k_onesweep<false, false>, kSortThreads);
     uint32_t* kin = hi;
     uint64_t* vin = pay;
     uint32_t* kout = hi_alt;
     uint64_t* vout = pay_alt;
     for (int pass = 0; pass < kPasses; ++pass) {
-        hipLaunchKernelGGL(xchg ? k_onesweep<true> : k_onesweep<false>, dim3((unsigned)nb), dim3(kSortThreads), 0,
-                           stream, kin, vin, kout, vout, n, pass * 8, s.hist + pass * kRadix,
-                           s.status + (int64_t)pass * nb * kRadix, s.tickets + pass, use_ticket, err);
+        auto kern = xchg ? (pass == 0 && x ? k_onesweep<true, true> : k_onesweep<true, false>)
+                         : k_onesweep<false, false>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n, pass * 8,
+                           s.hist + pass * kRadix, s.status + (int64_t)pass * nb * kRadix, s.tickets + pass,
+                           use_ticket, err, x, y, s.hist, s.dtot);
         MH_HIP_TRY(hipGetLastError());
         uint32_t* tk = kin; kin = kout; kout = tk;
         uint64_t* tv = vin; vin = vout; vout = tv;
