@@ -300,11 +300,15 @@ def main():
         raise RuntimeError(f"timed and repeated sample differ: {last_edges} vs {st['n_edges']} edges")
     value = edges / elapsed
     achieved_lane_ops = steps_total / args.steps * SWEEP_VALU_PER_STEP / (sweep_ms * 1e-3)
+    # the sweep's edge output against HBM bandwidth (8 B per edge written)
+    write_gbs = edges / args.steps * 8 / (sweep_ms * 1e-3) / 1e9
     roof = {"bound": "alu", "kernel": "k_sweep (unweighted)",
             "achieved": achieved_lane_ops / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
             "frac": achieved_lane_ops / PEAK_LANE_OPS, "traffic": None,
             "work_per_launch": f"{steps_total / args.steps:.0f} steps x {SWEEP_VALU_PER_STEP} VALU lane-ops",
-            "avg_launch_ms": sweep_ms}
+            "avg_launch_ms": sweep_ms,
+            "hbm_write": {"achieved": write_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": write_gbs / HBM_PEAK_GBS, "bytes_per_launch": edges / args.steps * 8}}
 
     out = {
         "metric": METRIC,
