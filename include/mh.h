@@ -285,6 +285,19 @@ mh_status mh_batch_autotune(mh_network* nets_host, int32_t n_networks, int32_t m
 mh_status mh_graph_launch(hipGraphExec_t exec, hipStream_t stream);
 mh_status mh_graph_destroy(hipGraphExec_t exec);
 
+/* Canonical order of an edge list (a convenience: the method's output, the
+ * edge list E of Alg. 1, is a set; its order leaves the sweep depending on the
+ * schedule).  Sorts src[0..n_edges), dst[...] and, if w is not NULL, w[...] in
+ * place by (src, dst) ascending, comparing node ids as integers; every pair
+ * appears once in a sample, so the order is total and a sample's sorted list is
+ * a function of its inputs alone.  Ids must be non-negative.  Device pointers on
+ * `stream`; workspace: mh_sort_edges_workspace_bytes(n_edges) bytes, owned by
+ * the caller.  Synchronous (reads the sort's status back): MH_EINVAL for
+ * n_edges < 0 or above INT32_MAX or missing arrays, MH_EWORKSPACE, MH_EHIP. */
+size_t mh_sort_edges_workspace_bytes(int64_t n_edges);
+mh_status mh_sort_edges(int32_t* src, int32_t* dst, int32_t* w, int64_t n_edges, void* workspace,
+                        size_t ws_bytes, hipStream_t stream);
+
 const char* mh_status_string(mh_status s);
 
 #ifdef __cplusplus

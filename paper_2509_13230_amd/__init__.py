@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
         "mh_plan_counts": ([vp, vp, i64, i32, vp, vp, sz, vp], ctypes.c_int),
         "mh_expected_degree_fwd": ([vp, vp, vp, i64, vp, vp, vp], ctypes.c_int),
         "mh_expected_degree_bwd": ([vp, vp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
+        "mh_sort_edges_workspace_bytes": ([i64], sz),
+        "mh_sort_edges": ([vp, vp, vp, i64, vp, sz, vp], ctypes.c_int),
         "mh_status_string": ([ctypes.c_int], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -349,6 +351,25 @@ def order(x: torch.Tensor, y: torch.Tensor | None = None):
     _check(L.mh_order(_ptr(x), _ptr(y), n, _ptr(perm), _ptr(zs), _ptr(ys), _ptr(status), _ptr(ws), ws.numel(),
                       _stream(dev)), "mh_order")
     return perm, zs, ys, status
+
+
+def sort_edges(src: torch.Tensor, dst: torch.Tensor, w: torch.Tensor | None = None, workspace=None):
+    """Sorts an edge list in place into canonical order, by (src, dst) (node
+    ids; the method's edge list is a set, so this order makes samples
+    comparable element by element).  Returns (src, dst, w)."""
+    if src.dtype != torch.int32 or dst.dtype != torch.int32 or src.shape != dst.shape or not src.is_cuda:
+        raise ValueError("src and dst must be int32 device tensors of one shape")
+    if w is not None and (w.dtype != torch.int32 or w.shape != src.shape):
+        raise ValueError("w must be an int32 tensor of the edges' shape")
+    if not (src.is_contiguous() and dst.is_contiguous() and (w is None or w.is_contiguous())):
+        raise ValueError("edge arrays must be contiguous")
+    L = lib()
+    m = src.numel()
+    need = L.mh_sort_edges_workspace_bytes(m)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, src.device)
+    _check(L.mh_sort_edges(_ptr(src), _ptr(dst), _ptr(w), m, _ptr(ws), ws.numel(), _stream(src.device)),
+           "mh_sort_edges")
+    return src, dst, w
 
 
 def bound(ys: torch.Tensor) -> torch.Tensor:

@@ -36,7 +36,7 @@ HIPCC_FLAGS = [
 ]
 
 SOURCES = ["mh_scan.hip", "mh_sort.hip", "mh_order.hip", "mh_sweep.hip", "mh_bf.hip", "mh_degree.hip",
-           "mh_api.hip", "mh_batched.hip"]
+           "mh_api.hip", "mh_batched.hip", "mh_edges.hip"]
 
 
 def hipcc() -> str:

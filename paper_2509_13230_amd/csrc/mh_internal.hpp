@@ -33,12 +33,14 @@ struct Arena {
     }
 };
 
-// Counting pass: same sequence of take() calls with no memory behind it.
+// Counting pass: same sequence of take() calls with no memory behind it
+// (every piece comes back null).
 struct Sizer {
     size_t used = 0;
     template <typename T>
-    void take(size_t count) {
+    T* take(size_t count) {
         used = ((used + 255) & ~size_t(255)) + count * sizeof(T);
+        return nullptr;
     }
 };
 

@@ -30,7 +30,8 @@ def test_header_declares_entry_points():
     names = _declared()
     for must in ("mh_sample_unweighted", "mh_sample_weighted", "mh_sample_bruteforce", "mh_expected_degree_fwd",
                  "mh_expected_degree_bwd", "mh_order", "mh_bound", "mh_plan_counts", "mh_workspace_bytes",
-                 "mh_sample_bipartite", "mh_bipartite_workspace_bytes"):
+                 "mh_sample_bipartite", "mh_bipartite_workspace_bytes", "mh_sort_edges",
+                 "mh_sort_edges_workspace_bytes"):
         assert must in names
 
 
@@ -129,3 +130,16 @@ def test_binding_fails_loudly_without_device():
         pytest.skip("a device is present")
     with pytest.raises(TypeError):
         mh.sample_unweighted(torch.zeros(10, dtype=torch.float64))
+
+
+def test_sort_edges_argument_errors(L):
+    P = ctypes.c_void_p(16)
+    assert L.mh_sort_edges(None, None, None, -1, None, 0, None) == -1           # negative count
+    assert L.mh_sort_edges(None, None, None, 1 << 31, None, 0, None) == -1      # beyond INT32_MAX edges
+    assert L.mh_sort_edges(None, None, None, 0, None, 0, None) == 0             # nothing to sort
+    assert L.mh_sort_edges(None, None, None, 1, None, 0, None) == 0
+    assert L.mh_sort_edges(None, P, None, 10, P, 1 << 20, None) == -1           # no src
+    assert L.mh_sort_edges(P, P, None, 10, P, 16, None) == -4                   # workspace too small
+    a = L.mh_sort_edges_workspace_bytes(1000)
+    b = L.mh_sort_edges_workspace_bytes(1_000_000)
+    assert 0 < a < b < 40 * 1_000_000
