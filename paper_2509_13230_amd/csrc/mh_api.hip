@@ -63,7 +63,7 @@ mh_status mh_order(const double* x, const double* y, int64_t n, int32_t* perm, d
     if (n == 0) return MH_OK;
     if (!x || !perm || !zs || (y && !ys)) return MH_EINVAL;
     if (!workspace || ws_bytes < mh::order_workspace_bytes(n)) return MH_EWORKSPACE;
-    return mh::order_nodes(x, y, n, perm, zs, ys, nullptr, status_dev, nullptr, nullptr, nullptr, workspace,
+    return mh::order_nodes(x, y, n, perm, zs, ys, nullptr, status_dev, nullptr, nullptr, nullptr, nullptr, workspace,
                            ws_bytes, stream);
 }
 

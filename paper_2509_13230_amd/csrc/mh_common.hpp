@@ -70,6 +70,26 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
     return v;
 }
 
+// Copies count values into LDS, value j from load(j), by a block of blockDim.x
+// threads, each taking at most PER values: all of a thread's loads are issued
+// (indices clamped into range, no branches) before any LDS store, so they are
+// in flight together instead of one round trip each.
+template <int PER, typename T, typename F>
+__device__ __forceinline__ void stage_lds(T* s, int64_t count, F load) {
+    if (count <= 0) return;
+    T v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int64_t j = threadIdx.x + (int64_t)q * blockDim.x;
+        v[q] = load(j < count ? j : count - 1);
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int64_t j = threadIdx.x + (int64_t)q * blockDim.x;
+        if (j < count) s[j] = v[q];
+    }
+}
+
 // ------------------------------------------------------------------ key bits
 // Non-negative binary64 values order like their bit patterns; the complement
 // orders them descending.  -0.0 is folded to +0.0 first.

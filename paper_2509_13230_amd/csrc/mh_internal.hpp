@@ -126,12 +126,12 @@ size_t order_workspace_bytes(int64_t n);
 // the same pass, with the look-back state mass_state (lb_tiles(n) words that
 // must be zero when this call's first kernel has run: pass them as e1 or
 // e2), and then mass_samples (optional, lb_samples(n) words) receives
-// P[256 k].  check_square: the largest z squared must be finite (one node
+// P[256 k] and z_samples (optional, (n - 1) / 256 + 1 values) z[256 k].  check_square: the largest z squared must be finite (one node
 // set, where it is the largest t).  e1, e2: u64 words zeroed by the first
 // kernel (look-back state of later steps, counters).
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
                       NodeRec* node, int32_t* status, uint64_t* mass_prefix, uint64_t* mass_state,
-                      uint64_t* mass_samples, void* ws, size_t ws_bytes, hipStream_t stream,
+                      uint64_t* mass_samples, double* z_samples, void* ws, size_t ws_bytes, hipStream_t stream,
                       bool check_square = true, ZeroRange e1 = {}, ZeroRange e2 = {});
 
 size_t bound_workspace_bytes(int64_t n);

@@ -101,15 +101,16 @@ __global__ __launch_bounds__(kThreads) void k_finish_order(const uint32_t* __res
 
 // The same, into node records, with the column masses scanned on the way:
 // P[r] = sum of floor(z 2^32) over ranks < r, P[n] = total (tiles of 4096
-// ranks, look-back state zero at launch).
+// ranks, look-back state zero at launch); every 256th P and z to the sample
+// arrays.
 __global__ __launch_bounds__(kLbThreads) void k_finish_order_scan(const uint32_t* __restrict__ keys,
                                                                   const uint64_t* __restrict__ vals, int64_t n,
                                                                   NodeRec* __restrict__ node,
                                                                   const double* __restrict__ y,
                                                                   double* __restrict__ ys, uint64_t* __restrict__ P,
                                                                   int64_t tiles, uint64_t* state,
-                                                                  uint64_t* samples, int32_t check_square,
-                                                                  int32_t* status) {
+                                                                  uint64_t* samples, double* zsamples,
+                                                                  int32_t check_square, int32_t* status) {
     __shared__ LbShared sh;
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int64_t base = tile * kLbTile;
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(kLbThreads) void k_finish_order_scan(const uint32_t
                 node[r].z = z;
                 node[r].id = (int32_t)id;
                 if (ys) ys[r] = y[id];
+                if (zsamples && (r & ((1 << kSampleShift) - 1)) == 0) zsamples[r >> kSampleShift] = z;
                 m = mass_q(z);
                 if (check_square && r == 0 && !isfinite(z * z)) raise_status(status, MH_EINVAL);
             }
@@ -282,7 +284,8 @@ size_t order_workspace_bytes(int64_t n) {
 
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
                       NodeRec* node, int32_t* status, uint64_t* mass_prefix, uint64_t* mass_state,
-                      uint64_t* mass_samples, void* ws, size_t ws_bytes, hipStream_t stream, bool check_square,
+                      uint64_t* mass_samples, double* z_samples, void* ws, size_t ws_bytes, hipStream_t stream,
+                      bool check_square,
                       ZeroRange e1, ZeroRange e2) {
     if (n <= 0) return MH_OK;
     Arena ar(ws, ws_bytes);
@@ -316,7 +319,7 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
         const int64_t grid = tiles < resident ? tiles : resident;
         hipLaunchKernelGGL(k_finish_order_scan, dim3((unsigned)grid), dim3(kLbThreads), 0, stream,
                            (const uint32_t*)keys, (const uint64_t*)vals, n, node, y, y ? ys : nullptr, mass_prefix,
-                           tiles, mass_state, mass_samples, (int32_t)check_square, status);
+                           tiles, mass_state, mass_samples, z_samples, (int32_t)check_square, status);
         MH_HIP_TRY(hipGetLastError());
         return MH_OK;
     }

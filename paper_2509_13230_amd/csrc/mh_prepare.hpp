@@ -21,6 +21,7 @@ struct NetBuffers {
     uint64_t* scan_state;  // look-back state of the two plan scans (P, then hoff)
     int64_t scan_words;
     uint64_t* Psamp;       // P[256 k] (written by the order's one-pass scan)
+    double* Zsamp;         // z[256 k] (the same)
     int32_t* hbrow;        // first row of every round of heavy items (written by the plan's scan)
     int64_t n;
     int32_t T;

@@ -58,13 +58,18 @@ constexpr int kPlanThreads = 1024;
 constexpr int kPlanSamples = 4096;
 
 // z of every zstep-th column into LDS (zstep: the smallest power of two >= 256
-// that leaves at most kPlanSamples samples); returns zstep, sets *nz.
-__device__ __forceinline__ int64_t stage_col_samples(const NodeRec* __restrict__ col, int64_t nc, double* s_z,
-                                                     int64_t* nz) {
+// that leaves at most kPlanSamples samples); returns zstep, sets *nz.  From
+// zsamp (z[256 k], contiguous) when given: a gather of one record per 4 KB
+// page costs an address translation each.
+__device__ __forceinline__ int64_t stage_col_samples(const NodeRec* __restrict__ col, const double* zsamp,
+                                                     int64_t nc, double* s_z, int64_t* nz) {
     int64_t zstep = 256;
     while ((nc - 1) / zstep + 1 > kPlanSamples) zstep *= 2;
     *nz = (nc - 1) / zstep + 1;
-    for (int64_t q = threadIdx.x; q < *nz; q += blockDim.x) s_z[q] = col[q * zstep].z;
+    static_assert(kPlanSamples <= 4 * kPlanThreads, "four samples per thread");
+    const int64_t sstep = zstep >> kSampleShift;
+    if (zsamp) stage_lds<4>(s_z, *nz, [=](int64_t q) { return zsamp[q * sstep]; });
+    else stage_lds<4>(s_z, *nz, [=](int64_t q) { return col[q * zstep].z; });
     return zstep;
 }
 
@@ -99,7 +104,8 @@ __device__ __forceinline__ int64_t plan_row(NodeRec* __restrict__ node, int64_t 
         if (T <= 0) {
             total = 1;
         } else {
-            const int64_t nd = (J - first + T - 1) / T;
+            // (J - first < 2^31 and mass <= m for most rows: no 64-bit division then)
+            const int64_t nd = J > first ? (int64_t)((uint32_t)(J - first + T - 1) / (uint32_t)T) : 0;
             int64_t ns = 0;
             uint64_t m = 0;
             if (J < nc) {
@@ -108,7 +114,7 @@ __device__ __forceinline__ int64_t plan_row(NodeRec* __restrict__ node, int64_t 
                 else if (md < 1.0) m = 1;
                 else m = (uint64_t)md;
                 const uint64_t mass = P[nc] - P[J];
-                ns = (mass == 0) ? 1 : (int64_t)((mass + m - 1) / m);
+                ns = (mass <= m) ? 1 : (int64_t)((mass + m - 1) / m);
             }
             total = nd + ns;
             if (total >= 2) {
@@ -124,7 +130,8 @@ __device__ __forceinline__ int64_t plan_row(NodeRec* __restrict__ node, int64_t 
 // One row per thread.  A block that holds a row with a dense part (the hubs,
 // a few blocks at most) stages column samples in LDS first.
 __global__ __launch_bounds__(kPlanThreads) void k_row_plan(NodeRec* __restrict__ node, const double* __restrict__ c,
-                                                           int64_t n, const NodeRec* __restrict__ col, int64_t nc,
+                                                           int64_t n, const NodeRec* __restrict__ col,
+                                                           const double* __restrict__ zsamp, int64_t nc,
                                                            int32_t bip, int32_t T, const uint64_t* __restrict__ P,
                                                            int32_t* __restrict__ jend, uint64_t* __restrict__ mq,
                                                            uint64_t* __restrict__ hn) {
@@ -146,7 +153,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_row_plan(NodeRec* __restrict__
     int64_t J = first;
     if (__syncthreads_or(dense)) {
         int64_t nz;
-        const int64_t zstep = stage_col_samples(col, nc, s_z, &nz);
+        const int64_t zstep = stage_col_samples(col, zsamp, nc, s_z, &nz);
         __syncthreads();
         if (dense) J = dense_end(col, nc, s, cr, first, s_z, nz, zstep);
     }
@@ -165,7 +172,8 @@ constexpr int kHrThreads = 1024;  // heavy items per round of k_heavy_records
 
 __global__ __launch_bounds__(kLbThreads) void k_row_plan_scan(NodeRec* __restrict__ node,
                                                               const double* __restrict__ c, int64_t n,
-                                                              const NodeRec* __restrict__ col, int64_t nc,
+                                                              const NodeRec* __restrict__ col,
+                                                              const double* __restrict__ zsamp, int64_t nc,
                                                               int32_t bip, int32_t T, const uint64_t* __restrict__ P,
                                                               int32_t* __restrict__ jend, uint64_t* __restrict__ mq,
                                                               uint64_t* __restrict__ hoff, int64_t tiles,
@@ -199,7 +207,7 @@ __global__ __launch_bounds__(kLbThreads) void k_row_plan_scan(NodeRec* __restric
         }
         if (__syncthreads_or(any)) {
             int64_t nz;
-            const int64_t zstep = stage_col_samples(col, nc, s_z, &nz);
+            const int64_t zstep = stage_col_samples(col, zsamp, nc, s_z, &nz);
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < kLbItems; ++k)
@@ -235,12 +243,12 @@ __global__ __launch_bounds__(kLbThreads) void k_row_plan_scan(NodeRec* __restric
     }
 }
 
-static mh_status launch_row_plan(NodeRec* node, const double* c, int64_t n, const NodeRec* col, int64_t nc,
-                                 int32_t bip, int32_t T, const uint64_t* P, int32_t* jend, uint64_t* mq,
+static mh_status launch_row_plan(NodeRec* node, const double* c, int64_t n, const NodeRec* col, const double* zsamp,
+                                 int64_t nc, int32_t bip, int32_t T, const uint64_t* P, int32_t* jend, uint64_t* mq,
                                  uint64_t* hn, hipStream_t stream) {
     const unsigned grid = (unsigned)((n + kPlanThreads - 1) / kPlanThreads);
-    hipLaunchKernelGGL(k_row_plan, dim3(grid), dim3(kPlanThreads), 0, stream, node, c, n, col, nc, bip, T, P, jend,
-                       mq, hn);
+    hipLaunchKernelGGL(k_row_plan, dim3(grid), dim3(kPlanThreads), 0, stream, node, c, n, col, zsamp, nc, bip, T, P,
+                       jend, mq, hn);
     MH_HIP_TRY(hipGetLastError());
     return MH_OK;
 }
@@ -286,12 +294,16 @@ __global__ __launch_bounds__(kHrThreads) void k_heavy_records(NetDesc D, HeavyRe
     while (lb_samples(nc) > pstep * (kHrSamples - 1) + 1) pstep *= 2;
     const int64_t np = (lb_samples(nc) - 1) / pstep + 1;
     const int64_t ps = pstep << kSampleShift;
-    for (int64_t j = threadIdx.x; j < np; j += kHrThreads) s_p[j] = Psamp[j * pstep];
+    static_assert(kHrSamples <= 4 * kHrThreads && kHrRows + 1 <= 5 * kHrThreads, "staging per thread");
+    stage_lds<4>(s_p, np, [=](int64_t j) { return Psamp[j * pstep]; });
     for (int64_t round = blockIdx.x; round * kHrThreads < lim; round += gridDim.x) {
         const int64_t R0 = hbrow[round];
         __syncthreads();  // s_h of the previous round is no longer read
-        for (int j = threadIdx.x; j <= kHrRows; j += kHrThreads)
-            s_h[j] = R0 + j <= n ? D.hoff[R0 + j] : ~0ull;
+        const uint64_t* hoff = D.hoff;
+        stage_lds<5>(s_h, kHrRows + 1, [=](int64_t j) {
+            const uint64_t v = hoff[R0 + j <= n ? R0 + j : n];  // loaded unconditionally
+            return R0 + j <= n ? v : ~0ull;
+        });
         __syncthreads();
         const int64_t it = round * kHrThreads + threadIdx.x;
         if (it >= lim) continue;
@@ -384,22 +396,24 @@ static unsigned heavy_grid(int64_t rec_cap) {
 // 2^30 rows) one look-back kernel plans the rows, scans the counts and writes
 // the first row of every round of stored heavy items to hbrow (rows_known);
 // beyond, the row plan and three scan kernels.
-static mh_status plan_rows(NodeRec* node, const double* c, int64_t n, const NodeRec* col, int64_t nc, int32_t bip,
+static mh_status plan_rows(NodeRec* node, const double* c, int64_t n, const NodeRec* col, const double* zsamp,
+                           int64_t nc, int32_t bip,
                            int32_t T, const uint64_t* P, int32_t* jend, uint64_t* mq, uint64_t* hoff,
                            uint64_t* hoff_state, int32_t* hbrow, int64_t rec_cap, int32_t* status, void* scratch,
                            size_t scratch_bytes, bool* rows_known, hipStream_t stream) {
     *rows_known = false;
+    if (nc > (int64_t)1 << 30) zsamp = nullptr;  // written by the order's one-pass scan only
     if (hoff && n <= (int64_t)1 << 30) {
         const int64_t tiles = lb_tiles(n);
         const int64_t resident = resident_blocks(k_row_plan_scan, kLbThreads);
         const int64_t grid = tiles < resident ? tiles : resident;
-        hipLaunchKernelGGL(k_row_plan_scan, dim3((unsigned)grid), dim3(kLbThreads), 0, stream, node, c, n, col, nc,
-                           bip, T, P, jend, mq, hoff, tiles, hoff_state, hbrow, rec_cap, status);
+        hipLaunchKernelGGL(k_row_plan_scan, dim3((unsigned)grid), dim3(kLbThreads), 0, stream, node, c, n, col,
+                           zsamp, nc, bip, T, P, jend, mq, hoff, tiles, hoff_state, hbrow, rec_cap, status);
         MH_HIP_TRY(hipGetLastError());
         *rows_known = true;
         return MH_OK;
     }
-    mh_status st = launch_row_plan(node, c, n, col, nc, bip, T, P, jend, mq, hoff, stream);
+    mh_status st = launch_row_plan(node, c, n, col, zsamp, nc, bip, T, P, jend, mq, hoff, stream);
     if (st != MH_OK || !hoff) return st;
     return scan_exclusive_u64(hoff, hoff, n, scratch, scratch_bytes, stream);
 }
@@ -421,11 +435,12 @@ static NetBuffers carve_network_impl(A& ar, int64_t n, bool weighted, int32_t T)
     B.scan_words = seg ? 2 * lb_tiles(n) : 0;
     B.scan_state = ar.template take<uint64_t>(B.scan_words);
     B.Psamp = ar.template take<uint64_t>(seg ? lb_samples(n) : 0);
+    B.Zsamp = ar.template take<double>(seg ? lb_samples(n) : 0);
     B.hbrow = ar.template take<int32_t>(seg ? B.rec_cap / kHrThreads + 2 : 0);
     if (!weighted) B.ys = B.c = nullptr;
     if (!seg)
         B.P = nullptr, B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.scan_state = nullptr, B.Psamp = nullptr,
-        B.hbrow = nullptr;
+        B.Zsamp = nullptr, B.hbrow = nullptr;
     B.n = n;
     B.T = T;
     B.weighted = weighted;
@@ -495,7 +510,7 @@ mh_status prepare_network(const double* x, const double* y, const NetBuffers& B,
     if (n <= 0) return MH_OK;
     const bool seg = B.T > 0;
     mh_status st = order_nodes(x, B.weighted ? y : nullptr, n, nullptr, nullptr, B.ys, B.node, status, B.P,
-                               B.scan_state, B.Psamp, scratch, scratch_bytes, stream, true,
+                               B.scan_state, B.Psamp, B.Zsamp, scratch, scratch_bytes, stream, true,
                                ZeroRange{B.scan_state, B.scan_words}, counters);
     if (st != MH_OK) return st;
     if (ev && ev[1]) MH_HIP_TRY(hipEventRecord(ev[1], stream));
@@ -504,7 +519,7 @@ mh_status prepare_network(const double* x, const double* y, const NetBuffers& B,
         if (st != MH_OK) return st;
     }
     bool rows_known = false;
-    st = plan_rows(B.node, B.c, n, B.node, n, 0, B.T, B.P, B.jend, B.mq, B.hoff,
+    st = plan_rows(B.node, B.c, n, B.node, B.Zsamp, n, 0, B.T, B.P, B.jend, B.mq, B.hoff,
                    seg ? B.scan_state + lb_tiles(n) : nullptr, B.hbrow, B.rec_cap, status, scratch,
                    scratch_bytes, &rows_known, stream);
     if (st != MH_OK) return st;
@@ -661,7 +676,7 @@ mh_status plan_counts_impl(const double* zs, const double* c, int64_t n, int32_t
         mh_status st = scan_exclusive_u64(P, P, n, ar.base + off, ws_bytes - off, stream);
         if (st != MH_OK) return st;
     }
-    mh_status pst = launch_row_plan(node, c, n, node, n, 0, T, P, jend, mq, nullptr, stream);
+    mh_status pst = launch_row_plan(node, c, n, node, nullptr, n, 0, T, P, jend, mq, nullptr, stream);
     if (pst != MH_OK) return pst;
     hipLaunchKernelGGL(k_unpack_nseg, dim3(grid), dim3(kThreads), 0, stream, node, n, nseg);
     MH_HIP_TRY(hipGetLastError());
@@ -727,6 +742,7 @@ struct BipBuffers {
     uint64_t* scan_state;  // look-back state: P scan over the columns, then hoff over the rows
     int64_t scan_words;
     uint64_t* Psamp;  // P[256 k] over the columns
+    double* Zsamp;    // z[256 k] over the columns
     int32_t* hbrow;   // first row of every round of heavy items over the rows
 };
 
@@ -749,11 +765,12 @@ BipBuffers carve_bipartite(A& ar, int64_t nr, int64_t nc, bool weighted, int32_t
     B.scan_words = seg ? lb_tiles(nc) + lb_tiles(nr) : 0;
     B.scan_state = ar.template take<uint64_t>(B.scan_words);
     B.Psamp = ar.template take<uint64_t>(seg ? lb_samples(nc) : 0);
+    B.Zsamp = ar.template take<double>(seg ? lb_samples(nc) : 0);
     B.hbrow = ar.template take<int32_t>(seg ? B.rec_cap / kHrThreads + 2 : 0);
     if (!weighted) B.ysr = B.c = B.ysc = nullptr;
     if (!seg)
         B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.P = nullptr, B.scan_state = nullptr, B.Psamp = nullptr,
-        B.hbrow = nullptr;
+        B.Zsamp = nullptr, B.hbrow = nullptr;
     return B;
 }
 
@@ -822,10 +839,10 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
     if (st != MH_OK) return st;
     // A1: each set sorted by its own z; the column masses for the plan
     // (the rows' first kernel zeroes the look-back state of both plan scans)
-    st = order_nodes(xr, yr, nr, nullptr, nullptr, B.ysr, B.rows, status, nullptr, nullptr, nullptr, scratch,
+    st = order_nodes(xr, yr, nr, nullptr, nullptr, B.ysr, B.rows, status, nullptr, nullptr, nullptr, nullptr, scratch,
                      scratch_bytes, stream, false, ZeroRange{B.scan_state, B.scan_words});
     if (st != MH_OK) return st;
-    st = order_nodes(xc, yc, nc, nullptr, nullptr, B.ysc, B.cols, status, B.P, B.scan_state, B.Psamp, scratch,
+    st = order_nodes(xc, yc, nc, nullptr, nullptr, B.ysc, B.cols, status, B.P, B.scan_state, B.Psamp, B.Zsamp, scratch,
                      scratch_bytes, stream, false);
     if (st != MH_OK) return st;
     if (ev && ev[1]) MH_HIP_TRY(hipEventRecord(ev[1], stream));
@@ -846,7 +863,7 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
     MH_HIP_TRY(hipGetLastError());
     // A3: plan over the columns
     bool rows_known = false;
-    st = plan_rows(B.rows, B.c, nr, B.cols, nc, 1, T, B.P, B.jend, B.mq, B.hoff,
+    st = plan_rows(B.rows, B.c, nr, B.cols, B.Zsamp, nc, 1, T, B.P, B.jend, B.mq, B.hoff,
                    seg ? B.scan_state + lb_tiles(nc) : nullptr, B.hbrow, B.rec_cap, status, scratch,
                    scratch_bytes, &rows_known, stream);
     if (st != MH_OK) return st;
