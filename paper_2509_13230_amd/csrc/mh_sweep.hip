@@ -383,11 +383,13 @@ __global__ __launch_bounds__(kHrThreads) void k_heavy_records(NetDesc D, HeavyRe
 
 }  // namespace
 
-// Blocks for the heavy records: one item per thread, up to 4 blocks per CU
-// (the item count is known only on the device; rec_cap bounds it).
+// Blocks for the heavy records: one item per thread in rounds of kHrThreads,
+// at most the blocks resident at once (the item count is known only on the
+// device, so most of a grid sized by rec_cap would be dispatched only to exit;
+// the blocks loop over the rounds instead).
 static unsigned heavy_grid(int64_t rec_cap) {
     const int64_t want = (rec_cap + kHrThreads - 1) / kHrThreads;
-    const int64_t cap = 4 * (int64_t)device_cus();
+    const int64_t cap = resident_blocks(k_heavy_records, kHrThreads);
     return (unsigned)(want < 1 ? 1 : (want < cap ? want : cap));
 }
 
