@@ -101,6 +101,54 @@ def cpu_baseline(x: np.ndarray, seed: int, seg_work: int, budget_s: float) -> di
                       f"{t_total:.1f} s single-threaded"}
 
 
+# VALU instructions per pair of the brute-force sampler's loop (Philox block,
+# the column's z, the uniform and the test), counted in the gfx950 code of
+# k_bruteforce<false>; staging of accepted pairs is not counted as work.
+BF_VALU_PER_PAIR = 65
+
+
+def bruteforce_vs_mh(args, x, dev) -> dict:
+    """The GPU brute-force sampler (every pair with its own Philox block)
+    against the plain MH sampler on one network: the first 50,000 nodes of the
+    N = 1M workload with their fitted x.  Both are synchronous calls that read
+    their edge count back; the time of each is the best of a few runs."""
+    import torch
+
+    import paper_2509_13230_amd as mh
+
+    xp = x[: args.bf_prefix].contiguous()
+    n = xp.numel()
+    pairs = n * (n - 1) // 2
+
+    def best(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        return min(t), out
+
+    t_bf, (sb, _) = best(lambda: mh.sample_bruteforce(xp, seed=args.seed, replica=0), 3)
+    t_mh, (sm, _) = best(lambda: mh.sample_unweighted(xp, seed=args.seed, replica=0, seg_work=args.seg_work), 10)
+    return {
+        "workload": f"first {n} nodes of the N=1M workload (their fitted x), one sample",
+        "pairs": pairs,
+        "ms_bruteforce": t_bf * 1e3,
+        "pairs_per_s_bruteforce": pairs / t_bf,
+        "edges_bruteforce": int(sb.numel()),
+        "edges_per_s_bruteforce": sb.numel() / t_bf,
+        "bruteforce_valu": {"achieved": pairs * BF_VALU_PER_PAIR / t_bf / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                            "unit": "TOP/s", "frac": pairs * BF_VALU_PER_PAIR / t_bf / PEAK_LANE_OPS},
+        "ms_mh": t_mh * 1e3,
+        "edges_mh": int(sm.numel()),
+        "edges_per_s_mh": sm.numel() / t_mh,
+        "speedup_mh_vs_bruteforce": t_bf / t_mh,
+    }
+
+
 def batched_ensemble(args, dev) -> dict:
     """The ensemble workload: 256 networks (N log-uniform in [1e3, 2e5],
     x = exp(Normal(-5, 2))) x 16 replicas = 4,096 samples.  Times one
@@ -213,6 +261,8 @@ def main():
     ap.add_argument("--grid-blocks", type=int, default=0, help="sweep grid (0 = all resident blocks)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--bf-prefix", type=int, default=50_000,
+                    help="nodes of the brute-force comparison network (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -334,6 +384,8 @@ def main():
     }
     if not args.skip_batched:
         out["batched"] = batched_ensemble(args, dev)
+    if args.bf_prefix > 0:
+        out["bruteforce"] = bruteforce_vs_mh(args, x, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, args.seed, args.seg_work, args.cpu_budget)
     print(json.dumps(out), flush=True)
