@@ -149,6 +149,56 @@ def bruteforce_vs_mh(args, x, dev) -> dict:
     }
 
 
+# VALU instructions per (row, column) pair of the expected-degree kernels'
+# inner loops, weighted, counted in their gfx950 code (one refined reciprocal
+# per pair; per iteration of four pairs: forward 95, adjoint 148).
+DEG_FWD_VALU_PER_PAIR = 95 / 4
+DEG_BWD_VALU_PER_PAIR = 148 / 4
+
+
+def expected_degree_bench(args, dev) -> dict:
+    """The O(N^2) expected degree / strength reduction and its adjoint on the
+    weighted N = 200,000 workload (power-law degrees 2.3 on [1, 5000], strengths
+    k (1 + Gamma(2, 3)); parameters from the sparse-limit recipe)."""
+    import torch
+
+    import paper_2509_13230_amd as mh
+    import workloads
+
+    k, st = workloads.cfg3_targets(seed=3, n=args.deg_n)
+    xn, yn = workloads.uecm_recipe(k, st)
+    x = torch.as_tensor(xn, device=dev)
+    y = torch.as_tensor(yn, device=dev)
+    n = x.numel()
+    gk = torch.ones(n, dtype=torch.float64, device=dev)
+    gs = torch.ones(n, dtype=torch.float64, device=dev)
+
+    def best(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        return min(t)
+
+    t_f = best(lambda: mh.expected_degree(x, y))
+    t_b = best(lambda: mh.expected_degree_grad(x, y, None, gk, gs))
+    pairs = n * n
+    return {
+        "workload": f"UECM N={n}: forward (k, s) and adjoint (gx, gy), binary64",
+        "pairs": pairs,
+        "ms_forward": t_f * 1e3,
+        "ms_adjoint": t_b * 1e3,
+        "forward_valu": {"achieved": pairs * DEG_FWD_VALU_PER_PAIR / t_f / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                         "unit": "TOP/s", "frac": pairs * DEG_FWD_VALU_PER_PAIR / t_f / PEAK_LANE_OPS},
+        "adjoint_valu": {"achieved": pairs * DEG_BWD_VALU_PER_PAIR / t_b / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                         "unit": "TOP/s", "frac": pairs * DEG_BWD_VALU_PER_PAIR / t_b / PEAK_LANE_OPS},
+    }
+
+
 def batched_ensemble(args, dev) -> dict:
     """The ensemble workload: 256 networks (N log-uniform in [1e3, 2e5],
     x = exp(Normal(-5, 2))) x 16 replicas = 4,096 samples.  Times one
@@ -263,6 +313,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--bf-prefix", type=int, default=50_000,
                     help="nodes of the brute-force comparison network (0: skip it)")
+    ap.add_argument("--deg-n", type=int, default=200_000,
+                    help="nodes of the expected-degree measurement (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -386,6 +438,8 @@ def main():
         out["batched"] = batched_ensemble(args, dev)
     if args.bf_prefix > 0:
         out["bruteforce"] = bruteforce_vs_mh(args, x, dev)
+    if args.deg_n > 0:
+        out["expected_degree"] = expected_degree_bench(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_np, args.seed, args.seg_work, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -3,6 +3,7 @@
 // every column value loaded from cache is used kRows times, and each row's
 // partial sums are combined across the 64 lanes in a fixed order at the end
 // (deterministic, error about (n/64) ulp instead of n ulp).
+#include <cfloat>
 #include "mh_common.hpp"
 #include "mh_internal.hpp"
 
@@ -14,6 +15,26 @@ constexpr int kThreads = 256;
 constexpr int kWavesPerBlock = kThreads / kWave;
 constexpr int kRows = 4;
 constexpr int kRowsPerBlock = kWavesPerBlock * kRows;
+
+// 1/d for d > 0 from the hardware reciprocal refined by two Newton-Raphson
+// steps (about 1 ulp).  A quotient n/d becomes n times it, and the quotients
+// of one pair share their denominator, so one reciprocal replaces up to five
+// divisions.  From d = 2^1000 on, d is scaled by 2^-100 around the reciprocal
+// so that the hardware estimate stays in the normal range; that path is taken
+// by whole waves, only when one of their lanes needs it.
+__device__ __forceinline__ double newton_rcp(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return fma(fma(-d, r, 1.0), r, r);
+}
+
+__device__ __forceinline__ double rcp_refined(double d) {
+    if (__builtin_expect(__any(d >= 0x1.0p1000), 0)) {
+        const double s = d < 0x1.0p1000 ? 1.0 : 0x1.0p-100;
+        return newton_rcp(d * s) * s;
+    }
+    return newton_rcp(d);
+}
 
 template <bool WEIGHTED>
 __global__ __launch_bounds__(kThreads) void k_expdeg_fwd(const double* __restrict__ x, const double* __restrict__ y,
@@ -39,20 +60,26 @@ __global__ __launch_bounds__(kThreads) void k_expdeg_fwd(const double* __restric
         const double mj = mult ? mult[j] : 1.0;
 #pragma unroll
         for (int q = 0; q < kRows; ++q) {
+            // straight-line code for every pair: a is clamped to the largest
+            // finite double, so that every term is finite and a pair of weight
+            // zero (the self-pair of a class of one, whose product alone may
+            // overflow) adds an exact zero; rows past n have x = 0 and are
+            // never stored
             const double wgt = (j == ii[q]) ? mj - 1.0 : mj;
-            if (wgt != 0.0 && ii[q] < n) {
-                const double a = xi[q] * xj;
-                if (WEIGHTED) {
-                    const double b = yi[q] * yj;
-                    const double ab = a * b;
-                    const double p = ab / (1.0 - b + ab);
-                    const double e = p / (1.0 - b);
-                    ak[q] += wgt * p;
-                    as[q] += wgt * e;
-                } else {
-                    const double p = a / (1.0 + a);
-                    ak[q] += wgt * p;
-                }
+            const double a = fmin(xi[q] * xj, DBL_MAX);
+            if (WEIGHTED) {
+                const double b = yi[q] * yj;
+                const double ab = a * b;
+                // p = ab / D and e = p / (1 - b) from one reciprocal of
+                // D (1 - b), which is at least (1 - b)^2 >= 2^-106
+                const double ob = 1.0 - b;
+                const double e = ab * rcp_refined((1.0 - b + ab) * ob);
+                const double p = e * ob;
+                ak[q] += wgt * p;
+                as[q] += wgt * e;
+            } else {
+                const double p = a * rcp_refined(1.0 + a);
+                ak[q] += wgt * p;
             }
         }
     }
@@ -80,7 +107,8 @@ __global__ __launch_bounds__(kThreads) void k_expdeg_bwd(const double* __restric
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t d0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kRows;
     if (d0 >= n) return;
-    double xd[kRows], yd[kRows], md[kRows], gkd[kRows], gsd[kRows], ax[kRows], ay[kRows];
+    double xd[kRows], yd[kRows], md[kRows], gkd[kRows], gsd[kRows], ax[kRows], ay[kRows], kdiag[kRows],
+        sdiag[kRows];
     int64_t dd[kRows];
 #pragma unroll
     for (int q = 0; q < kRows; ++q) {
@@ -93,6 +121,8 @@ __global__ __launch_bounds__(kThreads) void k_expdeg_bwd(const double* __restric
         gsd[q] = (WEIGHTED && ok) ? gs[dd[q]] : 0.0;
         ax[q] = 0.0;
         ay[q] = 0.0;
+        kdiag[q] = 2.0 * (md[q] - 1.0) * gkd[q];
+        sdiag[q] = 2.0 * (md[q] - 1.0) * gsd[q];
     }
     for (int64_t c = lane; c < n; c += kWave) {
         const double xc = x[c];
@@ -102,31 +132,27 @@ __global__ __launch_bounds__(kThreads) void k_expdeg_bwd(const double* __restric
         const double gsc = WEIGHTED ? gs[c] : 0.0;
 #pragma unroll
         for (int q = 0; q < kRows; ++q) {
-            if (dd[q] >= n) continue;
-            double fk, fs;
-            if (c == dd[q]) {
-                fk = 2.0 * (md[q] - 1.0) * gkd[q];
-                fs = WEIGHTED ? 2.0 * (md[q] - 1.0) * gsd[q] : 0.0;
-            } else {
-                fk = gkd[q] * mc + md[q] * gkc;
-                fs = WEIGHTED ? gsd[q] * mc + md[q] * gsc : 0.0;
-            }
-            if (fk == 0.0 && fs == 0.0) continue;
-            const double a = xd[q] * xc;
+            // straight-line as in the forward pass (a clamped, every term
+            // finite, zero factors add exact zeros)
+            const bool self = c == dd[q];
+            const double fk = self ? kdiag[q] : fma(gkd[q], mc, md[q] * gkc);
+            const double fs = WEIGHTED ? (self ? sdiag[q] : fma(gsd[q], mc, md[q] * gsc)) : 0.0;
+            const double a = fmin(xd[q] * xc, DBL_MAX);
             if (WEIGHTED) {
                 const double b = yd[q] * yc;
-                const double D = 1.0 - b + a * b;
-                const double D2 = D * D;
                 const double ob = 1.0 - b;
-                const double dpa = b * ob / D2;
-                const double dpb = a / D2;
-                const double dea = b / D2;
-                const double deb = a / (D2 * ob) + a * b / (D * ob * ob);
-                ax[q] += (fk * dpa + fs * dea) * xc;
-                ay[q] += (fk * dpb + fs * deb) * yc;
+                const double D = fma(a, b, ob);
+                const double r = rcp_refined(D * ob);
+                const double iD = ob * r, iob = D * r;
+                // x part: b / D^2 (fk (1 - b) + fs);
+                // y part: (a / D) (fk / D + fs / (1 - b) (1 / D + b / (1 - b))),
+                // grouped so that no factor underflows before the small ones
+                // multiply in
+                ax[q] = fma(b * (iD * iD) * xc, fma(fk, ob, fs), ax[q]);
+                ay[q] = fma(a * iD * yc, fma(fs * iob, fma(b, iob, iD), fk * iD), ay[q]);
             } else {
-                const double dpa = 1.0 / ((1.0 + a) * (1.0 + a));
-                ax[q] += fk * dpa * xc;
+                const double i1a = rcp_refined(1.0 + a);
+                ax[q] = fma(fk * xc, i1a * i1a, ax[q]);
             }
         }
     }

@@ -336,6 +336,34 @@ def test_expected_degree_grad_matches_oracle(mh, weighted):
         assert np.max(np.abs(gy.cpu().numpy() - ry)) <= 1e-10 * np.abs(ry).max()
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_expected_degree_wide_range(mh, weighted):
+    # x over 300 decades: products from 1e-320 (subnormal) to 1e302, beyond
+    # 2^1000 where the kernels divide instead of multiplying by a reciprocal;
+    # y up to 1 - 2^-40 so that 1 - y y' is tiny
+    rng = np.random.default_rng(10)
+    n = 1200
+    x = 10.0 ** rng.uniform(-160, 150, n)
+    x[:5] = [1e151, 3e150, 1e-160, 0.0, 1.0]
+    y = rng.uniform(0.0, 1.0, n) if weighted else None
+    if weighted:
+        y[:4] = [1 - 2.0 ** -40, 1 - 2.0 ** -40, 0.0, 0.5]
+    k, s = mh.expected_degree(dev(x), None if y is None else dev(y))
+    kr, sr = oracle.expected_degree(x, y)
+    assert np.max(np.abs(k.cpu().numpy() - kr) / np.maximum(kr, 1e-300)) <= 1e-10
+    if weighted:
+        assert np.max(np.abs(s.cpu().numpy() - sr) / np.maximum(sr, 1e-300)) <= 1e-10
+    gk = rng.normal(size=n)
+    gs = rng.normal(size=n) if weighted else None
+    gx, gy = mh.expected_degree_grad(dev(x), None if y is None else dev(y), None, dev(gk),
+                                     None if gs is None else dev(gs))
+    rx, ry = oracle.expected_degree_grad(x, y, None, gk, gs)
+    assert np.all(np.isfinite(gx.cpu().numpy()))
+    assert np.max(np.abs(gx.cpu().numpy() - rx)) <= 1e-10 * np.abs(rx).max()
+    if weighted:
+        assert np.max(np.abs(gy.cpu().numpy() - ry)) <= 1e-10 * np.abs(ry).max()
+
+
 # ------------------------------------------------------------------ full sizes
 def test_full_size_unweighted_matches_oracle(mh):
     # N = 1,000,000, power-law targets (exponent 2.1, k in [1, 1e4]); the bench's
