@@ -108,6 +108,16 @@ __device__ __forceinline__ uint64_t mass_q(double z) {
     return (uint64_t)(z * 4294967296.0);
 }
 
+// a * b + c as the three-address v_fma_f64.  In the sweep kernels the
+// compiler otherwise evaluates a Horner step as a copy of the loop-invariant
+// coefficient register followed by the two-address v_fmac_f64 (two
+// instructions instead of one); the result is the same correctly rounded fma.
+__device__ __forceinline__ double fma_vop3(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 // ------------------------------------------------------------------ logarithms
 // Natural logarithm for the sweep's two per-step logs, written out from the
 // series log(m) = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...), s = (m - 1)/(m + 1),
@@ -127,15 +137,15 @@ __device__ __forceinline__ double log_reduced(double m, int k) {
     sv = fma(fma(-sv, d, f), y, sv);
     const double z = sv * sv;
     double p = 1.0 / 21.0;
-    p = fma(p, z, 1.0 / 19.0);
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, 1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, 1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, 1.0 / 3.0);
+    p = fma_vop3(p, z, 1.0 / 19.0);
+    p = fma_vop3(p, z, 1.0 / 17.0);
+    p = fma_vop3(p, z, 1.0 / 15.0);
+    p = fma_vop3(p, z, 1.0 / 13.0);
+    p = fma_vop3(p, z, 1.0 / 11.0);
+    p = fma_vop3(p, z, 1.0 / 9.0);
+    p = fma_vop3(p, z, 1.0 / 7.0);
+    p = fma_vop3(p, z, 1.0 / 5.0);
+    p = fma_vop3(p, z, 1.0 / 3.0);
     const double s2 = sv + sv;
     const double lm = fma(s2, z * p, s2);
     // k ln2 in two parts: the high part has trailing zeros, so k * hi is exact
