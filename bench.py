@@ -40,10 +40,10 @@ HBM_PEAK_GBS = 8000.0
 
 # VALU instructions of one step of the sweep on its common path, counted in the
 # gfx950 code of k_sweep<false,false>: the draw (Philox block, the two
-# uniforms, the log of U1) 117, the acceptance test 15, the skip (log1p, the
+# uniforms, the log of U1) 109, the acceptance test 15, the skip (log1p, the
 # division, the next candidate's address) 67, the candidate load 1; loop,
 # refill and staging instructions are not counted as work.
-SWEEP_VALU_PER_STEP = 200
+SWEEP_VALU_PER_STEP = 192
 
 
 class HipEvents:

@@ -37,10 +37,24 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return {c0, c1, c2, c3};
 }
 
+// a * b + c as the three-address v_fma_f64.  In the sweep kernels the
+// compiler otherwise evaluates such a step as a copy of the loop-invariant
+// constant register followed by the two-address v_fmac_f64 (two instructions
+// instead of one); the result is the same correctly rounded fma.
+__device__ __forceinline__ double fma_vop3(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 // Uniform in (0, 1] from 53 bits: (((a << 21) | (b >> 11)) + 1) * 2^-53, exact in binary64.
 __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
-    const uint64_t m = ((uint64_t)a << 21) | (uint64_t)(b >> 11);
-    return (double)(m + 1u) * 0x1.0p-53;
+    // m = hi 2^32 + lo with hi = a >> 11 and lo = the low word of (a:b) >> 11;
+    // (m + 1) 2^-53 = hi 2^-21 + (lo + 1) 2^-53, each fma exact (each result
+    // is a multiple of 2^-53 no larger than 1, so it fits 53 bits)
+    const uint32_t hi = a >> 11;
+    const uint32_t lo = __builtin_amdgcn_alignbit(a, b, 11);
+    return fma_vop3((double)hi, 0x1.0p-21, fma_vop3((double)lo, 0x1.0p-53, 0x1.0p-53));
 }
 
 // ------------------------------------------------------------------ wave primitives
@@ -106,16 +120,6 @@ __device__ __forceinline__ double key_value(uint64_t key) {
 __device__ __forceinline__ uint64_t mass_q(double z) {
     if (z >= 1.0) return (uint64_t)1 << 32;
     return (uint64_t)(z * 4294967296.0);
-}
-
-// a * b + c as the three-address v_fma_f64.  In the sweep kernels the
-// compiler otherwise evaluates a Horner step as a copy of the loop-invariant
-// coefficient register followed by the two-address v_fmac_f64 (two
-// instructions instead of one); the result is the same correctly rounded fma.
-__device__ __forceinline__ double fma_vop3(double a, double b, double c) {
-    double d;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
 }
 
 // ------------------------------------------------------------------ logarithms
