@@ -47,6 +47,14 @@ __device__ __forceinline__ double fma_vop3(double a, double b, double c) {
     return d;
 }
 
+// 1/d for d in [2^-1000, 2^1000]: the hardware estimate refined by two
+// Newton-Raphson steps, within about 1 ulp (callers route other d elsewhere).
+__device__ __forceinline__ double newton_rcp(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return fma(fma(-d, r, 1.0), r, r);
+}
+
 // Uniform in (0, 1] from 53 bits: (((a << 21) | (b >> 11)) + 1) * 2^-53, exact in binary64.
 __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
     // m = hi 2^32 + lo with hi = a >> 11 and lo = the low word of (a:b) >> 11;

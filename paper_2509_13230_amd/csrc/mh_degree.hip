@@ -22,12 +22,6 @@ constexpr int kRowsPerBlock = kWavesPerBlock * kRows;
 // divisions.  From d = 2^1000 on, d is scaled by 2^-100 around the reciprocal
 // so that the hardware estimate stays in the normal range; that path is taken
 // by whole waves, only when one of their lanes needs it.
-__device__ __forceinline__ double newton_rcp(double d) {
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(fma(-d, r, 1.0), r, r);
-    return fma(fma(-d, r, 1.0), r, r);
-}
-
 __device__ __forceinline__ double rcp_refined(double d) {
     if (__builtin_expect(__any(d >= 0x1.0p1000), 0)) {
         const double s = d < 0x1.0p1000 ? 1.0 : 0x1.0p-100;
