@@ -549,16 +549,12 @@ void launch_sweep(const SweepLaunch& A, int64_t n, int32_t grid_blocks, hipStrea
     auto kern = k_sweep<W, S, false, OUT_EDGES, BIP>;
     int64_t want = (n + kWave - 1) / kWave;
     if (want < 16) want = 16;
-    // Default: 3 blocks (12 waves) per CU.  With fewer, larger per-wave item
-    // lists the lanes of a wave stay busier while its long chains finish, and
-    // 3 waves per SIMD still cover the load latency (measured on N = 1e6).
+    // Default: every block that fits at once (4 per CU unweighted, 3 weighted:
+    // the LDS stages bound it).  On N = 1e6 the unweighted sweep takes 64, 53
+    // and 51 us at 2, 3 and 4 blocks per CU: more waves per SIMD hide more of
+    // each iteration's load.
     int64_t cap = resident_blocks(kern, kThreads);
-    const int cus = device_cus();
-    if (grid_blocks > 0) {
-        if (grid_blocks < cap) cap = grid_blocks;
-    } else if ((int64_t)3 * cus < cap) {
-        cap = (int64_t)3 * cus;
-    }
+    if (grid_blocks > 0 && grid_blocks < cap) cap = grid_blocks;
     hipLaunchKernelGGL(kern, dim3((unsigned)(want < cap ? want : cap)), dim3(kThreads), 0, stream, A);
 }
 
