@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_zero_degrees(const NetDesc* 
 __global__ void k_batch_init(Counters* c) {
     if (threadIdx.x == 0) {
         c->n_edges = 0;
-        for (int i = 0; i < ST_COUNT; ++i) c->stats[i] = 0;
+        for (int i = 0; i < ST_COUNT; ++i) c->stats[i].v = 0;
         c->pad = 0;  // status is kept: it records invalid networks found by the preparation
     }
 }

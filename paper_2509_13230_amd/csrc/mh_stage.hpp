@@ -98,23 +98,32 @@ struct WaveStage {
     }
 };
 
+// A wave counts itself in *s_arrived (LDS, zeroed at block start) once its
+// LDS writes are done; true for the block's last wave, which then sees every
+// other wave's writes.
+template <int WAVES>
+__device__ __forceinline__ bool block_arrive(uint32_t* s_arrived) {
+    __threadfence_block();
+    uint32_t prev = 0;
+    if (__lane_id() == 0) prev = atomicAdd(s_arrived, 1u);
+    prev = __shfl(prev, 0, kWave);
+    if (prev != (uint32_t)(WAVES - 1)) return false;
+    __threadfence_block();
+    return true;
+}
+
 // End of a block's work: each wave leaves its unflushed count in s_fill and
-// counts itself in *s_arrived (LDS, zeroed at block start); the last wave to
-// arrive reserves the slots of all the block's stages with one atomic and
-// writes them.  Stage w of kind X is at s_X + w * kStageEdges.
+// arrives (block_arrive); the last wave to arrive reserves the slots of all
+// the block's stages with one atomic and writes them.  Stage w of kind X is
+// at s_X + w * kStageEdges.  Returns whether this wave was the last.
 template <bool WEIGHTED, int WAVES>
-__device__ __forceinline__ void block_final_flush(uint32_t fill, const int32_t* s_src, const int32_t* s_dst,
+__device__ __forceinline__ bool block_final_flush(uint32_t fill, const int32_t* s_src, const int32_t* s_dst,
                                                   const int32_t* s_w, const int32_t* s_sid, uint32_t* s_fill,
                                                   uint32_t* s_arrived, const EdgeOut& out, int32_t* sid_out) {
     const int lane = (int)__lane_id();
     const int wave = (int)(threadIdx.x >> 6);
     if (lane == 0) s_fill[wave] = fill;
-    __threadfence_block();  // this wave's stage and count are written before it counts itself
-    uint32_t prev = 0;
-    if (lane == 0) prev = atomicAdd(s_arrived, 1u);
-    prev = __shfl(prev, 0, kWave);
-    if (prev != (uint32_t)(WAVES - 1)) return;
-    __threadfence_block();
+    if (!block_arrive<WAVES>(s_arrived)) return false;
     uint32_t offs[WAVES];
     uint32_t total = 0;
 #pragma unroll
@@ -122,7 +131,7 @@ __device__ __forceinline__ void block_final_flush(uint32_t fill, const int32_t* 
         offs[w] = total;
         total += s_fill[w];
     }
-    if (total == 0) return;
+    if (total == 0) return true;
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(out.count, (unsigned long long)total);
     base = __shfl(base, 0, kWave);
@@ -140,6 +149,7 @@ __device__ __forceinline__ void block_final_flush(uint32_t fill, const int32_t* 
             }
         }
     }
+    return true;
 }
 
 }  // namespace mh

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kThreads) void k_unpack_nseg(const NodeRec* __restr
 __global__ void k_init_counters(Counters* c) {
     if (threadIdx.x == 0) {
         c->n_edges = 0;
-        for (int i = 0; i < ST_COUNT; ++i) c->stats[i] = 0;
+        for (int i = 0; i < ST_COUNT; ++i) c->stats[i].v = 0;
         c->status = 0;
         c->pad = 0;
     }
@@ -567,11 +567,11 @@ mh_status read_counters(const Counters* ctr, int64_t capacity, int64_t* n_edges_
     if (hc.status != 0) return (mh_status)hc.status;
     *n_edges_host = (int64_t)hc.n_edges;
     if (stats_host) {
-        stats_host->steps = (int64_t)hc.stats[ST_STEPS];
-        stats_host->proposals = (int64_t)hc.stats[ST_PROPOSALS];
-        stats_host->accepts = (int64_t)hc.stats[ST_ACCEPTS];
-        stats_host->segments = (int64_t)hc.stats[ST_SEGMENTS];
-        stats_host->saturated_w = (int64_t)hc.stats[ST_SATURATED];
+        stats_host->steps = (int64_t)hc.stats[ST_STEPS].v;
+        stats_host->proposals = (int64_t)hc.stats[ST_PROPOSALS].v;
+        stats_host->accepts = (int64_t)hc.stats[ST_ACCEPTS].v;
+        stats_host->segments = (int64_t)hc.stats[ST_SEGMENTS].v;
+        stats_host->saturated_w = (int64_t)hc.stats[ST_SATURATED].v;
         stats_host->n_edges = (int64_t)hc.n_edges;
     }
     if ((int64_t)hc.n_edges > capacity) return MH_ECAPACITY;
@@ -900,11 +900,11 @@ mh_status sample_bipartite_impl(const double* xr, const double* yr, int64_t nr, 
     if (hc.status != 0) return (mh_status)hc.status;
     *n_edges_host = (int64_t)hc.n_edges;
     if (stats_host) {
-        stats_host->steps = (int64_t)hc.stats[ST_STEPS];
-        stats_host->proposals = (int64_t)hc.stats[ST_PROPOSALS];
-        stats_host->accepts = (int64_t)hc.stats[ST_ACCEPTS];
-        stats_host->segments = (int64_t)hc.stats[ST_SEGMENTS];
-        stats_host->saturated_w = (int64_t)hc.stats[ST_SATURATED];
+        stats_host->steps = (int64_t)hc.stats[ST_STEPS].v;
+        stats_host->proposals = (int64_t)hc.stats[ST_PROPOSALS].v;
+        stats_host->accepts = (int64_t)hc.stats[ST_ACCEPTS].v;
+        stats_host->segments = (int64_t)hc.stats[ST_SEGMENTS].v;
+        stats_host->saturated_w = (int64_t)hc.stats[ST_SATURATED].v;
         stats_host->n_edges = (int64_t)hc.n_edges;
     }
     if ((int64_t)hc.n_edges > capacity) return MH_ECAPACITY;

@@ -31,11 +31,18 @@ constexpr int kSweepWaves = kSweepThreads / kWave;
 
 enum { ST_STEPS = 0, ST_PROPOSALS, ST_ACCEPTS, ST_SEGMENTS, ST_SATURATED, ST_COUNT };
 
+// A statistics counter alone in 256 bytes: the blocks' atomics on different
+// counters then go to different lines and proceed side by side.
+struct alignas(256) StatSlot {
+    unsigned long long v;
+    unsigned long long pad[31];
+};
+
 struct Counters {
     unsigned long long n_edges;
-    unsigned long long stats[ST_COUNT];
     int32_t status;
     int32_t pad;
+    StatSlot stats[ST_COUNT];
 };
 
 struct HeavyRec {
@@ -149,9 +156,10 @@ enum : uint32_t { S_IDLE = 0, S_REC, S_LOAD, S_STEP, S_DONE };
 // BIP: two node sets (single-sample launches only); the column arrays and the
 // chain start differ, and NET_NO_SELF rejects the candidate with the row's id.
 // Returns the number of edges left in the wave's stage (written by the caller).
+// STATS: the wave's counts are left in st_out[ST_COUNT] (LDS) for the block.
 template <bool WEIGHTED, bool STATS, bool BATCH, int OUT, bool BIP>
 __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_src, int32_t* s_dst, int32_t* s_w,
-                                           int32_t* s_sid) {
+                                           int32_t* s_sid, unsigned long long* st_out) {
     static_assert(!(BIP && BATCH), "two-set networks are sampled one at a time");
     const int wave = threadIdx.x >> 6;
     const int64_t gwave = (int64_t)blockIdx.x * kSweepWaves + wave;
@@ -391,11 +399,11 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
         const unsigned long long v3 = wave_sum((unsigned long long)st_segs);
         const unsigned long long v4 = wave_sum((unsigned long long)st_sat);
         if ((threadIdx.x & 63) == 0) {
-            atomicAdd(&A.ctr->stats[ST_STEPS], v0);
-            atomicAdd(&A.ctr->stats[ST_PROPOSALS], v1);
-            atomicAdd(&A.ctr->stats[ST_ACCEPTS], v2);
-            atomicAdd(&A.ctr->stats[ST_SEGMENTS], v3);
-            atomicAdd(&A.ctr->stats[ST_SATURATED], v4);
+            st_out[ST_STEPS] = v0;
+            st_out[ST_PROPOSALS] = v1;
+            st_out[ST_ACCEPTS] = v2;
+            st_out[ST_SEGMENTS] = v3;
+            st_out[ST_SATURATED] = v4;
         }
     }
     return stage.fill;
@@ -409,15 +417,31 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepLaunch A) {
     __shared__ int32_t s_sid[BATCH ? kSweepWaves : 1][BATCH ? kStageEdges : 1];
     __shared__ uint32_t s_fill[kSweepWaves];
     __shared__ uint32_t s_arrived;
+    __shared__ unsigned long long s_st[STATS ? kSweepWaves : 1][ST_COUNT];
     if (A.ctr->status != 0) return;
     if (threadIdx.x == 0) s_arrived = 0;
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     const uint32_t fill = sweep_body<WEIGHTED, STATS, BATCH, OUT, BIP>(
-        A, s_src[wave], s_dst[wave], WEIGHTED ? s_w[wave] : nullptr, BATCH ? s_sid[wave] : nullptr);
+        A, s_src[wave], s_dst[wave], WEIGHTED ? s_w[wave] : nullptr, BATCH ? s_sid[wave] : nullptr,
+        STATS ? s_st[wave] : nullptr);
+    bool last = false;
     if (OUT == OUT_EDGES)
-        block_final_flush<WEIGHTED, kSweepWaves>(fill, &s_src[0][0], &s_dst[0][0], WEIGHTED ? &s_w[0][0] : nullptr,
-                                                 BATCH ? &s_sid[0][0] : nullptr, s_fill, &s_arrived, A.out, A.sid);
+        last = block_final_flush<WEIGHTED, kSweepWaves>(fill, &s_src[0][0], &s_dst[0][0],
+                                                        WEIGHTED ? &s_w[0][0] : nullptr, BATCH ? &s_sid[0][0] : nullptr,
+                                                        s_fill, &s_arrived, A.out, A.sid);
+    else if (STATS)
+        last = block_arrive<kSweepWaves>(&s_arrived);
+    // the block's statistics: one atomic per counter, from the last wave
+    if (STATS && last) {
+        const int lane = (int)(threadIdx.x & 63);
+        if (lane < ST_COUNT) {
+            unsigned long long t = 0;
+#pragma unroll
+            for (int w = 0; w < kSweepWaves; ++w) t += s_st[w][lane];
+            atomicAdd(&A.ctr->stats[lane].v, t);
+        }
+    }
 }
 
 }  // namespace mh
