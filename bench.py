@@ -324,9 +324,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(a sample's rows, or a batch's samples, would be sharded across GPUs with no "
-              "communication; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the sampler has no multi-GPU path (a sample's rows, or a "
+              "batch's samples, would be split across GPUs with no communication between them).", file=sys.stderr)
         sys.exit(2)
 
     import torch
