@@ -199,6 +199,73 @@ def expected_degree_bench(args, dev) -> dict:
     }
 
 
+def weighted_bench(args, dev) -> dict:
+    """The weighted sampler on the UECM N = 200,000 workload (power-law degrees
+    2.3 on [1, 5000], strengths k (1 + Gamma(2, 3)); parameters from the
+    sparse-limit recipe): samples issued back to back on one stream, edges/s,
+    and the stage times (order, bound + plan, sweep) of an untimed repeat."""
+    import torch
+
+    import paper_2509_13230_amd as mh
+    import workloads
+
+    k, st = workloads.cfg3_targets(seed=3, n=args.w_n)
+    xn, yn = workloads.uecm_recipe(k, st)
+    x = torch.as_tensor(xn, device=dev)
+    y = torch.as_tensor(yn, device=dev)
+    n = x.numel()
+    L = mh.lib()
+    plan = mh.PlanParams(args.seg_work, 0, 0, 0, None)
+    ws = torch.empty(L.mh_workspace_bytes(n, 1, ctypes.byref(plan)), dtype=torch.uint8, device=dev)
+    s0, _, _ = mh.sample_weighted(x, y, seed=args.seed, replica=0, seg_work=args.seg_work, workspace=ws)
+    cap = int(len(s0) * 1.1) + 65536
+    src = torch.empty(cap, dtype=torch.int32, device=dev)
+    dst = torch.empty(cap, dtype=torch.int32, device=dev)
+    w = torch.empty(cap, dtype=torch.int32, device=dev)
+    steps = args.steps
+    for i in range(args.warmup):
+        mh.sample_async(x, y, (src, dst, w), ws, seed=args.seed, replica=1 + i, seg_work=args.seg_work)
+    torch.cuda.synchronize()
+    replicas = [3000 + i for i in range(steps)]
+    t0 = time.perf_counter()
+    for r in replicas:
+        mh.sample_async(x, y, (src, dst, w), ws, seed=args.seed, replica=r, seg_work=args.seg_work)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    last_edges = mh.sample_result(ws, cap)
+    ev = HipEvents(4 * steps)
+    ev_size = ctypes.sizeof(ctypes.c_void_p)
+    edges = 0
+    weight_sum = 0
+    wsteps = 0
+    wprops = 0
+    stage = np.zeros(3)
+    for i, r in enumerate(replicas):
+        s_, _, w_, stt = mh.sample_weighted(x, y, seed=args.seed, replica=r, seg_work=args.seg_work, stats=True,
+                                            out=(src, dst, w), workspace=ws,
+                                            stage_events=ev.address + 4 * i * ev_size)
+        stage += [ev.elapsed_ms(4 * i, 4 * i + 1), ev.elapsed_ms(4 * i + 1, 4 * i + 2),
+                  ev.elapsed_ms(4 * i + 2, 4 * i + 3)]
+        edges += stt["n_edges"]
+        wsteps += stt["steps"]
+        wprops += stt["proposals"]
+        weight_sum += int(w_.sum().item())
+    if stt["n_edges"] != last_edges:
+        raise RuntimeError(f"timed and repeated weighted sample differ: {last_edges} vs {stt['n_edges']} edges")
+    return {
+        "workload": f"UECM N={n}, power-law degrees (exponent 2.3, k in [1, 5000]), strengths k (1 + Gamma(2, 3)), "
+                    "sparse-limit parameters; samples issued back to back on one stream",
+        "samples": steps,
+        "ms_per_sample": elapsed / steps * 1e3,
+        "edges_per_s": edges / elapsed,
+        "mean_edges_per_sample": edges / steps,
+        "mean_weight": weight_sum / max(edges, 1),
+        "steps_per_sample": wsteps / steps,
+        "proposals_per_sample": wprops / steps,
+        "stages_ms": {"order": stage[0] / steps, "bound_plan": stage[1] / steps, "sweep": stage[2] / steps},
+    }
+
+
 def batched_ensemble(args, dev) -> dict:
     """The ensemble workload: 256 networks (N log-uniform in [1e3, 2e5],
     x = exp(Normal(-5, 2))) x 16 replicas = 4,096 samples.  Times one
@@ -315,6 +382,7 @@ def main():
                     help="nodes of the brute-force comparison network (0: skip it)")
     ap.add_argument("--deg-n", type=int, default=200_000,
                     help="nodes of the expected-degree measurement (0: skip it)")
+    ap.add_argument("--w-n", type=int, default=200_000, help="nodes of the weighted measurement (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -447,6 +515,8 @@ def main():
         out["batched"] = batched_ensemble(args, dev)
     if args.bf_prefix > 0:
         out["bruteforce"] = bruteforce_vs_mh(args, x, dev)
+    if args.w_n > 0:
+        out["weighted"] = weighted_bench(args, dev)
     if args.deg_n > 0:
         out["expected_degree"] = expected_degree_bench(args, dev)
     if not args.no_cpu_baseline:

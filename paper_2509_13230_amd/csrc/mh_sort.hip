@@ -400,7 +400,12 @@ __global__ __launch_bounds__(kTieThreads) void k_tie_runs(const uint32_t* __rest
 constexpr int kFixThreads = 1024;
 constexpr int kFixWaves = kFixThreads / kWave;
 constexpr int kFixLds = 8192;  // runs up to this long are sorted in LDS
-constexpr int kFixList = 512;  // runs longer than a wave per chunk of 32768 ranks: < 512
+// A block of k_fix_runs takes chunks of 256 bitmap words (8192 ranks), read
+// by its first 4 waves: small chunks spread the runs longer than a wave (each
+// sorted by the whole block) over many blocks.
+constexpr int kFixChunkWords = 256;
+constexpr int kFixScanWaves = kFixChunkWords / kWave;
+constexpr int kFixList = 128;  // runs longer than a wave per chunk of 8192 ranks: at most 128
 
 // Sorts up to 64 values held one per lane (absent lanes hold ~0).
 __device__ __forceinline__ uint64_t wave_bitonic(uint64_t v) {
@@ -443,23 +448,35 @@ __device__ int64_t block_run_end(const uint32_t* __restrict__ hi, int64_t n, int
 }
 
 // Stable LSD sort of pay[a, b) by its high 32 bits (4 passes of 8 bits) through
-// alt[a, b), by one block; the result ends in pay.
+// alt[a, b), by one block; the result ends in pay.  One read counts the digits
+// of all four passes, and a pass whose digit is the same for every value moves
+// nothing (runs of near-equal keys differ only in their last bits, so most of
+// their passes are of this kind).
 __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__ alt, int64_t a, int64_t b,
-                              uint32_t* s_cnt /* kFixWaves * 256 */, uint32_t* s_off /* 256 */,
-                              uint32_t* s_scan /* kFixWaves */) {
+                              uint32_t* s_cnt /* kFixWaves * 256 */, uint32_t* s_hist /* 4 * 256 */,
+                              uint32_t* s_off /* 256 */, uint32_t* s_scan /* kFixWaves */,
+                              uint32_t* s_flag /* 4 */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t lt = lanemask_lt();
+    const uint32_t len = (uint32_t)(b - a);
+    for (int i = threadIdx.x; i < 4 * 256; i += kFixThreads) s_hist[i] = 0;
+    if (threadIdx.x < 4) s_flag[threadIdx.x] = 0;  // one flag per pass: no reset races a late reader
+    __syncthreads();
+    for (int64_t i = a + threadIdx.x; i < b; i += kFixThreads) {
+        const uint64_t v = pay[i];
+#pragma unroll
+        for (int pass = 0; pass < 4; ++pass) atomicAdd(&s_hist[pass * 256 + ((uint32_t)(v >> (32 + 8 * pass)) & 255u)], 1u);
+    }
+    __syncthreads();
     uint64_t* src = pay;
     uint64_t* dst = alt;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 32 + 8 * pass;
-        // digit counts over the run, then their exclusive scan
-        for (int i = threadIdx.x; i < 256; i += kFixThreads) s_off[i] = 0;
+        // a pass with one digit for all values keeps the order as it is
+        if (threadIdx.x < 256 && s_hist[pass * 256 + threadIdx.x] == len) s_flag[pass] = 1;
         __syncthreads();
-        for (int64_t i = a + threadIdx.x; i < b; i += kFixThreads)
-            atomicAdd(&s_off[(uint32_t)(src[i] >> shift) & 255u], 1u);
-        __syncthreads();
-        const uint32_t c = threadIdx.x < 256 ? s_off[threadIdx.x] : 0u;
+        if (s_flag[pass]) continue;  // the same for every thread of the block
+        const uint32_t c = threadIdx.x < 256 ? s_hist[pass * 256 + threadIdx.x] : 0u;
         const uint32_t ex = block_exclusive(c, s_scan);
         if (threadIdx.x < 256) s_off[threadIdx.x] = ex;
         __syncthreads();
@@ -513,11 +530,16 @@ __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__
         src = dst;
         dst = t;
     }
+    if (src != pay) {  // an odd number of passes moved the values: back to pay
+        for (int64_t i = a + threadIdx.x; i < b; i += kFixThreads) pay[i] = src[i];
+        __syncthreads();
+    }
 }
 
-// Sorts by pay every run whose start bit is set.  Blocks take chunks of
-// 32768 ranks (1024 bitmap words, 64 per wave); a wave sorts the runs of at
-// most 64 that start in its words at once, and hands longer ones to the block,
+// Sorts by pay every run whose start bit is set.  Blocks take chunks of 8192
+// ranks (256 bitmap words, 64 for each of the first four waves); a wave sorts
+// the runs of at most 64 that start in its words at once, and hands longer
+// ones to the block,
 // which sorts them after the chunk's small runs, in LDS up to kFixLds, else
 // through alt.
 __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __restrict__ hi,
@@ -529,14 +551,16 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
     __shared__ uint32_t s_nlist;
     __shared__ uint32_t s_off[256];
     __shared__ uint32_t s_scan[kFixWaves];
+    __shared__ uint32_t s_flag[4];
+    static_assert(kFixWaves * 256 + 4 * 256 <= 2 * kFixLds, "digit counts fit in the run buffer");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t words = (n + 31) >> 5;
-    constexpr int64_t kChunkWords = (int64_t)kFixWaves * kWave;
+    constexpr int64_t kChunkWords = kFixChunkWords;
     for (int64_t cw = (int64_t)blockIdx.x * kChunkWords; cw < words; cw += (int64_t)gridDim.x * kChunkWords) {
         if (threadIdx.x == 0) s_nlist = 0;
         __syncthreads();
         const int64_t wi = cw + (int64_t)wave * kWave + lane;
-        uint32_t word = wi < words ? bits[wi] : 0u;
+        uint32_t word = (wave < kFixScanWaves && wi < words) ? bits[wi] : 0u;
         uint64_t pending = __ballot(word != 0);
         while (pending) {
             const int src_lane = __ffsll((unsigned long long)pending) - 1;
@@ -596,7 +620,8 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
                 for (int i = threadIdx.x; i < len; i += kFixThreads) pay[a + i] = s_run[i];
                 __syncthreads();
             } else {
-                block_lsd_run(pay, alt, a, b, reinterpret_cast<uint32_t*>(s_run), s_off, s_scan);
+                block_lsd_run(pay, alt, a, b, reinterpret_cast<uint32_t*>(s_run),
+                              reinterpret_cast<uint32_t*>(s_run) + kFixWaves * 256, s_off, s_scan, s_flag);
             }
         }
         __syncthreads();
@@ -712,7 +737,7 @@ mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint
     hipLaunchKernelGGL(k_tie_runs, dim3((unsigned)tie_grid), dim3(kTieThreads), 0, stream, (const uint32_t*)hi,
                        (const uint64_t*)pay, n, s.bits);
     MH_HIP_TRY(hipGetLastError());
-    const int64_t chunks = (((n + 31) >> 5) + (int64_t)kFixWaves * kWave - 1) / ((int64_t)kFixWaves * kWave);
+    const int64_t chunks = (((n + 31) >> 5) + kFixChunkWords - 1) / kFixChunkWords;
     const int64_t cus = device_cus();
     const int64_t fix_grid = chunks < cus ? chunks : cus;
     hipLaunchKernelGGL(k_fix_runs, dim3((unsigned)fix_grid), dim3(kFixThreads), 0, stream, (const uint32_t*)hi, pay,

@@ -253,6 +253,12 @@ static mh_status launch_row_plan(NodeRec* node, const double* c, int64_t n, cons
     return MH_OK;
 }
 
+// Records (16 bytes each) are kept for up to kRecPerRow n + 4096 heavy items;
+// the sweep locates any further ones itself, by searches in global memory
+// that stall their lanes.  The weighted bound is loose where y is near 1:
+// UECM with N = 200,000 (degrees 2.3 on [1, 5000]) has 7.1 n heavy items at
+// seg_work 8, against 0.2 n for the unweighted N = 1e6 workload.
+constexpr int64_t kRecPerRow = 8;
 constexpr int kHrSamples = 4096;  // P samples a block of k_heavy_records stages in LDS
 constexpr int kHrRows = 4096;     // rows of hoff a block of k_heavy_records stages in LDS
 
@@ -432,13 +438,13 @@ static NetBuffers carve_network_impl(A& ar, int64_t n, bool weighted, int32_t T)
     B.jend = ar.template take<int32_t>(seg ? n : 0);
     B.mq = ar.template take<uint64_t>(seg ? n : 0);
     B.hoff = ar.template take<uint64_t>(seg ? n + 1 : 0);
-    B.rec_cap = seg ? n + 4096 : 0;  // records for up to this many heavy items; more are located in the sweep
-    B.rec = ar.template take<HeavyRec>(B.rec_cap);
+    B.rec_cap = seg ? kRecPerRow * n + 4096 : 0;
     B.scan_words = seg ? 2 * lb_tiles(n) : 0;
     B.scan_state = ar.template take<uint64_t>(B.scan_words);
     B.Psamp = ar.template take<uint64_t>(seg ? lb_samples(n) : 0);
     B.Zsamp = ar.template take<double>(seg ? lb_samples(n) : 0);
     B.hbrow = ar.template take<int32_t>(seg ? B.rec_cap / kHrThreads + 2 : 0);
+    B.rec = ar.template take<HeavyRec>(B.rec_cap);  // last: the large, mostly unused reserve
     if (!weighted) B.ys = B.c = nullptr;
     if (!seg)
         B.P = nullptr, B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.scan_state = nullptr, B.Psamp = nullptr,
@@ -754,8 +760,7 @@ BipBuffers carve_bipartite(A& ar, int64_t nr, int64_t nc, bool weighted, int32_t
     B.jend = ar.template take<int32_t>(seg ? nr : 0);
     B.mq = ar.template take<uint64_t>(seg ? nr : 0);
     B.hoff = ar.template take<uint64_t>(seg ? nr + 1 : 0);
-    B.rec_cap = seg ? nr + 4096 : 0;
-    B.rec = ar.template take<HeavyRec>(B.rec_cap);
+    B.rec_cap = seg ? kRecPerRow * nr + 4096 : 0;
     B.cols = ar.template take<NodeRec>(nc);
     B.ysc = ar.template take<double>(weighted ? nc : 0);
     B.P = ar.template take<uint64_t>(seg ? nc + 1 : 0);
@@ -765,6 +770,7 @@ BipBuffers carve_bipartite(A& ar, int64_t nr, int64_t nc, bool weighted, int32_t
     B.Psamp = ar.template take<uint64_t>(seg ? lb_samples(nc) : 0);
     B.Zsamp = ar.template take<double>(seg ? lb_samples(nc) : 0);
     B.hbrow = ar.template take<int32_t>(seg ? B.rec_cap / kHrThreads + 2 : 0);
+    B.rec = ar.template take<HeavyRec>(B.rec_cap);  // last: the large, mostly unused reserve
     if (!weighted) B.ysr = B.c = B.ysc = nullptr;
     if (!seg)
         B.jend = nullptr, B.mq = nullptr, B.hoff = nullptr, B.P = nullptr, B.scan_state = nullptr, B.Psamp = nullptr,

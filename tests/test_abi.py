@@ -48,8 +48,9 @@ def test_workspace_sizes_grow_with_n(L):
     b = L.mh_workspace_bytes(1_000_000, 0, ctypes.byref(p))
     c = L.mh_workspace_bytes(1_000_000, 1, ctypes.byref(p))
     assert 0 < a < b < c
-    # roughly linear: a few tens of bytes per node
-    assert b < 200 * 1_000_000
+    # roughly linear: a few hundred bytes per node (most of it room for the
+    # records of up to 8 heavy items per row)
+    assert b < 400 * 1_000_000
     assert L.mh_bruteforce_workspace_bytes(50_000) > 0
 
 
@@ -118,7 +119,7 @@ def test_bipartite_argument_errors(L):
     a = L.mh_bipartite_workspace_bytes(1000, 2000, 0, ctypes.byref(p))
     b = L.mh_bipartite_workspace_bytes(1_000_000, 2000, 0, ctypes.byref(p))
     c = L.mh_bipartite_workspace_bytes(1_000_000, 2000, 1, ctypes.byref(p))
-    assert 0 < a < b < c < 200 * 1_002_000
+    assert 0 < a < b < c < 400 * 1_002_000
 
 
 def test_binding_fails_loudly_without_device():

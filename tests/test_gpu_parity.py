@@ -103,12 +103,20 @@ def _cluster(rng, base, count, dups=0):
     return v
 
 
-@pytest.mark.parametrize("case", ["small", "lds", "giant", "edges", "mixed"])
+def _near(rng, base, count, bits):
+    # base * (1 + k 2^-52) with k < 2^bits (repeats allowed): the low half of
+    # the key varies in its lowest `bits` bits only
+    return base * (1.0 + rng.integers(0, 1 << bits, size=count).astype(np.float64) * 2.0**-52)
+
+
+@pytest.mark.parametrize("case", ["small", "lds", "giant", "edges", "mixed", "near"])
 def test_order_high_half_ties_matches_oracle(mh, case):
     # keys that tie in their high 32 bits but not in their low ones: the sort
     # passes order only the high halves, the repair kernel the rest (a wave per
-    # run of at most 64, LDS up to 8192, a block's LSD beyond)
-    rng = np.random.default_rng(["small", "lds", "giant", "edges", "mixed"].index(case) + 40)
+    # run of at most 64, LDS up to 8192, a block's LSD beyond, which moves
+    # values only in the passes whose digit varies: "near" has runs beyond
+    # 8192 with 1, 2 and 3 such passes)
+    rng = np.random.default_rng(["small", "lds", "giant", "edges", "mixed", "near"].index(case) + 40)
     if case == "small":
         x = rng.lognormal(-4, 1.5, 300_000)  # tens of thousands of short runs
     elif case == "lds":
@@ -120,9 +128,12 @@ def test_order_high_half_ties_matches_oracle(mh, case):
         # run lengths around the wave and LDS limits, one run at each end
         parts = [_cluster(rng, 2.0 ** (4 - i), c) for i, c in enumerate([64, 65, 63, 8192, 8193, 2, 8191])]
         x = np.concatenate(parts + [np.full(1000, 1e-3), _cluster(rng, 2.0**-12, 100)])
-    else:
+    elif case == "mixed":
         x = np.concatenate([rng.lognormal(-4, 1.5, 100_000), _cluster(rng, 0.5, 3000, 3000),
                             np.round(rng.lognormal(-2, 1, 100_000), 4), _cluster(rng, 0.125, 20_000)])
+    else:
+        x = np.concatenate([_near(rng, 0.5, 20_000, 8), _near(rng, 0.25, 30_000, 16), _near(rng, 2.0, 12_000, 24),
+                            rng.lognormal(-3, 1, 50_000)])
     x = x[rng.permutation(len(x))]
     perm, zs, _, status = mh.order(dev(x))
     assert int(status.item()) == 0
