@@ -399,13 +399,14 @@ __global__ __launch_bounds__(kTieThreads) void k_tie_runs(const uint32_t* __rest
 // ------------------------------------------------------------------ run repair
 constexpr int kFixThreads = 1024;
 constexpr int kFixWaves = kFixThreads / kWave;
-constexpr int kFixLds = 8192;  // runs up to this long are sorted in LDS
-// A block of k_fix_runs takes chunks of 256 bitmap words (8192 ranks), read
-// by its first 4 waves: small chunks spread the runs longer than a wave (each
+constexpr int kFixBitonic = 512;  // runs up to this long are sorted in LDS (bitonic), longer ones by block_lsd_run
+constexpr int kFixLds = 2560;     // u64 words of LDS: the bitonic buffer, or block_lsd_run's digit counts
+// A block of k_fix_runs takes chunks of 64 bitmap words (2048 ranks), read by
+// its first wave: small chunks spread the runs longer than a wave (each
 // sorted by the whole block) over many blocks.
-constexpr int kFixChunkWords = 256;
+constexpr int kFixChunkWords = 64;
 constexpr int kFixScanWaves = kFixChunkWords / kWave;
-constexpr int kFixList = 128;  // runs longer than a wave per chunk of 8192 ranks: at most 128
+constexpr int kFixList = 32;  // runs longer than a wave per chunk of 2048 ranks: at most 32
 
 // Sorts up to 64 values held one per lane (absent lanes hold ~0).
 __device__ __forceinline__ uint64_t wave_bitonic(uint64_t v) {
@@ -536,12 +537,11 @@ __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__
     }
 }
 
-// Sorts by pay every run whose start bit is set.  Blocks take chunks of 8192
-// ranks (256 bitmap words, 64 for each of the first four waves); a wave sorts
-// the runs of at most 64 that start in its words at once, and hands longer
-// ones to the block,
-// which sorts them after the chunk's small runs, in LDS up to kFixLds, else
-// through alt.
+// Sorts by pay every run whose start bit is set.  Blocks take chunks of 2048
+// ranks (64 bitmap words, one per lane of the first wave); that wave sorts the
+// runs of at most 64 that start in its words at once, and hands longer ones to
+// the block, which sorts them after the chunk's small runs: in LDS (bitonic)
+// up to kFixBitonic, else by block_lsd_run through alt.
 __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __restrict__ hi,
                                                           uint64_t* __restrict__ pay, uint64_t* __restrict__ alt,
                                                           int64_t n, const uint32_t* __restrict__ bits) {
@@ -553,6 +553,7 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
     __shared__ uint32_t s_scan[kFixWaves];
     __shared__ uint32_t s_flag[4];
     static_assert(kFixWaves * 256 + 4 * 256 <= 2 * kFixLds, "digit counts fit in the run buffer");
+    static_assert(kFixBitonic <= kFixLds, "a bitonic run fits in the run buffer");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t words = (n + 31) >> 5;
     constexpr int64_t kChunkWords = kFixChunkWords;
@@ -596,7 +597,7 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
             const int64_t a = s_list[q];
             const int64_t b = block_run_end(hi, n, a, &s_pos);
             const int64_t len = b - a;
-            if (len <= kFixLds) {
+            if (len <= kFixBitonic) {
                 int p2 = 128;
                 while (p2 < len) p2 <<= 1;
                 for (int i = threadIdx.x; i < p2; i += kFixThreads) s_run[i] = i < len ? pay[a + i] : ~0ull;

@@ -113,9 +113,9 @@ def _near(rng, base, count, bits):
 def test_order_high_half_ties_matches_oracle(mh, case):
     # keys that tie in their high 32 bits but not in their low ones: the sort
     # passes order only the high halves, the repair kernel the rest (a wave per
-    # run of at most 64, LDS up to 8192, a block's LSD beyond, which moves
-    # values only in the passes whose digit varies: "near" has runs beyond
-    # 8192 with 1, 2 and 3 such passes)
+    # run of at most 64, LDS up to 512, a block's LSD beyond, which moves
+    # values only in the passes whose digit varies: "near" has long runs with
+    # 1, 2 and 3 such passes)
     rng = np.random.default_rng(["small", "lds", "giant", "edges", "mixed", "near"].index(case) + 40)
     if case == "small":
         x = rng.lognormal(-4, 1.5, 300_000)  # tens of thousands of short runs
@@ -126,7 +126,7 @@ def test_order_high_half_ties_matches_oracle(mh, case):
                             _cluster(rng, 2.0, 9000)])
     elif case == "edges":
         # run lengths around the wave and LDS limits, one run at each end
-        parts = [_cluster(rng, 2.0 ** (4 - i), c) for i, c in enumerate([64, 65, 63, 8192, 8193, 2, 8191])]
+        parts = [_cluster(rng, 2.0 ** (4 - i), c) for i, c in enumerate([64, 65, 63, 8192, 8193, 2, 8191, 512, 513])]
         x = np.concatenate(parts + [np.full(1000, 1e-3), _cluster(rng, 2.0**-12, 100)])
     elif case == "mixed":
         x = np.concatenate([rng.lognormal(-4, 1.5, 100_000), _cluster(rng, 0.5, 3000, 3000),
