@@ -509,6 +509,7 @@ def main():
                    "fit_residual": fit.residual},
         "stages_ms": {"order": stage[0] / args.steps, "bound_plan": stage[1] / args.steps, "sweep": sweep_ms},
         "sweep_steps_per_sample": steps_total / args.steps,
+        "sweep_only_edges_per_s": edges_per_sweep / (sweep_ms * 1e-3),
         "roofline": roof,
     }
     if not args.skip_batched:
