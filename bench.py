@@ -266,6 +266,57 @@ def weighted_bench(args, dev) -> dict:
     }
 
 
+def bipartite_bench(args, dev) -> dict:
+    """The two-set sampler (Sec. 2.6) on 1,000,000 rows (degrees power law 2.1
+    on [1, 10^4]) x 500,000 columns (2.5, rescaled to the same edge total),
+    sparse-limit parameters: synchronous samples (each reads its edge count
+    back), edges/s and the stage times of the same calls."""
+    import torch
+
+    import paper_2509_13230_amd as mh
+    import workloads
+
+    xr_n, xc_n, _, _ = workloads.bipartite_params(n_rows=args.bip_rows, n_cols=args.bip_rows // 2)
+    xr = torch.as_tensor(xr_n, device=dev)
+    xc = torch.as_tensor(xc_n, device=dev)
+    L = mh.lib()
+    plan = mh.PlanParams(args.seg_work, 0, 0, 0, None)
+    ws = torch.empty(L.mh_bipartite_workspace_bytes(xr.numel(), xc.numel(), 0, ctypes.byref(plan)),
+                     dtype=torch.uint8, device=dev)
+    first = mh.sample_bipartite(xr, xc, seed=args.seed, replica=0, seg_work=args.seg_work, workspace=ws)
+    cap = int(first.src.numel() * 1.1) + 65536
+    out = (torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev))
+    for i in range(args.warmup):
+        mh.sample_bipartite(xr, xc, seed=args.seed, replica=1 + i, seg_work=args.seg_work, out=out, workspace=ws)
+    steps = args.steps
+    ev = HipEvents(4 * steps)
+    ev_size = ctypes.sizeof(ctypes.c_void_p)
+    edges = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        r = mh.sample_bipartite(xr, xc, seed=args.seed, replica=4000 + i, seg_work=args.seg_work, out=out,
+                                workspace=ws)
+        edges += r.src.numel()
+    elapsed = time.perf_counter() - t0
+    # stage times from a repeat of the same samples with events (untimed)
+    stage = np.zeros(3)
+    for i in range(steps):
+        mh.sample_bipartite(xr, xc, seed=args.seed, replica=4000 + i, seg_work=args.seg_work, out=out,
+                            workspace=ws, stage_events=ev.address + 4 * i * ev_size)
+        stage += [ev.elapsed_ms(4 * i, 4 * i + 1), ev.elapsed_ms(4 * i + 1, 4 * i + 2),
+                  ev.elapsed_ms(4 * i + 2, 4 * i + 3)]
+    return {
+        "workload": f"bipartite {xr.numel()} x {xc.numel()}, degrees power law 2.1 / 2.5 on [1, 10^4], sparse-limit "
+                    "parameters; synchronous samples (edge count read back each time)",
+        "samples": steps,
+        "ms_per_sample": elapsed / steps * 1e3,
+        "edges_per_s": edges / elapsed,
+        "mean_edges_per_sample": edges / steps,
+        "stages_ms": {"order": stage[0] / steps, "bound_plan": stage[1] / steps, "sweep": stage[2] / steps},
+    }
+
+
 def batched_ensemble(args, dev) -> dict:
     """The ensemble workload: 256 networks (N log-uniform in [1e3, 2e5],
     x = exp(Normal(-5, 2))) x 16 replicas = 4,096 samples.  Times one
@@ -383,6 +434,8 @@ def main():
     ap.add_argument("--deg-n", type=int, default=200_000,
                     help="nodes of the expected-degree measurement (0: skip it)")
     ap.add_argument("--w-n", type=int, default=200_000, help="nodes of the weighted measurement (0: skip it)")
+    ap.add_argument("--bip-rows", type=int, default=1_000_000,
+                    help="rows of the bipartite measurement, with half as many columns (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -518,6 +571,8 @@ def main():
         out["bruteforce"] = bruteforce_vs_mh(args, x, dev)
     if args.w_n > 0:
         out["weighted"] = weighted_bench(args, dev)
+    if args.bip_rows > 0:
+        out["bipartite"] = bipartite_bench(args, dev)
     if args.deg_n > 0:
         out["expected_degree"] = expected_degree_bench(args, dev)
     if not args.no_cpu_baseline:
