@@ -79,7 +79,10 @@ typedef struct {
     int64_t n_edges;     /* same as accepts */
 } mh_stats;
 
-/* Bytes of workspace the sampler needs for n nodes (weighted != 0: UECM). */
+/* Bytes of workspace the sampler needs for n nodes (weighted != 0: UECM):
+ * about 200-220 bytes per node with segments (plan->seg_work > 0), most of it room
+ * for the records of up to 8 n + 4096 segments of heavy rows; a sample with
+ * more locates the others in its sweep, correctly but more slowly. */
 size_t mh_workspace_bytes(int64_t n, int weighted, const mh_plan_params* plan);
 
 /* Sample one network from the unweighted model (Sec. 2.4).
