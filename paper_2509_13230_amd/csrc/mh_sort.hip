@@ -19,9 +19,9 @@
 // update into an error, never a hang.  Keys are then reordered by digit in LDS
 // and written in coalesced runs.
 //
-// Repair: one kernel marks the start of every run of equal hi that holds a
-// descent of pay (a bitmap), a second sorts the marked runs by pay -- a wave
-// per run of up to 64, a block and LDS up to 8192, and a block-level LSD
+// Repair: one kernel finds every run of equal hi that holds a descent of pay,
+// claims it for one block (a bit at the run's start), and sorts it by pay --
+// a wave per run of up to 64, a block and LDS up to 512, and a block-level LSD
 // through scratch beyond.  Inputs whose keys differ within their high halves
 // (fitted parameters: ties by degree class) have no such runs.
 #include "mh_common.hpp"
@@ -348,8 +348,6 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
 }
 
 // ------------------------------------------------------------------ tie runs
-constexpr int kTieThreads = 256;
-
 // First index in [0, r] whose key equals hi[r] (hi ascending).
 __device__ __forceinline__ int64_t run_start(const uint32_t* __restrict__ hi, int64_t r) {
     const uint32_t h = hi[r];
@@ -362,51 +360,16 @@ __device__ __forceinline__ int64_t run_start(const uint32_t* __restrict__ hi, in
     return lo;
 }
 
-// Marks bit a of `bits` for every run [a, b) of equal hi whose pay is not
-// ascending.  A wave covers 64 consecutive ranks; of the descents it sees in
-// one run, the first marks it, and only a run that began before the wave's
-// first rank needs a search for its start.
-__global__ __launch_bounds__(kTieThreads) void k_tie_runs(const uint32_t* __restrict__ hi,
-                                                          const uint64_t* __restrict__ pay, int64_t n,
-                                                          uint32_t* __restrict__ bits) {
-    const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * kTieThreads;
-    const int64_t first = (int64_t)blockIdx.x * kTieThreads + (threadIdx.x & ~63);
-    for (int64_t wbase = first; wbase < n; wbase += stride) {
-        const int64_t r = wbase + lane;
-        bool eq = false, desc = false;
-        if (r > 0 && r < n) {
-            eq = hi[r - 1] == hi[r];
-            if (eq) desc = pay[r - 1] > pay[r];
-        }
-        const uint64_t dm = __ballot(desc);
-        if (dm == 0) continue;
-        const uint64_t starts = __ballot(!eq) & ~1ull;  // run starts inside the wave (lane 0 aside)
-        if (desc) {
-            const uint64_t le = lanemask_lt();
-            const uint64_t before = starts & le;
-            const int s = before ? 63 - __clzll((long long)before) : 0;  // segment's first lane in the wave
-            const uint64_t seg_desc = dm & le & ~((1ull << s) - 1);   // earlier descents in the segment
-            if (seg_desc == 0) {
-                const int64_t a = (before || !(wbase > 0 && hi[wbase - 1] == hi[wbase])) ? wbase + s
-                                                                                        : run_start(hi, wbase);
-                atomicOr(&bits[a >> 5], 1u << (a & 31));
-            }
-        }
-    }
-}
-
 // ------------------------------------------------------------------ run repair
 constexpr int kFixThreads = 1024;
 constexpr int kFixWaves = kFixThreads / kWave;
 constexpr int kFixBitonic = 512;  // runs up to this long are sorted in LDS (bitonic), longer ones by block_lsd_run
 constexpr int kFixLds = 2560;     // u64 words of LDS: the bitonic buffer, or block_lsd_run's digit counts
-// A block of k_fix_runs takes chunks of 64 bitmap words (2048 ranks), read by
-// its first wave: small chunks spread the runs longer than a wave (each
-// sorted by the whole block) over many blocks.
-constexpr int kFixChunkWords = 64;
-constexpr int kFixScanWaves = kFixChunkWords / kWave;
-constexpr int kFixList = 32;  // runs longer than a wave per chunk of 2048 ranks: at most 32
+// A block of k_fix_runs takes chunks of 2048 ranks: small chunks spread the
+// runs longer than a wave (each sorted by the whole block) over many blocks.
+constexpr int kFixChunk = 2048;
+constexpr int kFixClaims = kFixChunk / 2;  // runs with a descent among 2048 ranks: at most 1024
+constexpr int kFixList = 64;  // runs of 64 or more ranks meeting a chunk of 2048: at most 34
 
 // Sorts up to 64 values held one per lane (absent lanes hold ~0).
 __device__ __forceinline__ uint64_t wave_bitonic(uint64_t v) {
@@ -537,59 +500,83 @@ __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__
     }
 }
 
-// Sorts by pay every run whose start bit is set.  Blocks take chunks of 2048
-// ranks (64 bitmap words, one per lane of the first wave); that wave sorts the
-// runs of at most 64 that start in its words at once, and hands longer ones to
-// the block, which sorts them after the chunk's small runs: in LDS (bitonic)
-// up to kFixBitonic, else by block_lsd_run through alt.
+// Finds and sorts by pay every run of equal hi whose pay descends somewhere.
+// Blocks take chunks of 2048 ranks; each wave looks at 64 ranks at a time, and
+// the first descent it sees in a run claims the run by setting the run's
+// start bit in `claims` (zero at launch) with an atomic OR: the one block that
+// sets it sorts the whole run, wherever it lies.  A run without a descent is
+// never claimed, however long; while its owner sorts a run, other blocks may
+// read that run's values mid-sort, which can only make them try the claim
+// again, and fail.  The block's claimed runs of less than 64 ranks are sorted
+// by single waves at once; longer ones by the whole block: in LDS (bitonic) up
+// to kFixBitonic, else by block_lsd_run through alt.
 __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __restrict__ hi,
                                                           uint64_t* __restrict__ pay, uint64_t* __restrict__ alt,
-                                                          int64_t n, const uint32_t* __restrict__ bits) {
+                                                          int64_t n, uint32_t* __restrict__ claims) {
     __shared__ uint64_t s_run[kFixLds];
+    __shared__ int64_t s_claim[kFixClaims];
     __shared__ int64_t s_list[kFixList];
     __shared__ int64_t s_pos;
-    __shared__ uint32_t s_nlist;
+    __shared__ uint32_t s_nclaim, s_nlist;
     __shared__ uint32_t s_off[256];
     __shared__ uint32_t s_scan[kFixWaves];
     __shared__ uint32_t s_flag[4];
     static_assert(kFixWaves * 256 + 4 * 256 <= 2 * kFixLds, "digit counts fit in the run buffer");
     static_assert(kFixBitonic <= kFixLds, "a bitonic run fits in the run buffer");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t words = (n + 31) >> 5;
-    constexpr int64_t kChunkWords = kFixChunkWords;
-    for (int64_t cw = (int64_t)blockIdx.x * kChunkWords; cw < words; cw += (int64_t)gridDim.x * kChunkWords) {
-        if (threadIdx.x == 0) s_nlist = 0;
+    for (int64_t c0 = (int64_t)blockIdx.x * kFixChunk; c0 < n; c0 += (int64_t)gridDim.x * kFixChunk) {
+        const int64_t c1 = c0 + kFixChunk < n ? c0 + kFixChunk : n;
+        if (threadIdx.x == 0) {
+            s_nclaim = 0;
+            s_nlist = 0;
+        }
         __syncthreads();
-        const int64_t wi = cw + (int64_t)wave * kWave + lane;
-        uint32_t word = (wave < kFixScanWaves && wi < words) ? bits[wi] : 0u;
-        uint64_t pending = __ballot(word != 0);
-        while (pending) {
-            const int src_lane = __ffsll((unsigned long long)pending) - 1;
-            uint32_t wsrc = __shfl(word, src_lane, kWave);
-            const int64_t wbase = (cw + (int64_t)wave * kWave + src_lane) << 5;
-            while (wsrc) {
-                const int bit = __ffs(wsrc) - 1;
-                wsrc &= wsrc - 1;
-                const int64_t a = wbase + bit;
-                const uint32_t h = hi[a];
-                const int64_t r = a + lane;
-                const bool in = r < n && hi[r] == h;
-                const uint64_t inm = __ballot(in);
-                if (inm == ~0ull) {
-                    if (lane == 0) {
-                        const uint32_t slot = atomicAdd(&s_nlist, 1u);
-                        if (slot < kFixList) s_list[slot] = a;
-                    }
-                } else {
-                    // run of length < 64: lanes below the first differing lane
-                    const int len = __ffsll((unsigned long long)~inm) - 1;
-                    const bool mine = lane < len;
-                    uint64_t v = mine ? pay[r] : ~0ull;
-                    v = wave_bitonic(v);
-                    if (mine) pay[r] = v;
+        // 1. descents, and the claims of their runs
+        for (int64_t wbase = c0 + (int64_t)wave * kWave; wbase < c1; wbase += (int64_t)kFixWaves * kWave) {
+            const int64_t r = wbase + lane;
+            bool eq = false, desc = false;
+            if (r > 0 && r < c1) {
+                eq = hi[r - 1] == hi[r];
+                if (eq) desc = pay[r - 1] > pay[r];
+            }
+            const uint64_t dm = __ballot(desc);
+            if (dm == 0) continue;
+            const uint64_t starts = __ballot(!eq) & ~1ull;  // run starts inside the wave (lane 0 aside)
+            if (desc) {
+                const uint64_t le = lanemask_lt();
+                const uint64_t before = starts & le;
+                const int st = before ? 63 - __clzll((long long)before) : 0;  // segment's first lane in the wave
+                const uint64_t seg_desc = dm & le & ~((1ull << st) - 1);   // earlier descents in the segment
+                if (seg_desc == 0) {
+                    const int64_t a = (before || !(wbase > 0 && hi[wbase - 1] == hi[wbase])) ? wbase + st
+                                                                                            : run_start(hi, wbase);
+                    const uint32_t mask = 1u << (a & 31);
+                    if ((atomicOr(&claims[a >> 5], mask) & mask) == 0) s_claim[atomicAdd(&s_nclaim, 1u)] = a;
                 }
             }
-            pending &= pending - 1;
+        }
+        __syncthreads();
+        // 2. the claimed runs: below 64 ranks by a wave each, longer ones listed
+        const uint32_t ncl = s_nclaim;
+        for (uint32_t q = (uint32_t)wave; q < ncl; q += kFixWaves) {
+            const int64_t a = s_claim[q];
+            const uint32_t h = hi[a];
+            const int64_t r = a + lane;
+            const bool in = r < n && hi[r] == h;
+            const uint64_t inm = __ballot(in);
+            if (inm == ~0ull) {
+                if (lane == 0) {
+                    const uint32_t slot = atomicAdd(&s_nlist, 1u);
+                    if (slot < kFixList) s_list[slot] = a;
+                }
+            } else {
+                // run of length < 64: lanes below the first differing lane
+                const int len = __ffsll((unsigned long long)~inm) - 1;
+                const bool mine = lane < len;
+                uint64_t v = mine ? pay[r] : ~0ull;
+                v = wave_bitonic(v);
+                if (mine) pay[r] = v;
+            }
         }
         __syncthreads();
         const uint32_t nl = s_nlist < kFixList ? s_nlist : kFixList;
@@ -733,16 +720,11 @@ mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint
     }
     static_assert(kPasses % 2 == 0, "the passes end in the input arrays");
     // runs of equal high halves out of order by the low halves
-    const int64_t tie_grid_need = (n + kTieThreads - 1) / kTieThreads;
-    const int64_t tie_grid = tie_grid_need < 4096 ? tie_grid_need : 4096;
-    hipLaunchKernelGGL(k_tie_runs, dim3((unsigned)tie_grid), dim3(kTieThreads), 0, stream, (const uint32_t*)hi,
-                       (const uint64_t*)pay, n, s.bits);
-    MH_HIP_TRY(hipGetLastError());
-    const int64_t chunks = (((n + 31) >> 5) + kFixChunkWords - 1) / kFixChunkWords;
+    const int64_t chunks = (n + kFixChunk - 1) / kFixChunk;
     const int64_t cus = device_cus();
     const int64_t fix_grid = chunks < cus ? chunks : cus;
     hipLaunchKernelGGL(k_fix_runs, dim3((unsigned)fix_grid), dim3(kFixThreads), 0, stream, (const uint32_t*)hi, pay,
-                       pay_alt, n, (const uint32_t*)s.bits);
+                       pay_alt, n, s.bits);
     MH_HIP_TRY(hipGetLastError());
     return MH_OK;
 }
