@@ -109,14 +109,14 @@ def _near(rng, base, count, bits):
     return base * (1.0 + rng.integers(0, 1 << bits, size=count).astype(np.float64) * 2.0**-52)
 
 
-@pytest.mark.parametrize("case", ["small", "lds", "giant", "edges", "mixed", "near"])
+@pytest.mark.parametrize("case", ["small", "lds", "giant", "edges", "mixed", "near", "claimed"])
 def test_order_high_half_ties_matches_oracle(mh, case):
     # keys that tie in their high 32 bits but not in their low ones: the sort
     # passes order only the high halves, the repair kernel the rest (a wave per
     # run of at most 64, LDS up to 512, a block's LSD beyond, which moves
     # values only in the passes whose digit varies: "near" has long runs with
     # 1, 2 and 3 such passes)
-    rng = np.random.default_rng(["small", "lds", "giant", "edges", "mixed", "near"].index(case) + 40)
+    rng = np.random.default_rng(["small", "lds", "giant", "edges", "mixed", "near", "claimed"].index(case) + 40)
     if case == "small":
         x = rng.lognormal(-4, 1.5, 300_000)  # tens of thousands of short runs
     elif case == "lds":
@@ -131,9 +131,14 @@ def test_order_high_half_ties_matches_oracle(mh, case):
     elif case == "mixed":
         x = np.concatenate([rng.lognormal(-4, 1.5, 100_000), _cluster(rng, 0.5, 3000, 3000),
                             np.round(rng.lognormal(-2, 1, 100_000), 4), _cluster(rng, 0.125, 20_000)])
-    else:
+    elif case == "near":
         x = np.concatenate([_near(rng, 0.5, 20_000, 8), _near(rng, 0.25, 30_000, 16), _near(rng, 2.0, 12_000, 24),
                             rng.lognormal(-3, 1, 50_000)])
+    else:
+        # one run of 300,000 tied high halves with descents in every chunk of
+        # 2048 ranks: ~150 blocks see one and race to claim the run, while its
+        # owner sorts it; and a run of 200,000 exact ties (never claimed)
+        x = np.concatenate([_cluster(rng, 0.5, 300_000), np.full(200_000, 0.125), rng.lognormal(-3, 1, 50_000)])
     x = x[rng.permutation(len(x))]
     perm, zs, _, status = mh.order(dev(x))
     assert int(status.item()) == 0
