@@ -317,6 +317,39 @@ def bipartite_bench(args, dev) -> dict:
     }
 
 
+def atomic_add_rate(dev, slots: int = 1 << 22, blocks: int = 2048, iters: int = 256) -> float:
+    """Random int32 atomic adds per second on this GPU, from the probe library
+    (libmh_probe.so): blocks x 256 lanes, each adding 1 to `iters` random
+    counters of a table of `slots` (2^22 = 16 MB by default: the ensemble's
+    degree arrays in use at one time are of that order).  The degree sink
+    issues one such add per sampled edge, so this rate bounds it."""
+    import torch
+
+    import paper_2509_13230_amd as mh
+
+    path = os.path.join(os.path.dirname(mh.__file__), "libmh_probe.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2509_13230_amd.build`")
+    P = ctypes.CDLL(path)
+    P.mhp_atomic_adds.restype = ctypes.c_int
+    P.mhp_atomic_adds.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    buf = torch.zeros(slots, dtype=torch.int32, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    runs = []
+    for rep in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = P.mhp_atomic_adds(ctypes.c_void_p(buf.data_ptr()), slots, blocks, iters, stream)
+        torch.cuda.synchronize()
+        if rc != 0:
+            raise RuntimeError(f"mhp_atomic_adds failed ({rc})")
+        if rep:
+            runs.append(time.perf_counter() - t0)
+    n_ops = blocks * 256 * iters
+    assert int(buf.sum().item()) == 4 * n_ops
+    return n_ops / min(runs)
+
+
 def batched_ensemble(args, dev) -> dict:
     """The ensemble workload: 256 networks (N log-uniform in [1e3, 2e5],
     x = exp(Normal(-5, 2))) x 16 replicas = 4,096 samples.  Times one
@@ -397,6 +430,9 @@ def batched_ensemble(args, dev) -> dict:
         runs.append(time.perf_counter() - t0)
     t_batch = min(runs)
     batch_edges = int(deg.sum().item()) // 2
+    # The degree sink adds 1 to a column's counter per sampled edge (and each
+    # row's count once per row): bound by the GPU's rate of random atomic adds.
+    ceiling = atomic_add_rate(dev)
     return {
         "workload": f"{len(xs)} networks x {R} replicas = {S} samples, N log-uniform in [1e3, 2e5], "
                     "x = exp(Normal(-5, 2)), unweighted",
@@ -416,6 +452,11 @@ def batched_ensemble(args, dev) -> dict:
         "ms_plain_sync_total": t_plain * 1e3,
         "output": "degree sink (per-sample degree sequences)",
         "tuned": tuned,
+        "atomic_roofline": {"bound": "atomic", "achieved": batch_edges / t_batch, "peak": ceiling,
+                            "unit": "int32 atomic adds/s", "frac": batch_edges / t_batch / ceiling,
+                            "work_per_launch": f"{batch_edges} column adds (one per edge; per-row adds not counted)",
+                            "peak_source": "measured here (libmh_probe.so): 2048 x 256 lanes x 256 random int32 "
+                                           "atomic adds into 2^22 counters"},
     }
 
 

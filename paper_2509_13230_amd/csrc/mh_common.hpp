@@ -66,6 +66,23 @@ __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
 }
 
 // ------------------------------------------------------------------ wave primitives
+// A pointer into device memory, typed as such.  Pointers that a kernel reads
+// from device memory (a batch's table of networks) are otherwise compiled as
+// generic pointers: their loads become flat loads, and before a flat load the
+// compiler waits for every outstanding memory and LDS operation of the wave,
+// atomics included.  (The host pass parses device code without running it,
+// and its C++ rules refuse a copy out of another address space; there the
+// qualifier is left out.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MH_GLOBAL __attribute__((address_space(1)))
+#else
+#define MH_GLOBAL
+#endif
+template <class T>
+__device__ __forceinline__ const MH_GLOBAL T* in_global(const T* p) {
+    return (const MH_GLOBAL T*)p;
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const unsigned lane = __lane_id();
     return lane == 0 ? 0ull : (~0ull >> (64u - lane));

@@ -79,7 +79,8 @@ struct NetDesc {
     int32_t flags;         // NET_BIPARTITE, NET_NO_SELF
 };
 
-__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* __restrict__ a, int64_t lo, int64_t hi, uint64_t v) {
+__device__ __forceinline__ int64_t lower_bound_u64(const MH_GLOBAL uint64_t* __restrict__ a, int64_t lo, int64_t hi,
+                                                   uint64_t v) {
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo) / 2;
         if (a[mid] >= v) hi = mid; else lo = mid + 1;
@@ -87,7 +88,9 @@ __device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* __restrict__ 
     return lo;
 }
 
-__device__ __forceinline__ int64_t heavy_items(const NetDesc& D) { return D.hoff ? (int64_t)D.hoff[D.n] : 0; }
+__device__ __forceinline__ int64_t heavy_items(const NetDesc& D) {
+    return D.hoff ? (int64_t)in_global(D.hoff)[D.n] : 0;
+}
 
 __device__ __forceinline__ int64_t light_rows(const NetDesc& D) {
     return (D.flags & NET_BIPARTITE) ? D.n : (D.n > 1 ? D.n - 1 : 0);
@@ -97,16 +100,18 @@ __device__ __forceinline__ int64_t total_items(const NetDesc& D) { return heavy_
 
 // Row, segment index and column range of heavy item `it` (it < H).
 __device__ inline HeavyRec heavy_record(const NetDesc& D, int64_t it) {
+    const MH_GLOBAL uint64_t* hoff = in_global(D.hoff);
+    const MH_GLOBAL uint64_t* P = in_global(D.P);
     const int64_t n = D.n;
     int64_t lo = 0, hi = n;  // first row index with hoff > it, minus one
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo) / 2;
-        if (D.hoff[mid] > (uint64_t)it) hi = mid; else lo = mid + 1;
+        if (hoff[mid] > (uint64_t)it) hi = mid; else lo = mid + 1;
     }
     const int64_t r = lo - 1;
-    const int64_t g = it - (int64_t)D.hoff[r];
-    const int64_t nsg = (int64_t)(D.hoff[r + 1] - D.hoff[r]);
-    const int64_t J = D.jend[r];
+    const int64_t g = it - (int64_t)hoff[r];
+    const int64_t nsg = (int64_t)(hoff[r + 1] - hoff[r]);
+    const int64_t J = in_global(D.jend)[r];
     const int64_t T = D.T;
     const int64_t first = (D.flags & NET_BIPARTITE) ? 0 : r + 1;
     const int64_t nc = D.ncol;
@@ -118,10 +123,10 @@ __device__ inline HeavyRec heavy_record(const NetDesc& D, int64_t it) {
     } else {
         const int64_t kk = g - nd;
         const int64_t ns = nsg - nd;
-        const uint64_t base = D.P[J];
-        const uint64_t m = D.mq[r];
-        a = (kk == 0) ? J : lower_bound_u64(D.P, J, nc, base + (uint64_t)kk * m);
-        b = (kk == ns - 1) ? nc : lower_bound_u64(D.P, J, nc, base + (uint64_t)(kk + 1) * m);
+        const uint64_t base = P[J];
+        const uint64_t m = in_global(D.mq)[r];
+        a = (kk == 0) ? J : lower_bound_u64(P, J, nc, base + (uint64_t)kk * m);
+        b = (kk == ns - 1) ? nc : lower_bound_u64(P, J, nc, base + (uint64_t)(kk + 1) * m);
     }
     return HeavyRec{(int32_t)r, (int32_t)g, (int32_t)a, (int32_t)b};
 }
@@ -185,13 +190,13 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
     int32_t id = 0, sample = 0, row_deg = 0;
     double s = 0.0, cr = 1.0, ysr = 0.0, tq = 0.0, U2 = 0.0;
     // the lane's network
-    const NodeRec* node = A.net.node;
-    const double* ys = A.net.ys;
+    const MH_GLOBAL NodeRec* node = in_global(A.net.node);
+    const MH_GLOBAL double* ys = in_global(A.net.ys);
     // column arrays: their own only with two node sets (never batched); with
     // one set the candidates are read through `node` / `ys`, which follow the
     // lane's current network
-    const NodeRec* col = BIP ? A.net.col : nullptr;
-    const double* ysc = BIP ? A.net.ysc : nullptr;
+    const MH_GLOBAL NodeRec* col = in_global(BIP ? A.net.col : nullptr);
+    const MH_GLOBAL double* ysc = in_global(BIP ? A.net.ysc : nullptr);
     int32_t* deg = nullptr;
     // Values in flight from the previous iteration's loads.  The steps below
     // only choose addresses; each value is then loaded at one place at the end
@@ -208,11 +213,11 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
     int64_t kbase = 0;
 
     for (;;) {
-        const NodeRec* pa = nullptr;
-        const double* pb = nullptr;
-        const double* py = nullptr;
-        const double* pc = nullptr;
-        const HeavyRec* prc = nullptr;
+        const MH_GLOBAL NodeRec* pa = nullptr;
+        const MH_GLOBAL double* pb = nullptr;
+        const MH_GLOBAL double* py = nullptr;
+        const MH_GLOBAL double* pc = nullptr;
+        const MH_GLOBAL HeavyRec* prc = nullptr;
         // 1. the next draw of every lane that will draw this iteration
         const bool draws = (state == S_STEP) || (state == S_LOAD);
         double E = 0.0, U2n = 0.0;
@@ -295,7 +300,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
                 pa = &node[r];
                 pb = BIP ? &col[hr.a].z : &node[pos].z;
                 if (WEIGHTED) {
-                    pc = &D.c[r];
+                    pc = in_global(&D.c[r]);
                     py = &ys[r];
                 }
                 start_rb = true;
@@ -352,14 +357,14 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
                         Dp = &A.batch.nets[A.batch.sample_net[lo]];
                         replica = A.batch.sample_rep[lo];
                         H = heavy_items(*Dp);
-                        node = Dp->node;
-                        ys = Dp->ys;
+                        node = in_global(Dp->node);
+                        ys = in_global(Dp->ys);
                         if (OUT == OUT_DEGREES) deg = A.batch.degrees + A.batch.deg_off[lo];
                     }
                     if (it < H) {
                         rec_direct = it >= Dp->rec_cap;
                         rc_it = it;
-                        if (!rec_direct) prc = &Dp->rec[it];
+                        if (!rec_direct) prc = in_global(&Dp->rec[it]);
                         state = S_REC;
                     } else {
                         r = (int32_t)(it - H);
@@ -372,7 +377,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
                         if (BIP) pb = &col[0].z;
                         start_rb = BIP;
                         if (WEIGHTED) {
-                            pc = &Dp->c[r];
+                            pc = in_global(&Dp->c[r]);
                             py = &ys[r];
                         }
                         state = S_LOAD;

@@ -144,3 +144,24 @@ def test_sort_edges_argument_errors(L):
     a = L.mh_sort_edges_workspace_bytes(1000)
     b = L.mh_sort_edges_workspace_bytes(1_000_000)
     assert 0 < a < b < 40 * 1_000_000
+
+
+def test_probe_library_exports_and_checks_arguments(L):
+    """The benchmark's atomic-rate probe lives in a library of its own; its
+    argument checks (power-of-two table, positive grid) return before any
+    device work."""
+    import paper_2509_13230_amd as mh
+
+    path = os.path.join(os.path.dirname(mh.library_path()), "libmh_probe.so")
+    P = ctypes.CDLL(path)
+    f = P.mhp_atomic_adds
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    assert not hasattr(L, "mhp_atomic_adds")
+    fake = ctypes.c_void_p(0x1000)
+    assert f(None, 1024, 1, 1, None) == -1
+    assert f(fake, 1000, 1, 1, None) == -1
+    assert f(fake, 0, 1, 1, None) == -1
+    assert f(fake, 1 << 31, 1, 1, None) == -1
+    assert f(fake, 1024, 0, 1, None) == -1
+    assert f(fake, 1024, 1, -1, None) == -1
