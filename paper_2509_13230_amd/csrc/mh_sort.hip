@@ -348,10 +348,23 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
 }
 
 // ------------------------------------------------------------------ tie runs
-// First index in [0, r] whose key equals hi[r] (hi ascending).
+// First index in [0, r] whose key equals hi[r] (hi ascending).  Probes go back
+// from r in doubling steps of 64, 128, ... until one lands before the run (or
+// at 0), then bisect that last step: about 2 log2(d / 64) dependent loads for a
+// run that began d ranks before r, instead of log2(r).
 __device__ __forceinline__ int64_t run_start(const uint32_t* __restrict__ hi, int64_t r) {
     const uint32_t h = hi[r];
-    int64_t lo = 0, up = r;
+    int64_t up = r;  // hi[up] == h
+    int64_t lo = 0;  // every index below lo is before the run
+    for (int64_t step = 64;; step <<= 1) {
+        const int64_t p = up - step;
+        if (p <= 0) break;
+        if (hi[p] < h) {
+            lo = p + 1;
+            break;
+        }
+        up = p;
+    }
     while (lo < up) {
         const int64_t mid = (lo + up) >> 1;
         if (hi[mid] < h) lo = mid + 1;
@@ -363,8 +376,7 @@ __device__ __forceinline__ int64_t run_start(const uint32_t* __restrict__ hi, in
 // ------------------------------------------------------------------ run repair
 constexpr int kFixThreads = 1024;
 constexpr int kFixWaves = kFixThreads / kWave;
-constexpr int kFixBitonic = 512;  // runs up to this long are sorted in LDS (bitonic), longer ones by block_lsd_run
-constexpr int kFixLds = 2560;     // u64 words of LDS: the bitonic buffer, or block_lsd_run's digit counts
+constexpr int kFixLds = 2560;  // runs up to this long are sorted in LDS (block_lds_run), longer ones by block_lsd_run
 // A block of k_fix_runs takes chunks of 2048 ranks: small chunks spread the
 // runs longer than a wave (each sorted by the whole block) over many blocks.
 constexpr int kFixChunk = 2048;
@@ -411,31 +423,56 @@ __device__ int64_t block_run_end(const uint32_t* __restrict__ hi, int64_t n, int
     return up;
 }
 
-// Stable LSD sort of pay[a, b) by its high 32 bits (4 passes of 8 bits) through
-// alt[a, b), by one block; the result ends in pay.  One read counts the digits
-// of all four passes, and a pass whose digit is the same for every value moves
-// nothing (runs of near-equal keys differ only in their last bits, so most of
-// their passes are of this kind).
+// Stable LSD sort of pay[a, b) by its high 32 bits through alt[a, b), by one
+// block; the result ends in pay.  The digits are those of the high word minus
+// its least value in the run, 8 bits a pass, as many passes as the spread needs
+// (values of a run of near-equal keys lie a few units apart, so one pass, even
+// where they straddle a byte boundary).  One read counts the digits of every
+// pass, and a pass whose digit is the same for every value moves nothing.
 __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__ alt, int64_t a, int64_t b,
                               uint32_t* s_cnt /* kFixWaves * 256 */, uint32_t* s_hist /* 4 * 256 */,
                               uint32_t* s_off /* 256 */, uint32_t* s_scan /* kFixWaves */,
                               uint32_t* s_flag /* 4 */) {
+    __shared__ uint32_t s_mm[2];  // least and largest high word of the run
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t lt = lanemask_lt();
     const uint32_t len = (uint32_t)(b - a);
     for (int i = threadIdx.x; i < 4 * 256; i += kFixThreads) s_hist[i] = 0;
     if (threadIdx.x < 4) s_flag[threadIdx.x] = 0;  // one flag per pass: no reset races a late reader
+    if (threadIdx.x == 0) {
+        s_mm[0] = ~0u;
+        s_mm[1] = 0u;
+    }
     __syncthreads();
+    uint32_t mn = ~0u, mx = 0u;
     for (int64_t i = a + threadIdx.x; i < b; i += kFixThreads) {
-        const uint64_t v = pay[i];
+        const uint32_t h = (uint32_t)(pay[i] >> 32);
+        mn = h < mn ? h : mn;
+        mx = h > mx ? h : mx;
+    }
 #pragma unroll
-        for (int pass = 0; pass < 4; ++pass) atomicAdd(&s_hist[pass * 256 + ((uint32_t)(v >> (32 + 8 * pass)) & 255u)], 1u);
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t on = __shfl_xor(mn, d, kWave), ox = __shfl_xor(mx, d, kWave);
+        mn = on < mn ? on : mn;
+        mx = ox > mx ? ox : mx;
+    }
+    if (lane == 0) {
+        atomicMin(&s_mm[0], mn);
+        atomicMax(&s_mm[1], mx);
+    }
+    __syncthreads();
+    const uint32_t base = s_mm[0];
+    const uint32_t spread = s_mm[1] - base;
+    const int npass = spread == 0 ? 0 : (spread >> 8) == 0 ? 1 : (spread >> 16) == 0 ? 2 : (spread >> 24) == 0 ? 3 : 4;
+    for (int64_t i = a + threadIdx.x; i < b; i += kFixThreads) {
+        const uint32_t d = (uint32_t)(pay[i] >> 32) - base;
+        for (int pass = 0; pass < npass; ++pass) atomicAdd(&s_hist[pass * 256 + ((d >> (8 * pass)) & 255u)], 1u);
     }
     __syncthreads();
     uint64_t* src = pay;
     uint64_t* dst = alt;
-    for (int pass = 0; pass < 4; ++pass) {
-        const int shift = 32 + 8 * pass;
+    for (int pass = 0; pass < npass; ++pass) {
+        const int shift = 8 * pass;
         // a pass with one digit for all values keeps the order as it is
         if (threadIdx.x < 256 && s_hist[pass * 256 + threadIdx.x] == len) s_flag[pass] = 1;
         __syncthreads();
@@ -460,7 +497,7 @@ __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__
             for (int r = 0; r < kKeysPerLane; ++r) {
                 const int64_t i = wb + (int64_t)r * kWave + lane;
                 const bool valid = i < b;
-                const uint32_t dg = (uint32_t)(v[r] >> shift) & 255u;
+                const uint32_t dg = (((uint32_t)(v[r] >> 32) - base) >> shift) & 255u;
                 const uint64_t m = match_digit(dg, valid);
                 const uint32_t prior = s_cnt[wave * 256 + dg];
                 rk[r] = prior + (uint32_t)__popcll(m & lt);
@@ -484,7 +521,7 @@ __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__
             for (int r = 0; r < kKeysPerLane; ++r) {
                 const int64_t i = wb + (int64_t)r * kWave + lane;
                 if (i < b) {
-                    const uint32_t dg = (uint32_t)(v[r] >> shift) & 255u;
+                    const uint32_t dg = (((uint32_t)(v[r] >> 32) - base) >> shift) & 255u;
                     dst[a + s_cnt[wave * 256 + dg] + rk[r]] = v[r];
                 }
             }
@@ -500,6 +537,111 @@ __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__
     }
 }
 
+// Stable sort by the high 32 bits of the run of equal hi that starts at a, in
+// LDS, if the run ends within kFixLds ranks of a; returns false (nothing
+// written) if it is longer.  One read of the window finds the run's end and
+// loads its values; the digits are those of the high word minus its least value
+// in the run, 8 bits a pass, as many passes as the spread needs (one for a run
+// of near-equal keys); each pass ranks values stably as the block LSD does,
+// from s_a into s_b; one write returns the result.
+__device__ bool block_lds_run(const uint32_t* __restrict__ hi, uint64_t* __restrict__ pay, int64_t n, int64_t a,
+                              uint64_t* s_a /* kFixLds */, uint64_t* s_b /* kFixLds */,
+                              uint32_t* s_cnt /* kFixWaves * 256 */, uint32_t* s_scan /* kFixWaves */,
+                              uint32_t* s_misc /* 3 */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
+    const int win = n - a < kFixLds ? (int)(n - a) : kFixLds;
+    const uint32_t h0 = hi[a];
+    if (threadIdx.x == 0) {
+        s_misc[0] = (uint32_t)win;  // first rank of the window (from a) whose hi differs
+        s_misc[1] = ~0u;
+        s_misc[2] = 0u;
+    }
+    __syncthreads();
+    for (int i0 = 0; i0 < win; i0 += kFixThreads) {
+        const int i = i0 + threadIdx.x;
+        const bool in = i < win;
+        const uint64_t m = __ballot(in && hi[a + i] != h0);
+        // one atomic per wave: its first rank past the run
+        if (m && lane == __ffsll((unsigned long long)m) - 1) atomicMin(&s_misc[0], (uint32_t)i);
+        if (in) s_a[i] = pay[a + i];
+    }
+    // a run that fills the window may go on past it
+    const bool longer = a + win < n && hi[a + win] == h0;
+    __syncthreads();
+    const int len = (int)s_misc[0];
+    if (len == win && longer) return false;  // the same for every thread of the block
+    uint32_t mn = ~0u, mx = 0u;
+    for (int i = threadIdx.x; i < len; i += kFixThreads) {
+        const uint32_t h = (uint32_t)(s_a[i] >> 32);
+        mn = h < mn ? h : mn;
+        mx = h > mx ? h : mx;
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t on = __shfl_xor(mn, d, kWave), ox = __shfl_xor(mx, d, kWave);
+        mn = on < mn ? on : mn;
+        mx = ox > mx ? ox : mx;
+    }
+    if (lane == 0) {
+        atomicMin(&s_misc[1], mn);
+        atomicMax(&s_misc[2], mx);
+    }
+    __syncthreads();
+    const uint32_t base = s_misc[1];
+    const uint32_t spread = s_misc[2] - base;
+    const int npass = spread == 0 ? 0 : (spread >> 8) == 0 ? 1 : (spread >> 16) == 0 ? 2 : (spread >> 24) == 0 ? 3 : 4;
+    static_assert(kFixLds <= kFixWaves * kWaveKeys, "one round of the block ranks the whole window");
+    const int wb = wave * kWaveKeys;
+    const int nw = (len + kWaveKeys - 1) / kWaveKeys;  // waves that hold values
+    for (int pass = 0; pass < npass; ++pass) {
+        const int shift = 8 * pass;
+        for (int i = threadIdx.x; i < nw * 256; i += kFixThreads) s_cnt[i] = 0;
+        __syncthreads();
+        uint64_t v[kKeysPerLane];
+        uint32_t dg[kKeysPerLane], rk[kKeysPerLane];
+#pragma unroll
+        for (int r = 0; r < kKeysPerLane; ++r) {
+            const int i = wb + r * kWave + lane;
+            const bool valid = i < len;
+            v[r] = valid ? s_a[i] : 0ull;
+            dg[r] = ((((uint32_t)(v[r] >> 32)) - base) >> shift) & 255u;
+            const uint64_t m = match_digit(dg[r], valid);
+            const uint32_t prior = s_cnt[wave * 256 + dg[r]];
+            rk[r] = prior + (uint32_t)__popcll(m & lt);
+            __builtin_amdgcn_wave_barrier();
+            if (valid && (m & lt) == 0) s_cnt[wave * 256 + dg[r]] = prior + (uint32_t)__popcll(m);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        // per digit: the waves' counts become running offsets, then the digit's start is added
+        uint32_t tot = 0;
+        if (threadIdx.x < 256) {
+            for (int w = 0; w < nw; ++w) {
+                const uint32_t t = s_cnt[w * 256 + threadIdx.x];
+                s_cnt[w * 256 + threadIdx.x] = tot;
+                tot += t;
+            }
+        }
+        const uint32_t start = block_exclusive(tot, s_scan);
+        if (threadIdx.x < 256)
+            for (int w = 0; w < nw; ++w) s_cnt[w * 256 + threadIdx.x] += start;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kKeysPerLane; ++r) {
+            const int i = wb + r * kWave + lane;
+            if (i < len) s_b[s_cnt[wave * 256 + dg[r]] + rk[r]] = v[r];
+        }
+        __syncthreads();
+        uint64_t* t = s_a;
+        s_a = s_b;
+        s_b = t;
+    }
+    for (int i = threadIdx.x; i < len; i += kFixThreads) pay[a + i] = s_a[i];
+    __syncthreads();
+    return true;
+}
+
 // Finds and sorts by pay every run of equal hi whose pay descends somewhere.
 // Blocks take chunks of 2048 ranks; each wave looks at 64 ranks at a time, and
 // the first descent it sees in a run claims the run by setting the run's
@@ -508,12 +650,15 @@ __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__
 // never claimed, however long; while its owner sorts a run, other blocks may
 // read that run's values mid-sort, which can only make them try the claim
 // again, and fail.  The block's claimed runs of less than 64 ranks are sorted
-// by single waves at once; longer ones by the whole block: in LDS (bitonic) up
-// to kFixBitonic, else by block_lsd_run through alt.
+// by single waves at once; longer ones by the whole block: in LDS up to kFixLds
+// (block_lds_run), else by block_lsd_run through alt.
 __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __restrict__ hi,
                                                           uint64_t* __restrict__ pay, uint64_t* __restrict__ alt,
                                                           int64_t n, uint32_t* __restrict__ claims) {
     __shared__ uint64_t s_run[kFixLds];
+    __shared__ uint64_t s_run2[kFixLds];
+    __shared__ uint32_t s_wcnt[kFixWaves * 256];
+    __shared__ uint32_t s_misc[3];
     __shared__ int64_t s_claim[kFixClaims];
     __shared__ int64_t s_list[kFixList];
     __shared__ int64_t s_pos;
@@ -522,7 +667,6 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
     __shared__ uint32_t s_scan[kFixWaves];
     __shared__ uint32_t s_flag[4];
     static_assert(kFixWaves * 256 + 4 * 256 <= 2 * kFixLds, "digit counts fit in the run buffer");
-    static_assert(kFixBitonic <= kFixLds, "a bitonic run fits in the run buffer");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t c0 = (int64_t)blockIdx.x * kFixChunk; c0 < n; c0 += (int64_t)gridDim.x * kFixChunk) {
         const int64_t c1 = c0 + kFixChunk < n ? c0 + kFixChunk : n;
@@ -582,35 +726,10 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
         const uint32_t nl = s_nlist < kFixList ? s_nlist : kFixList;
         for (uint32_t q = 0; q < nl; ++q) {
             const int64_t a = s_list[q];
+            if (block_lds_run(hi, pay, n, a, s_run, s_run2, s_wcnt, s_scan, s_misc)) continue;
             const int64_t b = block_run_end(hi, n, a, &s_pos);
-            const int64_t len = b - a;
-            if (len <= kFixBitonic) {
-                int p2 = 128;
-                while (p2 < len) p2 <<= 1;
-                for (int i = threadIdx.x; i < p2; i += kFixThreads) s_run[i] = i < len ? pay[a + i] : ~0ull;
-                __syncthreads();
-                for (int k = 2; k <= p2; k <<= 1) {
-                    for (int j = k >> 1; j > 0; j >>= 1) {
-                        for (int i = threadIdx.x; i < p2; i += kFixThreads) {
-                            const int l = i ^ j;
-                            if (l > i) {
-                                const uint64_t x = s_run[i], y = s_run[l];
-                                const bool up = (i & k) == 0;
-                                if ((x > y) == up) {
-                                    s_run[i] = y;
-                                    s_run[l] = x;
-                                }
-                            }
-                        }
-                        __syncthreads();
-                    }
-                }
-                for (int i = threadIdx.x; i < len; i += kFixThreads) pay[a + i] = s_run[i];
-                __syncthreads();
-            } else {
-                block_lsd_run(pay, alt, a, b, reinterpret_cast<uint32_t*>(s_run),
-                              reinterpret_cast<uint32_t*>(s_run) + kFixWaves * 256, s_off, s_scan, s_flag);
-            }
+            block_lsd_run(pay, alt, a, b, reinterpret_cast<uint32_t*>(s_run),
+                          reinterpret_cast<uint32_t*>(s_run) + kFixWaves * 256, s_off, s_scan, s_flag);
         }
         __syncthreads();
     }
