@@ -215,21 +215,21 @@ def weighted_bench(args, dev) -> dict:
     y = torch.as_tensor(yn, device=dev)
     n = x.numel()
     L = mh.lib()
-    plan = mh.PlanParams(args.seg_work, 0, 0, 0, None)
+    plan = mh.PlanParams(args.w_seg_work, 0, 0, 0, None)
     ws = torch.empty(L.mh_workspace_bytes(n, 1, ctypes.byref(plan)), dtype=torch.uint8, device=dev)
-    s0, _, _ = mh.sample_weighted(x, y, seed=args.seed, replica=0, seg_work=args.seg_work, workspace=ws)
+    s0, _, _ = mh.sample_weighted(x, y, seed=args.seed, replica=0, seg_work=args.w_seg_work, workspace=ws)
     cap = int(len(s0) * 1.1) + 65536
     src = torch.empty(cap, dtype=torch.int32, device=dev)
     dst = torch.empty(cap, dtype=torch.int32, device=dev)
     w = torch.empty(cap, dtype=torch.int32, device=dev)
     steps = args.steps
     for i in range(args.warmup):
-        mh.sample_async(x, y, (src, dst, w), ws, seed=args.seed, replica=1 + i, seg_work=args.seg_work)
+        mh.sample_async(x, y, (src, dst, w), ws, seed=args.seed, replica=1 + i, seg_work=args.w_seg_work)
     torch.cuda.synchronize()
     replicas = [3000 + i for i in range(steps)]
     t0 = time.perf_counter()
     for r in replicas:
-        mh.sample_async(x, y, (src, dst, w), ws, seed=args.seed, replica=r, seg_work=args.seg_work)
+        mh.sample_async(x, y, (src, dst, w), ws, seed=args.seed, replica=r, seg_work=args.w_seg_work)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     last_edges = mh.sample_result(ws, cap)
@@ -241,7 +241,7 @@ def weighted_bench(args, dev) -> dict:
     wprops = 0
     stage = np.zeros(3)
     for i, r in enumerate(replicas):
-        s_, _, w_, stt = mh.sample_weighted(x, y, seed=args.seed, replica=r, seg_work=args.seg_work, stats=True,
+        s_, _, w_, stt = mh.sample_weighted(x, y, seed=args.seed, replica=r, seg_work=args.w_seg_work, stats=True,
                                             out=(src, dst, w), workspace=ws,
                                             stage_events=ev.address + 4 * i * ev_size)
         stage += [ev.elapsed_ms(4 * i, 4 * i + 1), ev.elapsed_ms(4 * i + 1, 4 * i + 2),
@@ -256,6 +256,7 @@ def weighted_bench(args, dev) -> dict:
         "workload": f"UECM N={n}, power-law degrees (exponent 2.3, k in [1, 5000]), strengths k (1 + Gamma(2, 3)), "
                     "sparse-limit parameters; samples issued back to back on one stream",
         "samples": steps,
+        "seg_work": args.w_seg_work,
         "ms_per_sample": elapsed / steps * 1e3,
         "edges_per_s": edges / elapsed,
         "mean_edges_per_sample": edges / steps,
@@ -280,14 +281,14 @@ def bipartite_bench(args, dev) -> dict:
     xr = torch.as_tensor(xr_n, device=dev)
     xc = torch.as_tensor(xc_n, device=dev)
     L = mh.lib()
-    plan = mh.PlanParams(args.seg_work, 0, 0, 0, None)
+    plan = mh.PlanParams(args.bip_seg_work, 0, 0, 0, None)
     ws = torch.empty(L.mh_bipartite_workspace_bytes(xr.numel(), xc.numel(), 0, ctypes.byref(plan)),
                      dtype=torch.uint8, device=dev)
-    first = mh.sample_bipartite(xr, xc, seed=args.seed, replica=0, seg_work=args.seg_work, workspace=ws)
+    first = mh.sample_bipartite(xr, xc, seed=args.seed, replica=0, seg_work=args.bip_seg_work, workspace=ws)
     cap = int(first.src.numel() * 1.1) + 65536
     out = (torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev))
     for i in range(args.warmup):
-        mh.sample_bipartite(xr, xc, seed=args.seed, replica=1 + i, seg_work=args.seg_work, out=out, workspace=ws)
+        mh.sample_bipartite(xr, xc, seed=args.seed, replica=1 + i, seg_work=args.bip_seg_work, out=out, workspace=ws)
     steps = args.steps
     ev = HipEvents(4 * steps)
     ev_size = ctypes.sizeof(ctypes.c_void_p)
@@ -295,14 +296,14 @@ def bipartite_bench(args, dev) -> dict:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        r = mh.sample_bipartite(xr, xc, seed=args.seed, replica=4000 + i, seg_work=args.seg_work, out=out,
+        r = mh.sample_bipartite(xr, xc, seed=args.seed, replica=4000 + i, seg_work=args.bip_seg_work, out=out,
                                 workspace=ws)
         edges += r.src.numel()
     elapsed = time.perf_counter() - t0
     # stage times from a repeat of the same samples with events (untimed)
     stage = np.zeros(3)
     for i in range(steps):
-        mh.sample_bipartite(xr, xc, seed=args.seed, replica=4000 + i, seg_work=args.seg_work, out=out,
+        mh.sample_bipartite(xr, xc, seed=args.seed, replica=4000 + i, seg_work=args.bip_seg_work, out=out,
                             workspace=ws, stage_events=ev.address + 4 * i * ev_size)
         stage += [ev.elapsed_ms(4 * i, 4 * i + 1), ev.elapsed_ms(4 * i + 1, 4 * i + 2),
                   ev.elapsed_ms(4 * i + 2, 4 * i + 3)]
@@ -310,6 +311,7 @@ def bipartite_bench(args, dev) -> dict:
         "workload": f"bipartite {xr.numel()} x {xc.numel()}, degrees power law 2.1 / 2.5 on [1, 10^4], sparse-limit "
                     "parameters; synchronous samples (edge count read back each time)",
         "samples": steps,
+        "seg_work": args.bip_seg_work,
         "ms_per_sample": elapsed / steps * 1e3,
         "edges_per_s": edges / elapsed,
         "mean_edges_per_sample": edges / steps,
@@ -475,8 +477,11 @@ def main():
     ap.add_argument("--deg-n", type=int, default=200_000,
                     help="nodes of the expected-degree measurement (0: skip it)")
     ap.add_argument("--w-n", type=int, default=200_000, help="nodes of the weighted measurement (0: skip it)")
+    ap.add_argument("--w-seg-work", type=int, default=32,
+                    help="seg_work of the weighted measurement (the best of 8-128 on that workload)")
     ap.add_argument("--bip-rows", type=int, default=1_000_000,
                     help="rows of the bipartite measurement, with half as many columns (0: skip it)")
+    ap.add_argument("--bip-seg-work", type=int, default=8, help="seg_work of the two-set measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,

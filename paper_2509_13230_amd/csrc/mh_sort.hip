@@ -376,7 +376,7 @@ __device__ __forceinline__ int64_t run_start(const uint32_t* __restrict__ hi, in
 // ------------------------------------------------------------------ run repair
 constexpr int kFixThreads = 1024;
 constexpr int kFixWaves = kFixThreads / kWave;
-constexpr int kFixLds = 2560;  // runs up to this long are sorted in LDS (block_lds_run), longer ones by block_lsd_run
+constexpr int kFixLds = 4096;  // runs up to this long are sorted in LDS (block_lds_run), longer ones by block_lsd_run
 // A block of k_fix_runs takes chunks of 2048 ranks: small chunks spread the
 // runs longer than a wave (each sorted by the whole block) over many blocks.
 constexpr int kFixChunk = 2048;
@@ -539,8 +539,9 @@ __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__
 
 // Stable sort by the high 32 bits of the run of equal hi that starts at a, in
 // LDS, if the run ends within kFixLds ranks of a; returns false (nothing
-// written) if it is longer.  One read of the window finds the run's end and
-// loads its values; the digits are those of the high word minus its least value
+// written) if it is longer.  The window is read 1024 ranks a round until a
+// round finds the run's end, loading the values on the way; the digits are
+// those of the high word minus its least value
 // in the run, 8 bits a pass, as many passes as the spread needs (one for a run
 // of near-equal keys); each pass ranks values stably as the block LSD does,
 // from s_a into s_b; one write returns the result.
@@ -558,6 +559,7 @@ __device__ bool block_lds_run(const uint32_t* __restrict__ hi, uint64_t* __restr
         s_misc[2] = 0u;
     }
     __syncthreads();
+    // the window in rounds of one rank per thread, until a round sees the run end
     for (int i0 = 0; i0 < win; i0 += kFixThreads) {
         const int i = i0 + threadIdx.x;
         const bool in = i < win;
@@ -565,10 +567,13 @@ __device__ bool block_lds_run(const uint32_t* __restrict__ hi, uint64_t* __restr
         // one atomic per wave: its first rank past the run
         if (m && lane == __ffsll((unsigned long long)m) - 1) atomicMin(&s_misc[0], (uint32_t)i);
         if (in) s_a[i] = pay[a + i];
+        __syncthreads();
+        const bool found = s_misc[0] < (uint32_t)win;
+        __syncthreads();  // every thread has read s_misc[0] before the next round may lower it
+        if (found) break;
     }
     // a run that fills the window may go on past it
     const bool longer = a + win < n && hi[a + win] == h0;
-    __syncthreads();
     const int len = (int)s_misc[0];
     if (len == win && longer) return false;  // the same for every thread of the block
     uint32_t mn = ~0u, mx = 0u;

@@ -113,7 +113,7 @@ def _near(rng, base, count, bits):
 def test_order_high_half_ties_matches_oracle(mh, case):
     # keys that tie in their high 32 bits but not in their low ones: the sort
     # passes order only the high halves, the repair kernel the rest (a wave per
-    # run of at most 64, a block in LDS up to 2560, a block's LSD through global
+    # run of at most 64, a block in LDS up to 4096, a block's LSD through global
     # memory beyond; both take as many 8-bit passes as the spread of the low
     # halves needs: "near" has runs of either kind with 1, 2 and 3 passes)
     rng = np.random.default_rng(["small", "lds", "giant", "edges", "mixed", "near", "claimed"].index(case) + 40)
@@ -126,10 +126,10 @@ def test_order_high_half_ties_matches_oracle(mh, case):
                             _cluster(rng, 2.0, 9000)])
     elif case == "edges":
         # run lengths around the wave and LDS limits, one run at each end
-        lens = [64, 65, 63, 8192, 8193, 2, 8191, 512, 513, 2559, 2560, 2561]
+        lens = [64, 65, 63, 8192, 8193, 2, 8191, 512, 513, 4095, 4096, 4097]
         parts = [_cluster(rng, 2.0 ** (4 - i), c) for i, c in enumerate(lens)]
         # the last run fills the LDS window exactly where the keys end
-        x = np.concatenate(parts + [np.full(1000, 1e-3), _cluster(rng, 2.0**-12, 2560)])
+        x = np.concatenate(parts + [np.full(1000, 1e-3), _cluster(rng, 2.0**-12, 4096)])
     elif case == "mixed":
         x = np.concatenate([rng.lognormal(-4, 1.5, 100_000), _cluster(rng, 0.5, 3000, 3000),
                             np.round(rng.lognormal(-2, 1, 100_000), 4), _cluster(rng, 0.125, 20_000)])
