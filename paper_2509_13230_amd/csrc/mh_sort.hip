@@ -377,6 +377,7 @@ __device__ __forceinline__ int64_t run_start(const uint32_t* __restrict__ hi, in
 constexpr int kFixThreads = 1024;
 constexpr int kFixWaves = kFixThreads / kWave;
 constexpr int kFixLds = 4096;  // runs up to this long are sorted in LDS (block_lds_run), longer ones by block_lsd_run
+constexpr int kFixWaveRun = 256;  // runs up to this long are sorted by one wave (wave_lds_run)
 // A block of k_fix_runs takes chunks of 2048 ranks: small chunks spread the
 // runs longer than a wave (each sorted by the whole block) over many blocks.
 constexpr int kFixChunk = 2048;
@@ -537,6 +538,91 @@ __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__
     }
 }
 
+// Stable sort by the high 32 bits of the run of equal hi (= h) that starts at
+// a, by one wave, if the run ends within kFixWaveRun ranks of a (its first 64
+// ranks are known to be in it); returns false (nothing written) if it is
+// longer.  Each lane holds 4 values in registers; the digits are those of
+// block_lds_run; a pass ranks them with the wave's 256 digit counts (s_c) and
+// scatters them through s_b (kFixWaveRun values), both the wave's own LDS.
+__device__ bool wave_lds_run(const uint32_t* __restrict__ hi, uint64_t* __restrict__ pay, int64_t n, int64_t a,
+                             uint32_t h, uint64_t* s_b, uint32_t* s_c) {
+    constexpr int K = kFixWaveRun / kWave;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lanemask_lt();
+    int len = -1;
+    for (int k = 1; k <= K && len < 0; ++k) {
+        const int i = k * kWave + lane;
+        const bool past = i <= kFixWaveRun && (a + i >= n || hi[a + i] != h);
+        const uint64_t m = __ballot(past);
+        if (m) len = k * kWave + __ffsll((unsigned long long)m) - 1;
+    }
+    if (len < 0) return false;  // the same for every lane of the wave
+    uint64_t v[K];
+    uint32_t mn = ~0u, mx = 0u;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = k * kWave + lane;
+        v[k] = i < len ? pay[a + i] : 0ull;
+        if (i < len) {
+            const uint32_t hv = (uint32_t)(v[k] >> 32);
+            mn = hv < mn ? hv : mn;
+            mx = hv > mx ? hv : mx;
+        }
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t on = __shfl_xor(mn, d, kWave), ox = __shfl_xor(mx, d, kWave);
+        mn = on < mn ? on : mn;
+        mx = ox > mx ? ox : mx;
+    }
+    const uint32_t spread = mx - mn;
+    const int npass = spread == 0 ? 0 : (spread >> 8) == 0 ? 1 : (spread >> 16) == 0 ? 2 : (spread >> 24) == 0 ? 3 : 4;
+    for (int pass = 0; pass < npass; ++pass) {
+        const int shift = 8 * pass;
+#pragma unroll
+        for (int k = 0; k < K; ++k) s_c[k * kWave + lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        uint32_t dg[K], rk[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const bool valid = k * kWave + lane < len;
+            dg[k] = ((((uint32_t)(v[k] >> 32)) - mn) >> shift) & 255u;
+            const uint64_t m = match_digit(dg[k], valid);
+            const uint32_t prior = s_c[dg[k]];
+            rk[k] = prior + (uint32_t)__popcll(m & lt);
+            __builtin_amdgcn_wave_barrier();
+            if (valid && (m & lt) == 0) s_c[dg[k]] = prior + (uint32_t)__popcll(m);
+            __builtin_amdgcn_wave_barrier();
+        }
+        // digit starts: lane l scans digits 4l .. 4l + 3
+        const uint32_t c0 = s_c[4 * lane], c1 = s_c[4 * lane + 1], c2 = s_c[4 * lane + 2], c3 = s_c[4 * lane + 3];
+        const uint32_t tot = c0 + c1 + c2 + c3;
+        const uint32_t pre = wave_inclusive_scan(tot) - tot;
+        __builtin_amdgcn_wave_barrier();
+        s_c[4 * lane] = pre;
+        s_c[4 * lane + 1] = pre + c0;
+        s_c[4 * lane + 2] = pre + c0 + c1;
+        s_c[4 * lane + 3] = pre + c0 + c1 + c2;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (k * kWave + lane < len) s_b[s_c[dg[k]] + rk[k]] = v[k];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = k * kWave + lane;
+            v[k] = i < len ? s_b[i] : 0ull;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = k * kWave + lane;
+        if (i < len) pay[a + i] = v[k];
+    }
+    return true;
+}
+
 // Stable sort by the high 32 bits of the run of equal hi that starts at a, in
 // LDS, if the run ends within kFixLds ranks of a; returns false (nothing
 // written) if it is longer.  The window is read 1024 ranks a round until a
@@ -654,8 +740,9 @@ __device__ bool block_lds_run(const uint32_t* __restrict__ hi, uint64_t* __restr
 // sets it sorts the whole run, wherever it lies.  A run without a descent is
 // never claimed, however long; while its owner sorts a run, other blocks may
 // read that run's values mid-sort, which can only make them try the claim
-// again, and fail.  The block's claimed runs of less than 64 ranks are sorted
-// by single waves at once; longer ones by the whole block: in LDS up to kFixLds
+// again, and fail.  The block's claimed runs are sorted by single waves at
+// once up to kFixWaveRun ranks (bitonic over the lanes below 64, else
+// wave_lds_run), longer ones by the whole block: in LDS up to kFixLds
 // (block_lds_run), else by block_lsd_run through alt.
 __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __restrict__ hi,
                                                           uint64_t* __restrict__ pay, uint64_t* __restrict__ alt,
@@ -672,6 +759,7 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
     __shared__ uint32_t s_scan[kFixWaves];
     __shared__ uint32_t s_flag[4];
     static_assert(kFixWaves * 256 + 4 * 256 <= 2 * kFixLds, "digit counts fit in the run buffer");
+    static_assert(kFixWaves * kFixWaveRun <= kFixLds, "every wave has a slice of the second run buffer");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t c0 = (int64_t)blockIdx.x * kFixChunk; c0 < n; c0 += (int64_t)gridDim.x * kFixChunk) {
         const int64_t c1 = c0 + kFixChunk < n ? c0 + kFixChunk : n;
@@ -705,7 +793,7 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
             }
         }
         __syncthreads();
-        // 2. the claimed runs: below 64 ranks by a wave each, longer ones listed
+        // 2. the claimed runs: up to kFixWaveRun ranks by a wave each, longer ones listed
         const uint32_t ncl = s_nclaim;
         for (uint32_t q = (uint32_t)wave; q < ncl; q += kFixWaves) {
             const int64_t a = s_claim[q];
@@ -714,7 +802,7 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
             const bool in = r < n && hi[r] == h;
             const uint64_t inm = __ballot(in);
             if (inm == ~0ull) {
-                if (lane == 0) {
+                if (!wave_lds_run(hi, pay, n, a, h, s_run2 + wave * kFixWaveRun, s_wcnt + wave * 256) && lane == 0) {
                     const uint32_t slot = atomicAdd(&s_nlist, 1u);
                     if (slot < kFixList) s_list[slot] = a;
                 }

@@ -113,7 +113,7 @@ def _near(rng, base, count, bits):
 def test_order_high_half_ties_matches_oracle(mh, case):
     # keys that tie in their high 32 bits but not in their low ones: the sort
     # passes order only the high halves, the repair kernel the rest (a wave per
-    # run of at most 64, a block in LDS up to 4096, a block's LSD through global
+    # run of at most 256, a block in LDS up to 4096, a block's LSD through global
     # memory beyond; both take as many 8-bit passes as the spread of the low
     # halves needs: "near" has runs of either kind with 1, 2 and 3 passes)
     rng = np.random.default_rng(["small", "lds", "giant", "edges", "mixed", "near", "claimed"].index(case) + 40)
@@ -126,7 +126,7 @@ def test_order_high_half_ties_matches_oracle(mh, case):
                             _cluster(rng, 2.0, 9000)])
     elif case == "edges":
         # run lengths around the wave and LDS limits, one run at each end
-        lens = [64, 65, 63, 8192, 8193, 2, 8191, 512, 513, 4095, 4096, 4097]
+        lens = [64, 65, 63, 8192, 8193, 2, 8191, 512, 513, 4095, 4096, 4097, 255, 256, 257]
         parts = [_cluster(rng, 2.0 ** (4 - i), c) for i, c in enumerate(lens)]
         # the last run fills the LDS window exactly where the keys end
         x = np.concatenate(parts + [np.full(1000, 1e-3), _cluster(rng, 2.0**-12, 4096)])
@@ -136,7 +136,8 @@ def test_order_high_half_ties_matches_oracle(mh, case):
     elif case == "near":
         x = np.concatenate([_near(rng, 0.5, 20_000, 8), _near(rng, 0.25, 30_000, 16), _near(rng, 2.0, 12_000, 24),
                             _near(rng, 8.0, 2000, 8), _near(rng, 16.0, 2500, 16), _near(rng, 32.0, 1500, 24),
-                            _near(rng, 64.0, 700, 2), rng.lognormal(-3, 1, 50_000)])
+                            _near(rng, 64.0, 700, 2), _near(rng, 128.0, 200, 8), _near(rng, 256.0, 250, 24),
+                            _near(rng, 512.0, 100, 16), rng.lognormal(-3, 1, 50_000)])
     else:
         # one run of 300,000 tied high halves with descents in every chunk of
         # 2048 ranks: ~150 blocks see one and race to claim the run, while its
