@@ -348,29 +348,34 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
 }
 
 // ------------------------------------------------------------------ tie runs
-// First index in [0, r] whose key equals hi[r] (hi ascending).  Probes go back
-// from r in doubling steps of 64, 128, ... until one lands before the run (or
-// at 0), then bisect that last step: about 2 log2(d / 64) dependent loads for a
-// run that began d ranks before r, instead of log2(r).
-__device__ __forceinline__ int64_t run_start(const uint32_t* __restrict__ hi, int64_t r) {
+// First index in [0, r] whose key equals hi[r] (hi ascending), found by the
+// whole wave (r the same in every lane): lane l first probes r - 64 * 2^l,
+// which brackets the start within a factor of two of its distance; then each
+// round's 63 evenly spaced probes narrow the bracket 64-fold.  A start 3,000
+// ranks back costs 3 rounds of loads where a one-lane search takes ~18.
+__device__ int64_t wave_run_start(const uint32_t* __restrict__ hi, int64_t r) {
+    const int lane = threadIdx.x & 63;
     const uint32_t h = hi[r];
-    int64_t up = r;  // hi[up] == h
-    int64_t lo = 0;  // every index below lo is before the run
-    for (int64_t step = 64;; step <<= 1) {
-        const int64_t p = up - step;
-        if (p <= 0) break;
-        if (hi[p] < h) {
-            lo = p + 1;
-            break;
-        }
-        up = p;
+    int64_t lo, up;  // the start is in (lo, up]: hi[lo] < h (or lo = -1), hi[up] == h
+    {
+        const int sh = lane < 40 ? lane : 40;
+        const int64_t p = r - ((int64_t)64 << sh);
+        const bool before = p < 0 || hi[p] < h;  // true from some lane on (lane 40 at the latest)
+        const int l = __ffsll((unsigned long long)__ballot(before)) - 1;
+        lo = r - ((int64_t)64 << l);
+        if (lo < 0) lo = -1;
+        up = l == 0 ? r : r - ((int64_t)64 << (l - 1));
     }
-    while (lo < up) {
-        const int64_t mid = (lo + up) >> 1;
-        if (hi[mid] < h) lo = mid + 1;
-        else up = mid;
+    while (up - lo > 1) {
+        const int64_t step = (up - lo + 63) / 64;
+        const int64_t p = lo + step * (lane + 1);
+        const bool before = p < up && hi[p] < h;  // a prefix of the lanes
+        const int cnt = __popcll(__ballot(before));
+        const int64_t nup = lo + step * (cnt + 1);
+        lo += step * cnt;
+        up = nup < up ? nup : up;
     }
-    return lo;
+    return up;
 }
 
 // ------------------------------------------------------------------ run repair
@@ -778,15 +783,22 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
             }
             const uint64_t dm = __ballot(desc);
             if (dm == 0) continue;
-            const uint64_t starts = __ballot(!eq) & ~1ull;  // run starts inside the wave (lane 0 aside)
+            const uint64_t eqm = __ballot(eq);
+            const uint64_t starts = ~eqm & ~1ull;  // run starts inside the wave (lane 0 aside)
+            // the wave's first segment (lanes before the first start) continues a
+            // run from before the wave: if it holds a descent, the wave finds that
+            // run's start together
+            const bool cont = (eqm & 1ull) != 0;
+            const uint64_t first_seg = starts ? (1ull << (__ffsll((unsigned long long)starts) - 1)) - 1 : ~0ull;
+            int64_t a_cont = wbase;
+            if (cont && (dm & first_seg)) a_cont = wave_run_start(hi, wbase);
             if (desc) {
                 const uint64_t le = lanemask_lt();
                 const uint64_t before = starts & le;
                 const int st = before ? 63 - __clzll((long long)before) : 0;  // segment's first lane in the wave
                 const uint64_t seg_desc = dm & le & ~((1ull << st) - 1);   // earlier descents in the segment
                 if (seg_desc == 0) {
-                    const int64_t a = (before || !(wbase > 0 && hi[wbase - 1] == hi[wbase])) ? wbase + st
-                                                                                            : run_start(hi, wbase);
+                    const int64_t a = before ? wbase + st : a_cont;
                     const uint32_t mask = 1u << (a & 31);
                     if ((atomicOr(&claims[a >> 5], mask) & mask) == 0) s_claim[atomicAdd(&s_nclaim, 1u)] = a;
                 }
