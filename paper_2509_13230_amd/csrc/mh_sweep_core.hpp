@@ -311,6 +311,8 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
             ++row_deg;
             atomicAdd(&deg[dst_id], 1);
         }
+        // the accepted edge's sample: step 4 may move the lane to an item of the next sample
+        const int32_t acc_sample = sample;
         // 3. the skip: candidate pos + 1 + floor(-log U1 / -log(1 - q)), or the end of the segment
         if (go) {
             bool ended = true;
@@ -394,7 +396,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
             if (py) ry = *py;
             if (pc) rcc = *pc;
         }
-        if (OUT == OUT_EDGES) stage.push_sid(acc, id, dst_id, wt, sample, s_sid, A.out, A.sid);
+        if (OUT == OUT_EDGES) stage.push_sid(acc, id, dst_id, wt, acc_sample, s_sid, A.out, A.sid);
         if (__ballot(state != S_DONE) == 0) break;
     }
     if (STATS) {

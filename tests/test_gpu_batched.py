@@ -64,6 +64,32 @@ def test_batch_edges_match_oracle(mh, seg_work):
         assert np.array_equal(_keys(src[sel], dst[sel], sizes[i])[0], _keys(ora.src, ora.dst, sizes[i])[0]), (i, r)
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_batch_edges_labelled_when_lanes_cross_samples(mh, weighted):
+    # one block: every lane takes many items in turn, from one sample and then
+    # the next, and may accept the last candidate of a segment in the same
+    # step that it moves on; each edge keeps the sample it was drawn in
+    sizes = [700, 30, 1500, 200, 900]
+    xs, ys = _nets(5 if weighted else 4, sizes, weighted=weighted)
+    b = mh.Batch([dev(x) for x in xs], [dev(y) for y in ys] if weighted else None, seg_work=4, max_samples=16)
+    net = [0, 1, 2, 3, 4, 2, 0]
+    rep = [0, 0, 1, 2, 3, 4, 5]
+    for grid in (1, 2):
+        src, dst, w, sid = b.sample_edges(net, rep, seed=11, grid_blocks=grid)
+        src, dst, sid = src.cpu().numpy(), dst.cpu().numpy(), sid.cpu().numpy()
+        w = None if w is None else w.cpu().numpy()
+        for s, (i, r) in enumerate(zip(net, rep)):
+            sel = sid == s
+            ora = oracle.sample_mh(xs[i], ys[i] if weighted else None, seed=11, replica=r, seg_work=4)
+            if len(ora.tie_rows):
+                continue
+            kg, wg = _keys(src[sel], dst[sel], sizes[i], None if w is None else w[sel])
+            ko, wo = _keys(ora.src, ora.dst, sizes[i], ora.w if weighted else None)
+            assert np.array_equal(kg, ko), (grid, s)
+            if weighted:
+                assert np.array_equal(wg, wo), (grid, s)
+
+
 def test_batch_weighted_edges_match_oracle(mh):
     sizes = [500, 1200, 64]
     xs, ys = _nets(2, sizes, weighted=True)
