@@ -387,7 +387,7 @@ constexpr int kFixWaveRun = 256;  // runs up to this long are sorted by one wave
 // runs longer than a wave (each sorted by the whole block) over many blocks.
 constexpr int kFixChunk = 2048;
 constexpr int kFixClaims = kFixChunk / 2;  // runs with a descent among 2048 ranks: at most 1024
-constexpr int kFixList = 64;  // runs of 64 or more ranks meeting a chunk of 2048: at most 34
+constexpr int kFixList = 64;  // runs of more than kFixWaveRun ranks claimed by a chunk of 2048: at most 9
 
 // Sorts up to 64 values held one per lane (absent lanes hold ~0).
 __device__ __forceinline__ uint64_t wave_bitonic(uint64_t v) {
