@@ -383,9 +383,11 @@ constexpr int kFixThreads = 1024;
 constexpr int kFixWaves = kFixThreads / kWave;
 constexpr int kFixLds = 4096;  // runs up to this long are sorted in LDS (block_lds_run), longer ones by block_lsd_run
 constexpr int kFixWaveRun = 256;  // runs up to this long are sorted by one wave (wave_lds_run)
-// A block of k_fix_runs takes chunks of 2048 ranks: small chunks spread the
-// runs longer than a wave (each sorted by the whole block) over many blocks.
-constexpr int kFixChunk = 2048;
+// A block of k_fix_runs takes chunks of ranks: small chunks spread the runs
+// longer than a wave (each sorted by the whole block) over many blocks.  Chunks
+// are 1024 ranks where every chunk then has a block of its own, else 2048
+// (fewer chunks a block: each costs its barriers).
+constexpr int kFixChunk = 2048;  // the largest chunk
 constexpr int kFixClaims = kFixChunk / 2;  // runs with a descent among 2048 ranks: at most 1024
 constexpr int kFixList = 64;  // runs of more than kFixWaveRun ranks claimed by a chunk of 2048: at most 9
 
@@ -751,7 +753,7 @@ __device__ bool block_lds_run(const uint32_t* __restrict__ hi, uint64_t* __restr
 // (block_lds_run), else by block_lsd_run through alt.
 __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __restrict__ hi,
                                                           uint64_t* __restrict__ pay, uint64_t* __restrict__ alt,
-                                                          int64_t n, uint32_t* __restrict__ claims) {
+                                                          int64_t n, uint32_t* __restrict__ claims, int32_t chunk) {
     __shared__ uint64_t s_run[kFixLds];
     __shared__ uint64_t s_run2[kFixLds];
     __shared__ uint32_t s_wcnt[kFixWaves * 256];
@@ -766,8 +768,8 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
     static_assert(kFixWaves * 256 + 4 * 256 <= 2 * kFixLds, "digit counts fit in the run buffer");
     static_assert(kFixWaves * kFixWaveRun <= kFixLds, "every wave has a slice of the second run buffer");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int64_t c0 = (int64_t)blockIdx.x * kFixChunk; c0 < n; c0 += (int64_t)gridDim.x * kFixChunk) {
-        const int64_t c1 = c0 + kFixChunk < n ? c0 + kFixChunk : n;
+    for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < n; c0 += (int64_t)gridDim.x * chunk) {
+        const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
         if (threadIdx.x == 0) {
             s_nclaim = 0;
             s_nlist = 0;
@@ -944,11 +946,12 @@ mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint
     }
     static_assert(kPasses % 2 == 0, "the passes end in the input arrays");
     // runs of equal high halves out of order by the low halves
-    const int64_t chunks = (n + kFixChunk - 1) / kFixChunk;
     const int64_t cus = device_cus();
+    const int32_t chunk = n <= (kFixChunk / 2) * cus ? kFixChunk / 2 : kFixChunk;
+    const int64_t chunks = (n + chunk - 1) / chunk;
     const int64_t fix_grid = chunks < cus ? chunks : cus;
     hipLaunchKernelGGL(k_fix_runs, dim3((unsigned)fix_grid), dim3(kFixThreads), 0, stream, (const uint32_t*)hi, pay,
-                       pay_alt, n, s.bits);
+                       pay_alt, n, s.bits, chunk);
     MH_HIP_TRY(hipGetLastError());
     return MH_OK;
 }
