@@ -373,15 +373,25 @@ def batched_ensemble(args, dev) -> dict:
     reps = [r for _ in xs for r in range(R)]
     S = len(net_ids)
 
+    # batched: prepare once, autotune on a probe (seg_work and grid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = mh.Batch(xs, seg_work=args.seg_work, max_samples=S)
+    torch.cuda.synchronize()
+    t_prepare = time.perf_counter() - t0
+    probe = list(range(0, len(xs), max(1, len(xs) // 16)))
+    tuned = b.autotune(probe, [0] * len(probe), seg_candidates=(8, 16, 32), grid_candidates=(0, 1024, 2048))
+    sw = tuned["seg_work"]  # the plain samples use the same segment length
+
     # plain: every sample through the single-sample entry point
     max_n = max(x.numel() for x in xs)
     L = mh.lib()
-    plan = mh.PlanParams(args.seg_work, 0, 0, 0, None)
+    plan = mh.PlanParams(sw, 0, 0, 0, None)
     ws = torch.empty(L.mh_workspace_bytes(max_n, 0, ctypes.byref(plan)), dtype=torch.uint8, device=dev)
     # capacity: the largest sample seen on replica 0 of every network, with margin
     caps = []
     for x in xs:
-        s_, _ = mh.sample_unweighted(x, seed=args.seed, replica=0, seg_work=args.seg_work, workspace=ws)
+        s_, _ = mh.sample_unweighted(x, seed=args.seed, replica=0, seg_work=sw, workspace=ws)
         caps.append(s_.numel())
     cap = int(max(caps) * 1.1) + 65536
     src = torch.empty(cap, dtype=torch.int32, device=dev)
@@ -390,7 +400,7 @@ def batched_ensemble(args, dev) -> dict:
     t0 = time.perf_counter()
     plain_edges = 0
     for i, r in zip(net_ids, reps):
-        s_, _ = mh.sample_unweighted(xs[i], seed=args.seed, replica=r, seg_work=args.seg_work, out=(src, dst),
+        s_, _ = mh.sample_unweighted(xs[i], seed=args.seed, replica=r, seg_work=sw, out=(src, dst),
                                      workspace=ws)
         plain_edges += s_.numel()
     torch.cuda.synchronize()
@@ -398,23 +408,16 @@ def batched_ensemble(args, dev) -> dict:
     # the same samples issued back to back through the asynchronous entry point
     # (no count readback between samples): the faster way to use the plain path
     for i, r in zip(net_ids[:8], reps[:8]):
-        mh.sample_async(xs[i], None, (src, dst), ws, seed=args.seed, replica=r, seg_work=args.seg_work)
+        mh.sample_async(xs[i], None, (src, dst), ws, seed=args.seed, replica=r, seg_work=sw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i, r in zip(net_ids, reps):
-        mh.sample_async(xs[i], None, (src, dst), ws, seed=args.seed, replica=r, seg_work=args.seg_work)
+        mh.sample_async(xs[i], None, (src, dst), ws, seed=args.seed, replica=r, seg_work=sw)
     torch.cuda.synchronize()
     t_plain_async = time.perf_counter() - t0
     del src, dst, ws
 
-    # batched: prepare once, autotune on a probe, then one graph launch per ensemble
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b = mh.Batch(xs, seg_work=args.seg_work, max_samples=S)
-    torch.cuda.synchronize()
-    t_prepare = time.perf_counter() - t0
-    probe = list(range(0, len(xs), max(1, len(xs) // 16)))
-    tuned = b.autotune(probe, [0] * len(probe), seg_candidates=(8, 16, 32), grid_candidates=(0, 1024, 2048))
+    # batched: one graph launch per ensemble (prepared and tuned above)
     net_t = torch.tensor(net_ids, dtype=torch.int32, device=dev)
     rep_t = torch.tensor(reps, dtype=torch.int32, device=dev)
     off = b.degree_offsets(torch.tensor(net_ids))
@@ -441,6 +444,8 @@ def batched_ensemble(args, dev) -> dict:
         "samples": S,
         "edges": batch_edges,
         "plain_edges": plain_edges,
+        # the same (network, replica, seed, seg_work) draws the same samples either way
+        "plain_edges_equal": plain_edges == batch_edges,
         "replicas_per_s_batched": S / t_batch,
         "replicas_per_s_batched_incl_prepare": S / (t_batch + t_prepare),
         "replicas_per_s_plain": S / t_plain_async,
