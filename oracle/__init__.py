@@ -53,6 +53,10 @@ def lib() -> ctypes.CDLL:
         L.mho_philox4x32_10.restype = None
         L.mho_u53.argtypes = [u32, u32]
         L.mho_u53.restype = d
+        L.mho_skip_real.argtypes = [d, d, d]
+        L.mho_skip_real.restype = d
+        L.mho_skip_reals.argtypes = [vp, i64, d, d, vp]
+        L.mho_skip_reals.restype = None
         L.mho_order.argtypes = [vp, i64, vp]
         L.mho_bound.argtypes = [vp, i64, vp]
         L.mho_plan_counts.argtypes = [vp, vp, i64, i32, vp]
@@ -101,6 +105,15 @@ def philox(ctr, key) -> np.ndarray:
 
 def u53(a: int, b: int) -> float:
     return lib().mho_u53(a, b)
+
+
+def skip_reals(u1, tq: float, c: float = 1.0) -> np.ndarray:
+    """The sampler's skip d = -log(u1) / log1p(tq / c) for each uniform u1
+    (the candidate is floor(d) columns past the chain's position)."""
+    u = _f64(u1)
+    d = np.zeros(len(u))
+    lib().mho_skip_reals(_p(u), len(u), float(tq), float(c), _p(d))
+    return d
 
 
 def order(z) -> np.ndarray:
@@ -168,20 +181,20 @@ def sample_mh(x, y=None, seed: int = 1, replica: int = 0, seg_work: int = 0,
     st = Stats()
     ntr = ctypes.c_int64(0)
     cap = capacity if capacity is not None else max(1024, 8 * n)
+    tcap = 1024
     while True:
         src = np.zeros(cap, dtype=np.int32)
         dst = np.zeros(cap, dtype=np.int32)
         w = np.zeros(cap, dtype=np.int32) if y is not None else None
-        ties = np.zeros(1024, dtype=np.int32)
+        ties = np.zeros(tcap, dtype=np.int32)
         m = lib().mho_sample_mh(_p(x), _p(y), n, seed, replica, seg_work, _p(src), _p(dst), _p(w), cap,
                                 ctypes.byref(st), _p(ties), len(ties), ctypes.byref(ntr))
         if m < 0:
             raise ValueError("oracle: invalid parameters (code %d)" % m)
-        if m <= cap:
+        if m <= cap and ntr.value <= tcap:
             break
-        cap = int(m)
-    return Sample(src[:m], dst[:m], None if w is None else w[:m], st.as_dict(),
-                  ties[: min(ntr.value, len(ties))].copy())
+        cap, tcap = max(cap, int(m)), max(tcap, int(ntr.value))
+    return Sample(src[:m], dst[:m], None if w is None else w[:m], st.as_dict(), ties[: ntr.value].copy())
 
 
 def sample_bf(x, y=None, seed: int = 1, replica: int = 0, row_begin: int = 0, row_end: int | None = None,
@@ -243,21 +256,21 @@ def sample_bipartite(xr, xc, yr=None, yc=None, exclude_self=False, seed: int = 1
     st = Stats()
     ntr = ctypes.c_int64(0)
     cap = capacity if capacity is not None else max(1024, 8 * (len(xr) + len(xc)))
+    tcap = 1024
     while True:
         src = np.zeros(cap, dtype=np.int32)
         dst = np.zeros(cap, dtype=np.int32)
         w = np.zeros(cap, dtype=np.int32) if yr is not None else None
-        ties = np.zeros(1024, dtype=np.int32)
+        ties = np.zeros(tcap, dtype=np.int32)
         m = lib().mho_sample_bipartite(_p(xr), _p(yr), len(xr), _p(xc), _p(yc), len(xc), int(exclude_self), seed,
                                        replica, seg_work, _p(src), _p(dst), _p(w), cap, ctypes.byref(st), _p(ties),
                                        len(ties), ctypes.byref(ntr))
         if m < 0:
             raise ValueError("oracle: invalid parameters (code %d)" % m)
-        if m <= cap:
+        if m <= cap and ntr.value <= tcap:
             break
-        cap = int(m)
-    return Sample(src[:m], dst[:m], None if w is None else w[:m], st.as_dict(),
-                  ties[: min(ntr.value, len(ties))].copy())
+        cap, tcap = max(cap, int(m)), max(tcap, int(ntr.value))
+    return Sample(src[:m], dst[:m], None if w is None else w[:m], st.as_dict(), ties[: ntr.value].copy())
 
 
 def sample_bipartite_bf(xr, xc, yr=None, yc=None, exclude_self=False, seed: int = 1, replica: int = 0,

@@ -241,6 +241,22 @@ static int near_int(double d) {
     return fabs(d - f) <= tol;
 }
 
+/* The skip of Sec. 2.3 before it is floored: the next candidate lies
+   L = floor(d) columns past the chain's position, where L is geometric with
+   P(L = l) = (1 - q)^l q, drawn by inversion as d = log U / log(1 - q).
+   The proposal probability is q = t_q / (c + t_q) (c = 1 unweighted: q is the
+   true p; c = 1 - Y weighted: q is the bound), so 1 - q = c / (c + t_q) and
+   -log(1 - q) = log1p(t_q / c), which stays accurate when q is near 0 or 1. */
+static double skip_real(double u1, double tq, double c) {
+    return -log(u1) / log1p(tq / c);
+}
+
+double mho_skip_real(double u1, double tq, double c) { return skip_real(u1, tq, c); }
+
+void mho_skip_reals(const double* u1, int64_t n, double tq, double c, double* d) {
+    for (int64_t i = 0; i < n; ++i) d[i] = skip_real(u1[i], tq, c);
+}
+
 /* Weight given an edge: geometric on {1, 2, ...} with P(w) = b^(w-1)(1-b)
    (Sec. 2.5), by inversion: w = 1 + floor(log U / log b). */
 static int32_t draw_weight(double u, double b, int64_t* saturated, int* tie) {
@@ -330,8 +346,7 @@ int64_t mho_sample_mh(const double* x, const double* y, int64_t n, uint64_t seed
                 ++st.steps;
                 double U1 = mho_u53(u[0], u[1]);
                 double U2 = mho_u53(u[2], u[3]);
-                double lq = y ? log1p(tq / cr) : log1p(tq);
-                double d = -log(U1) / lq;
+                double d = skip_real(U1, tq, cr);
                 double room = (double)(b - 1 - pos);
                 if (near_int(d) || fabs(d - room) <= 1e-12 * (room > 1.0 ? room : 1.0)) row_tie = 1;
                 if (d >= room) break;
@@ -518,8 +533,7 @@ int64_t mho_sample_bipartite(const double* xr, const double* yr, int64_t nr, con
                     ++st.steps;
                     double U1 = mho_u53(u[0], u[1]);
                     double U2 = mho_u53(u[2], u[3]);
-                    double lq = yr ? log1p(tq / cr) : log1p(tq);
-                    double d = -log(U1) / lq;
+                    double d = skip_real(U1, tq, cr);
                     double room = (double)(b - 1 - pos);
                     if (near_int(d) || fabs(d - room) <= 1e-12 * (room > 1.0 ? room : 1.0)) row_tie = 1;
                     if (d >= room) break;

@@ -40,6 +40,13 @@ void mho_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 /* Uniform in (0, 1] with 53 random bits: (((a << 21) | (b >> 11)) + 1) * 2^-53. */
 double mho_u53(uint32_t a, uint32_t b);
 
+/* The sampler's skip before flooring: d = -log(u1) / log1p(tq / c), so that
+   L = floor(d) is geometric with P(L = l) = (1 - q)^l q, q = tq / (c + tq)
+   (c = 1 for the unweighted model).  The sampler calls exactly this; the
+   array form applies it to u1[0..n). */
+double mho_skip_real(double u1, double tq, double c);
+void mho_skip_reals(const double* u1, int64_t n, double tq, double c, double* d);
+
 /* Node order: stable sort of ids by z descending, ties by id ascending. */
 int mho_order(const double* z, int64_t n, int32_t* perm);
 
