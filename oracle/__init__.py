@@ -39,13 +39,21 @@ def build(force: bool = False) -> str:
 
 
 _lib = None
+_lib_path = None  # another build of mh_oracle.c to load instead (see use_library)
+
+
+def use_library(path: str) -> None:
+    """Load the oracle's functions from another build of its source from now
+    on (the planted-mistake test builds altered copies of mh_oracle.c)."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
 
 
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+        path = _lib_path if _lib_path is not None else build()
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER
         d, i32, i64, u32, u64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
         vp = ctypes.c_void_p

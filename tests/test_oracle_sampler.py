@@ -313,3 +313,129 @@ def test_capacity_retry_identical():
     full = oracle.sample_mh(x, None, seed=2, replica=1, seg_work=4)
     small = oracle.sample_mh(x, None, seed=2, replica=1, seg_work=4, capacity=3)
     assert np.array_equal(full.src, small.src) and np.array_equal(full.dst, small.dst)
+
+
+# ------------------------------------------------------------------ skip law (Sec. 2.3)
+def _u53_draws(seed: int, n: int) -> np.ndarray:
+    # uniforms on the sampler's grid {k 2^-53 : k = 1 .. 2^53}
+    rng = np.random.default_rng(seed)
+    return (rng.integers(0, 1 << 53, size=n, dtype=np.int64).astype(np.float64) + 1.0) * 2.0 ** -53
+
+
+@pytest.mark.parametrize("tq,c", [(0.05, 1.0), (1.0, 1.0), (20.0, 1.0), (0.3, 0.55), (4.0, 0.2)])
+def test_skip_law_chi2(tq, c):
+    # floor(d) is geometric on {0, 1, ...} with P(L = l) = (1 - q)^l q and
+    # q = t_q / (c + t_q): the proposal probability of Sec. 2.3 (unweighted,
+    # c = 1) or the weighted bound of Sec. 2.5 (c = 1 - Y)
+    R = 200_000
+    L = np.floor(oracle.skip_reals(_u53_draws(int(tq * 1000 + c * 10), R), tq, c))
+    assert np.all(L >= 0)
+    q = tq / (c + tq)
+    lmax = int(np.ceil(np.log(5.0 / R) / np.log1p(-q))) if q < 1 else 1
+    lmax = max(1, min(lmax, 400))
+    obs = np.array([np.sum(L == l) for l in range(lmax)] + [np.sum(L >= lmax)], dtype=float)
+    pl = np.array([(1 - q) ** l * q for l in range(lmax)] + [(1 - q) ** lmax])
+    e = pl * R
+    keep = e >= 5
+    chi = ((obs[keep] - e[keep]) ** 2 / e[keep]).sum() + (obs[~keep].sum() - e[~keep].sum()) ** 2 / max(
+        e[~keep].sum(), 1e-300) * (e[~keep].sum() > 0)
+    assert stats.chi2.sf(chi, max(int(keep.sum()), 1)) > 1e-6
+
+
+@pytest.mark.parametrize("q,c", [(1e-9, 1.0), (1e-9, 0.3), (1e-18, 1.0), (1e-150, 1.0)])
+def test_skip_mean_at_tiny_q(q, c):
+    # mean of the geometric skip is (1 - q)/q, its variance (1 - q)/q^2: within
+    # 4 sigma over R draws, at proposal probabilities where 1 - q rounds to 1 in
+    # binary64 (a skip computed from log(1 - q) would never end)
+    R = 400_000
+    tq = c * q / (1.0 - q)
+    L = np.floor(oracle.skip_reals(_u53_draws(7, R), tq, c))
+    mean = (1.0 - q) / q
+    sigma = np.sqrt((1.0 - q) / q ** 2 / R)
+    assert np.all(np.isfinite(L))
+    assert abs(L.mean() - mean) <= 4 * sigma
+
+
+@pytest.mark.parametrize("c", [1.0, 0.25])
+def test_skip_at_q_near_one(c):
+    # q = 1 - 1e-9: the next column is proposed unless U1 <= 1 - q, i.e. with
+    # probability q; L = 0 exactly when -log U1 < log1p(t_q / c).  Every draw
+    # of 400,000 gives L = 0 except with probability 4e-4, and the mean
+    # (1 - q)/q = 1e-9 is within 4 sigma (sigma = 5e-8) only then.
+    q = 1.0 - 1e-9
+    tq = c * q / (1.0 - q)
+    R = 400_000
+    L = np.floor(oracle.skip_reals(_u53_draws(8, R), tq, c))
+    assert abs(L.mean() - (1 - q) / q) <= 4 * np.sqrt((1 - q) / q ** 2 / R)
+    # the boundary itself: U1 just above and at 1/(1 + t_q / c)
+    thr = 1.0 / (1.0 + tq / c)
+    k = np.floor(thr * 2.0 ** 53)
+    assert np.floor(oracle.skip_reals([(k + 2) * 2.0 ** -53], tq, c))[0] == 0
+    assert np.floor(oracle.skip_reals([(k - 2) * 2.0 ** -53], tq, c))[0] >= 1
+
+
+def test_skip_endpoints_and_monotone():
+    # U1 = 1 gives d = 0 (the next column); d falls as U1 grows
+    d = oracle.skip_reals([1.0], 0.7, 1.0)
+    assert d[0] == 0.0
+    u = np.sort(_u53_draws(9, 2000))
+    d = oracle.skip_reals(u, 0.7, 0.8)
+    assert np.all(np.diff(d) <= 0)
+    assert np.allclose(d, -np.log(u) / np.log1p(0.7 / 0.8), rtol=1e-15)
+
+
+# ------------------------------------------------------------------ weighted brute force (Secs. 2.2, 2.5)
+def test_weighted_bf_joint_law_and_weights():
+    # one node set, weighted: every pair an edge independently with
+    # p = t / (1 - b + t), and given the edge w ~ b^(w-1)(1 - b), w >= 1
+    rng = np.random.default_rng(24)
+    n = 5
+    x = np.exp(rng.normal(0.5, 1.0, n))
+    y = rng.uniform(0.3, 0.85, n)
+    p, b = _p_uecm(x, y)
+    W = {}
+
+    def fn(rep):
+        src, dst, w, _ = oracle.sample_bf(x, y, seed=81, replica=rep)
+        for a, c, ww in zip(src, dst, w):
+            assert a < c
+            W.setdefault((int(a), int(c)), []).append(int(ww))
+        return src, dst
+
+    assert _joint_chi2(fn, n, p, 40_000) > 1e-6
+    assert len(W) == n * (n - 1) // 2
+    for (i, j), ws in W.items():
+        ws = np.array(ws)
+        bij = b[i, j]
+        kmax = 10
+        obs = np.array([np.sum(ws == k) for k in range(1, kmax)] + [np.sum(ws >= kmax)], dtype=float)
+        pk = np.array([bij ** (k - 1) * (1 - bij) for k in range(1, kmax)] + [bij ** (kmax - 1)])
+        e = pk * len(ws)
+        keep = e >= 5
+        chi = ((obs[keep] - e[keep]) ** 2 / e[keep]).sum()
+        assert stats.chi2.sf(chi, max(keep.sum() - 1, 1)) > 1e-6, (i, j)
+        # the mean weight 1 / (1 - b): within 4 sigma (variance b / (1 - b)^2)
+        assert abs(ws.mean() - 1 / (1 - bij)) <= 4 * np.sqrt(bij / (1 - bij) ** 2 / len(ws))
+
+
+def test_weighted_bf_mean_strength_4sigma():
+    # the brute force's strengths over replicas against s_i = sum_j p_ij / (1 - b_ij)
+    rng = np.random.default_rng(25)
+    n = 400
+    x = np.exp(rng.normal(-1.5, 1.0, n))
+    y = rng.uniform(0.2, 0.9, n)
+    ek, es = oracle.expected_degree(x, y)
+    P, B = _p_uecm(x, y)
+    np.fill_diagonal(P, 0.0)
+    varw = P * (1 + B) / (1 - B) ** 2 - (P / (1 - B)) ** 2
+    R = 200
+    deg = np.zeros(n)
+    stren = np.zeros(n)
+    for rep in range(R):
+        src, dst, w, _ = oracle.sample_bf(x, y, seed=12, replica=rep)
+        deg += np.bincount(src, minlength=n) + np.bincount(dst, minlength=n)
+        stren += np.bincount(src, weights=w, minlength=n) + np.bincount(dst, weights=w, minlength=n)
+    zk = (deg / R - ek) / np.sqrt((P * (1 - P)).sum(axis=1) / R)
+    zs = (stren / R - es) / np.sqrt(varw.sum(axis=1) / R)
+    assert stats.chi2.sf((zk ** 2).sum(), n) > 1e-6
+    assert stats.chi2.sf((zs ** 2).sum(), n) > 1e-6
