@@ -79,6 +79,10 @@ def lib() -> ctypes.CDLL:
         L.mho_sample_bipartite_bf.restype = i64
         L.mho_plan_row_bipartite.argtypes = [vp, i64, d, d, i32, vp, vp, i64]
         L.mho_plan_row_bipartite.restype = i64
+        L.mho_sample_chung_lu.argtypes = [vp, i64, u64, u32, i32, vp, vp, i64, vp, vp, i64, P(i64)]
+        L.mho_sample_chung_lu.restype = i64
+        L.mho_count_triangles.argtypes = [vp, vp, i64, i64]
+        L.mho_count_triangles.restype = i64
         L.mho_sample_bf.argtypes = [vp, vp, i64, u64, u32, i64, i64, vp, vp, vp, i64, P(i64)]
         L.mho_sample_bf.restype = i64
         L.mho_expected_degree.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
@@ -203,6 +207,51 @@ def sample_mh(x, y=None, seed: int = 1, replica: int = 0, seg_work: int = 0,
             break
         cap, tcap = max(cap, int(m)), max(tcap, int(ntr.value))
     return Sample(src[:m], dst[:m], None if w is None else w[:m], st.as_dict(), ties[: ntr.value].copy())
+
+
+def sample_chung_lu(w, seed: int = 1, replica: int = 0, seg_work: int = 0, capacity: int | None = None) -> Sample:
+    """Miller-Hagberg sampler of the Chung-Lu model, p_ij = min(w_i w_j, 1)
+    (Sec. 2.3; the biased comparison model of Sec. 2.1)."""
+    w = _f64(w)
+    n = len(w)
+    st = Stats()
+    ntr = ctypes.c_int64(0)
+    cap = capacity if capacity is not None else max(1024, 8 * n)
+    tcap = 1024
+    while True:
+        src = np.zeros(cap, dtype=np.int32)
+        dst = np.zeros(cap, dtype=np.int32)
+        ties = np.zeros(tcap, dtype=np.int32)
+        m = lib().mho_sample_chung_lu(_p(w), n, seed, replica, seg_work, _p(src), _p(dst), cap, ctypes.byref(st),
+                                      _p(ties), len(ties), ctypes.byref(ntr))
+        if m < 0:
+            raise ValueError("oracle: invalid parameters (code %d)" % m)
+        if m <= cap and ntr.value <= tcap:
+            break
+        cap, tcap = max(cap, int(m)), max(tcap, int(ntr.value))
+    return Sample(src[:m], dst[:m], None, st.as_dict(), ties[: ntr.value].copy())
+
+
+def count_triangles(src, dst, n: int) -> int:
+    """Triangles of the simple undirected graph with these edges (each once)."""
+    s = np.ascontiguousarray(src, dtype=np.int32)
+    d = np.ascontiguousarray(dst, dtype=np.int32)
+    t = lib().mho_count_triangles(_p(s), _p(d), len(s), int(n))
+    if t < 0:
+        raise ValueError("oracle: invalid edge list")
+    return int(t)
+
+
+def rank_counts(src, dst, perm) -> np.ndarray:
+    """counts[j] = number of edges whose endpoint of larger rank (later in the
+    node order perm) has rank j: the edges among the first K ranks number
+    counts[:K].sum(), the numerator of the rich-club density of the K nodes of
+    largest parameter (Sec. 2.1, Fig. 1A)."""
+    perm = np.asarray(perm)
+    rank = np.empty(len(perm), dtype=np.int64)
+    rank[perm] = np.arange(len(perm))
+    hi = np.maximum(rank[np.asarray(src, np.int64)], rank[np.asarray(dst, np.int64)])
+    return np.bincount(hi, minlength=len(perm)).astype(np.int64)
 
 
 def sample_bf(x, y=None, seed: int = 1, replica: int = 0, row_begin: int = 0, row_end: int | None = None,

@@ -29,6 +29,12 @@ def ubcm_p(t: float) -> Fraction:
     return t / (1 + t)
 
 
+def chung_lu_p(t: float) -> Fraction:
+    """p = min(w_i w_j, 1): the Chung-Lu model read as edge probabilities
+    (Sec. 2.1), exactly for the float t = w_i w_j."""
+    return min(F(t), Fraction(1))
+
+
 def uecm_p(t: float, b: float) -> Fraction:
     """p = t / (1 - b + t), t = x_i y_i x_j y_j, b = y_i y_j (Sec. 2.5)."""
     t, b = F(t), F(b)
@@ -139,19 +145,23 @@ def bernoulli_law(p: dict[int, Fraction], cols: list[int]) -> dict[frozenset, Fr
     return out
 
 
-def row_law(zs, r: int, segments, ys=None, Y=None, force_first: bool = False):
+def row_law(zs, r: int, segments, ys=None, Y=None, force_first: bool = False, chung_lu: bool = False):
     """Law of row r's accepted columns for sorted parameters zs (and ys).
 
     segments: list of (a, b) column ranges covering (r, N).
-    ys is None: UBCM (proposal = target).  Otherwise UECM with bound value Y
-    (the Y used for row r).  Returns (law, target_law).
+    ys is None: UBCM, or with chung_lu the Chung-Lu model (proposal = target
+    in both).  Otherwise UECM with bound value Y (the Y used for row r).
+    Returns (law, target_law).
     """
     n = len(zs)
     s = zs[r]
     p, qcol = {}, {}
     for j in range(r, n):
         t = s * zs[j]  # float product, as the sampler computes it
-        if ys is None:
+        if chung_lu:
+            p[j] = chung_lu_p(t)
+            qcol[j] = p[j]
+        elif ys is None:
             p[j] = ubcm_p(t)
             qcol[j] = p[j]
         else:

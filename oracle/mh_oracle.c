@@ -251,6 +251,14 @@ static double skip_real(double u1, double tq, double c) {
     return -log(u1) / log1p(tq / c);
 }
 
+/* The skip of the Chung-Lu chain (Sec. 2.3): the proposal probability is
+   q = min(t_q, 1) itself, so -log(1 - q) = -log1p(-t_q) for t_q < 1; at
+   q = 1 every column is a candidate (L = 0). */
+static double skip_real_chung_lu(double u1, double tq) {
+    if (tq >= 1.0) return 0.0;
+    return -log(u1) / -log1p(-tq);
+}
+
 double mho_skip_real(double u1, double tq, double c) { return skip_real(u1, tq, c); }
 
 void mho_skip_reals(const double* u1, int64_t n, double tq, double c, double* d) {
@@ -296,9 +304,14 @@ static void emit(edge_sink* es, int32_t a, int32_t b, int32_t wt) {
     ++es->count;
 }
 
-int64_t mho_sample_mh(const double* x, const double* y, int64_t n, uint64_t seed, uint32_t replica,
-                      int32_t seg_work, int32_t* src, int32_t* dst, int32_t* w, int64_t capacity,
-                      mho_stats* stats, int32_t* tie_rows, int64_t tie_cap, int64_t* n_tie_rows) {
+/* One node set.  chung_lu != 0 (x holds the Chung-Lu weights w_i, y NULL):
+   the target is p = min(t, 1) and the proposal q = min(t_q, 1), the chain of
+   the Miller-Hagberg algorithm for the Chung-Lu model (Sec. 2.3); accept iff
+   U2 * q < p. */
+static int64_t sample_one_set(const double* x, const double* y, int chung_lu, int64_t n, uint64_t seed,
+                              uint32_t replica, int32_t seg_work, int32_t* src, int32_t* dst, int32_t* w,
+                              int64_t capacity, mho_stats* stats, int32_t* tie_rows, int64_t tie_cap,
+                              int64_t* n_tie_rows) {
     mho_stats st;
     memset(&st, 0, sizeof(st));
     int64_t ntr = 0;
@@ -346,14 +359,20 @@ int64_t mho_sample_mh(const double* x, const double* y, int64_t n, uint64_t seed
                 ++st.steps;
                 double U1 = mho_u53(u[0], u[1]);
                 double U2 = mho_u53(u[2], u[3]);
-                double d = skip_real(U1, tq, cr);
+                double d = chung_lu ? skip_real_chung_lu(U1, tq) : skip_real(U1, tq, cr);
                 double room = (double)(b - 1 - pos);
-                if (near_int(d) || fabs(d - room) <= 1e-12 * (room > 1.0 ? room : 1.0)) row_tie = 1;
+                /* a skip of exactly 0 at q = 1 is no rounding decision */
+                if (!(chung_lu && tq >= 1.0) &&
+                    (near_int(d) || fabs(d - room) <= 1e-12 * (room > 1.0 ? room : 1.0)))
+                    row_tie = 1;
                 if (d >= room) break;
                 int64_t j = pos + 1 + (int64_t)d;
                 double t = s * zs[j];
                 double lhs, rhs;
-                if (y) {
+                if (chung_lu) {
+                    lhs = U2 * (tq < 1.0 ? tq : 1.0);
+                    rhs = t < 1.0 ? t : 1.0;
+                } else if (y) {
                     double e = 1.0 - ys[r] * ys[j];
                     lhs = (U2 * tq) * (e + t);
                     rhs = t * (cr + tq);
@@ -392,6 +411,20 @@ done:
     if (stats) *stats = st;
     if (n_tie_rows) *n_tie_rows = ntr;
     return es.count;
+}
+
+int64_t mho_sample_mh(const double* x, const double* y, int64_t n, uint64_t seed, uint32_t replica,
+                      int32_t seg_work, int32_t* src, int32_t* dst, int32_t* w, int64_t capacity,
+                      mho_stats* stats, int32_t* tie_rows, int64_t tie_cap, int64_t* n_tie_rows) {
+    return sample_one_set(x, y, 0, n, seed, replica, seg_work, src, dst, w, capacity, stats, tie_rows, tie_cap,
+                          n_tie_rows);
+}
+
+int64_t mho_sample_chung_lu(const double* wgt, int64_t n, uint64_t seed, uint32_t replica, int32_t seg_work,
+                            int32_t* src, int32_t* dst, int64_t capacity, mho_stats* stats, int32_t* tie_rows,
+                            int64_t tie_cap, int64_t* n_tie_rows) {
+    return sample_one_set(wgt, NULL, 1, n, seed, replica, seg_work, src, dst, NULL, capacity, stats, tie_rows,
+                          tie_cap, n_tie_rows);
 }
 
 /* ------------------------------------------------------------------ bipartite */
@@ -748,4 +781,52 @@ int mho_expected_degree_grad(const double* x, const double* y, const double* mul
         if (y && gy) gy[d] = nsum_get(&sy);
     }
     return MHO_OK;
+}
+
+/* ------------------------------------------------------------------ triangles */
+/* Number of triangles of a simple undirected graph given as an edge list (each
+   edge once, either orientation, no self-loops), by the definition: unordered
+   triples {a, b, c} whose three pairs are all edges.  Each triangle is counted
+   once, at its two smallest ids a < b: the common neighbours c > b of a and b.
+   Used for the triangle statistics of sampled networks (Sec. 2.1, Fig. 1B). */
+static int cmp_i32(const void* pa, const void* pb) {
+    int32_t a = *(const int32_t*)pa, b = *(const int32_t*)pb;
+    return (a > b) - (a < b);
+}
+
+int64_t mho_count_triangles(const int32_t* src, const int32_t* dst, int64_t m, int64_t n) {
+    if (m < 0 || n < 0) return -1;
+    int64_t* deg = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t* adj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+    int64_t* fill = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < m; ++e) {
+        ++deg[src[e] + 1];
+        ++deg[dst[e] + 1];
+    }
+    for (int64_t i = 0; i < n; ++i) deg[i + 1] += deg[i];  /* deg[i] = start of i's list */
+    for (int64_t e = 0; e < m; ++e) {
+        adj[deg[src[e]] + fill[src[e]]++] = dst[e];
+        adj[deg[dst[e]] + fill[dst[e]]++] = src[e];
+    }
+    for (int64_t i = 0; i < n; ++i) qsort(adj + deg[i], (size_t)(deg[i + 1] - deg[i]), sizeof(int32_t), cmp_i32);
+    int64_t tri = 0;
+    for (int64_t a = 0; a < n; ++a) {
+        for (int64_t p = deg[a]; p < deg[a + 1]; ++p) {
+            int32_t b = adj[p];
+            if (b <= a) continue;
+            /* common neighbours c > b of a and b: merge the two sorted lists */
+            int64_t i = deg[a], j = deg[b];
+            while (i < deg[a + 1] && j < deg[b + 1]) {
+                if (adj[i] < adj[j]) ++i;
+                else if (adj[i] > adj[j]) ++j;
+                else {
+                    if (adj[i] > b) ++tri;
+                    ++i;
+                    ++j;
+                }
+            }
+        }
+    }
+    free(deg); free(adj); free(fill);
+    return tri;
 }

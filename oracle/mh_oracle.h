@@ -72,6 +72,19 @@ int64_t mho_sample_mh(const double* x, const double* y, int64_t n, uint64_t seed
                       int32_t seg_work, int32_t* src, int32_t* dst, int32_t* w, int64_t capacity,
                       mho_stats* stats, int32_t* tie_rows, int64_t tie_cap, int64_t* n_tie_rows);
 
+/* Miller-Hagberg sampler of the Chung-Lu model (Sec. 2.3, the comparison model
+   of Sec. 2.1): p_ij = min(w_i w_j, 1) with w_i = k_i / sqrt(2M).  The same
+   order, plan, counters and chain as mho_sample_mh, with proposal
+   q = min(t_q, 1), skip -log U1 / -log1p(-t_q) (0 when t_q >= 1) and
+   acceptance U2 * q < min(t, 1). */
+int64_t mho_sample_chung_lu(const double* w, int64_t n, uint64_t seed, uint32_t replica, int32_t seg_work,
+                            int32_t* src, int32_t* dst, int64_t capacity, mho_stats* stats, int32_t* tie_rows,
+                            int64_t tie_cap, int64_t* n_tie_rows);
+
+/* Triangles of a simple undirected graph (edge list, each edge once, either
+   orientation, ids < n): unordered triples whose three pairs are edges. */
+int64_t mho_count_triangles(const int32_t* src, const int32_t* dst, int64_t m, int64_t n);
+
 /* Bipartite / directed sampler (Sec. 2.6).  Rows are the "+" set (xr, yr, nr),
    columns the "-" set (xc, yc, nc), each sorted by its own z descending (ties
    by id); every row sweeps all columns; yr == NULL selects the unweighted

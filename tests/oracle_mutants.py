@@ -88,6 +88,17 @@ MUTANTS = [
     ("bipartite bound from the smallest column y",
      "if (yr && yc[j] > ymax_c) ymax_c = yc[j];", "if (yr && (ymax_c == 0.0 || yc[j] < ymax_c)) ymax_c = yc[j];", 0,
      [("test_oracle_bipartite", "test_bipartite_weighted_joint_law_and_weights", {"seg_work": 0})]),
+    ("Chung-Lu proposal not capped at 1",
+     "lhs = U2 * (tq < 1.0 ? tq : 1.0);", "lhs = U2 * tq;", 0,
+     [("test_oracle_chung_lu", "test_chung_lu_joint_law_chi2", {"seg_work": 0})]),
+    ("Chung-Lu skip with the unweighted model's log(1 - q)",
+     "return -log(u1) / -log1p(-tq);", "return -log(u1) / log1p(tq);", 0,
+     [("test_oracle_chung_lu", "test_chung_lu_joint_law_chi2", {"seg_work": 0}),
+      ("test_oracle_chung_lu", "test_homogeneous_chung_lu_is_erdos_renyi", {})]),
+    ("triangle counted at every common neighbour",
+     "if (adj[i] > b) ++tri;", "++tri;", 0,
+     [("test_oracle_chung_lu", "test_triangles_brute_force", {}),
+      ("test_oracle_chung_lu", "test_triangles_closed_forms", {})]),
 ]
 
 
