@@ -82,23 +82,100 @@ class HipEvents:
         return float(out.value)
 
 
-def cpu_baseline(x: np.ndarray, seed: int, seg_work: int, budget_s: float) -> dict:
-    """The CPU oracle (sequential, one thread) on whole samples of the same workload."""
+def edge_divergences(gs, gd, os_, od, n: int, tie_rows) -> tuple[int, int]:
+    """(divergences, of which outside near-tie rows) between a GPU and an
+    oracle edge list of one sample: pairs present in one list only."""
+    gk = np.sort(np.asarray(gs, np.int64) * n + np.asarray(gd, np.int64))
+    ok = np.sort(np.asarray(os_, np.int64) * n + np.asarray(od, np.int64))
+    diff = np.concatenate([np.setdiff1d(gk, ok, assume_unique=True), np.setdiff1d(ok, gk, assume_unique=True)])
+    outside = int((~np.isin(diff // n, np.asarray(tie_rows, np.int64))).sum()) if len(diff) else 0
+    return len(diff), outside
+
+
+def cpu_baseline(x: np.ndarray, seed: int, seg_work: int, budget_s: float, replicas: list, gpu_sample) -> dict:
+    """The CPU oracle (sequential, one thread) on whole samples of the same
+    workload and the same (seed, replica) pairs as the timed samples.  After
+    the clock, each oracle sample is compared with the GPU's sample of the same
+    replica (gpu_sample(replica) -> (src, dst) numpy arrays), edge for edge."""
     import oracle
 
     oracle.build()
     t_total = 0.0
     edges = 0
     reps = 0
-    while reps < 1 or (t_total < budget_s and reps < 500):
+    samples = []
+    while reps < 1 or (t_total < budget_s and reps < len(replicas)):
         t0 = time.perf_counter()
-        s = oracle.sample_mh(x, None, seed=seed, replica=10_000 + reps, seg_work=seg_work, capacity=int(2.5e6))
+        s = oracle.sample_mh(x, None, seed=seed, replica=replicas[reps], seg_work=seg_work, capacity=int(2.5e6))
         t_total += time.perf_counter() - t0
         edges += s.n_edges
+        samples.append((replicas[reps], s))
         reps += 1
+    n = len(x)
+    div = outside = ties = 0
+    for r, s in samples:
+        gs, gd = gpu_sample(r)
+        d, o = edge_divergences(gs, gd, s.src, s.dst, n, s.tie_rows)
+        div += d
+        outside += o
+        ties += len(s.tie_rows)
+    try:
+        host_cpus = len(os.sched_getaffinity(0))
+    except AttributeError:
+        host_cpus = os.cpu_count()
     return {"value": edges / t_total, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} whole samples of the N=1M workload (order + plan + sequential sweep), "
-                      f"{t_total:.1f} s single-threaded"}
+            "host_cpus": host_cpus,
+            "sample": f"{reps} whole samples of the N=1M workload (order + plan + sequential sweep), the timed "
+                      f"samples' (seed, replica) pairs first, {t_total:.1f} s single-threaded",
+            "parity": {"samples_compared": reps, "edges_compared": edges, "divergences": div,
+                       "divergences_outside_near_tie_rows": outside, "near_tie_rows": ties,
+                       "allowed": max(1, int(edges * 1e-7))}}
+
+
+def small_bench(args, dev) -> dict:
+    """The N = 2,000 network (x = exp(Normal(-4, 1.5))): microseconds per
+    sample of the plain MH sampler and of the GPU brute force, as synchronous
+    calls (each reads its edge count back; the best of many), and of MH
+    samples issued back to back through the asynchronous entry point."""
+    import torch
+
+    import paper_2509_13230_amd as mh
+    import workloads
+
+    xn = workloads.cfg1_small(seed=1)
+    x = torch.as_tensor(xn, device=dev)
+    n = x.numel()
+    L = mh.lib()
+    plan = mh.PlanParams(args.seg_work, 0, 0, 0, None)
+    ws = torch.empty(L.mh_workspace_bytes(n, 0, ctypes.byref(plan)), dtype=torch.uint8, device=dev)
+    src = torch.empty(64 * n, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+
+    def best(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        return min(t), out
+
+    t_mh, (sm, _) = best(lambda: mh.sample_unweighted(x, seed=args.seed, replica=0, seg_work=args.seg_work,
+                                                      out=(src, dst), workspace=ws), 50)
+    t_bf, (sb, _) = best(lambda: mh.sample_bruteforce(x, seed=args.seed, replica=0, out=(src, dst)), 50)
+    k = 200
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(k):
+        mh.sample_async(x, None, (src, dst), ws, seed=args.seed, replica=r, seg_work=args.seg_work)
+    torch.cuda.synchronize()
+    t_async = (time.perf_counter() - t0) / k
+    return {"workload": f"N={n}, x = exp(Normal(-4, 1.5)), one sample", "input_sha256": workloads.sha256(xn),
+            "us_per_sample_mh_sync": t_mh * 1e6, "us_per_sample_mh_back_to_back": t_async * 1e6,
+            "us_per_sample_bruteforce_sync": t_bf * 1e6, "edges_mh": int(sm.numel()), "edges_bruteforce": int(sb.numel()),
+            "pairs": n * (n - 1) // 2}
 
 
 # VALU instructions per pair of the brute-force sampler's loop (Philox block,
@@ -133,6 +210,7 @@ def bruteforce_vs_mh(args, x, dev) -> dict:
 
     t_bf, (sb, _) = best(lambda: mh.sample_bruteforce(xp, seed=args.seed, replica=0), 3)
     t_mh, (sm, _) = best(lambda: mh.sample_unweighted(xp, seed=args.seed, replica=0, seg_work=args.seg_work), 10)
+    acc = degree_accuracy(args, xp, dev)
     return {
         "workload": f"first {n} nodes of the N=1M workload (their fitted x), one sample",
         "pairs": pairs,
@@ -146,7 +224,46 @@ def bruteforce_vs_mh(args, x, dev) -> dict:
         "edges_mh": int(sm.numel()),
         "edges_per_s_mh": sm.numel() / t_mh,
         "speedup_mh_vs_bruteforce": t_bf / t_mh,
+        "degree_accuracy": acc,
     }
+
+
+def degree_accuracy(args, xp, dev) -> dict:
+    """Both samplers' mean degrees over R replicas against the exact expected
+    degrees: z_i = (mean_i - E_i) / sqrt(V_i / R), E_i = sum_j p_ij and
+    V_i = sum_j p_ij (1 - p_ij) computed in float64 by torch over all pairs.
+    An exact sampler gives z close to standard normal: |z| <= 4 for all but a
+    few in 1e4 nodes and mean z^2 near 1."""
+    import torch
+
+    import paper_2509_13230_amd as mh
+
+    n = xp.numel()
+    R = args.accuracy_replicas
+    E = torch.zeros(n, dtype=torch.float64, device=dev)
+    V = torch.zeros(n, dtype=torch.float64, device=dev)
+    for a in range(0, n, 2048):
+        t = xp[a:a + 2048, None] * xp[None, :]
+        p = t / (1.0 + t)
+        idx = torch.arange(a, min(a + 2048, n), device=dev)
+        p[idx - a, idx] = 0.0
+        E[a:a + 2048] = p.sum(1)
+        V[a:a + 2048] = (p * (1.0 - p)).sum(1)
+    out = {"replicas": R, "nodes": n}
+    for name, fn in (("mh", lambda r: mh.sample_unweighted(xp, seed=args.seed, replica=r, seg_work=args.seg_work)),
+                     ("bruteforce", lambda r: mh.sample_bruteforce(xp, seed=args.seed, replica=r))):
+        deg = torch.zeros(n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(R):
+            s_, d_ = fn(100 + r)
+            deg += torch.bincount(s_.long(), minlength=n).double() + torch.bincount(d_.long(), minlength=n).double()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        z = (deg / R - E) / torch.sqrt(V / R)
+        out[name] = {"within_4_sigma": float((z.abs() <= 4).double().mean()), "max_abs_z": float(z.abs().max()),
+                     "mean_z2": float((z * z).mean()), "ms_per_replica_incl_degree_count": el / R * 1e3}
+    return out
 
 
 # VALU instructions per (row, column) pair of the expected-degree kernels'
@@ -398,11 +515,12 @@ def batched_ensemble(args, dev) -> dict:
     dst = torch.empty(cap, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain_edges = 0
+    plain_counts = []
     for i, r in zip(net_ids, reps):
         s_, _ = mh.sample_unweighted(xs[i], seed=args.seed, replica=r, seg_work=sw, out=(src, dst),
                                      workspace=ws)
-        plain_edges += s_.numel()
+        plain_counts.append(s_.numel())
+    plain_edges = sum(plain_counts)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     # the same samples issued back to back through the asynchronous entry point
@@ -435,6 +553,39 @@ def batched_ensemble(args, dev) -> dict:
         runs.append(time.perf_counter() - t0)
     t_batch = min(runs)
     batch_edges = int(deg.sum().item()) // 2
+    del deg, g
+
+    # batched, edge output: the samples in consecutive groups whose edges fit
+    # one output buffer (src, dst and the sample index, int32 each), one
+    # persistent launch per group, the buffer reused like the plain samples'
+    group_cap = args.batch_edge_buffer
+    groups, cur, cur_edges = [], [], 0
+    for s_i, c in enumerate(plain_counts):
+        if cur and cur_edges + c > group_cap:
+            groups.append(cur)
+            cur, cur_edges = [], 0
+        cur.append(s_i)
+        cur_edges += c
+    groups.append(cur)
+    esrc = torch.empty(group_cap, dtype=torch.int32, device=dev)
+    edst = torch.empty(group_cap, dtype=torch.int32, device=dev)
+    esid = torch.empty(group_cap, dtype=torch.int32, device=dev)
+    gnet = [torch.tensor([net_ids[j] for j in grp], dtype=torch.int32, device=dev) for grp in groups]
+    grep = [torch.tensor([reps[j] for j in grp], dtype=torch.int32, device=dev) for grp in groups]
+    b.sample_edges_async(gnet[0], grep[0], args.seed, esrc, edst, None, esid, group_cap, tuned["grid_blocks"])
+    b.result(group_cap)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    edge_total = 0
+    for gn, gr in zip(gnet, grep):
+        b.sample_edges_async(gn, gr, args.seed, esrc, edst, None, esid, group_cap, tuned["grid_blocks"])
+        m = b.result(group_cap)
+        if m < 0:
+            raise RuntimeError(f"batched edge output overflowed its buffer ({-m} edges)")
+        edge_total += m
+    torch.cuda.synchronize()
+    t_batch_edges = time.perf_counter() - t0
+    del esrc, edst, esid
     # The degree sink adds 1 to a column's counter per sampled edge (and each
     # row's count once per row): bound by the GPU's rate of random atomic adds.
     ceiling = atomic_add_rate(dev)
@@ -446,24 +597,32 @@ def batched_ensemble(args, dev) -> dict:
         "plain_edges": plain_edges,
         # the same (network, replica, seed, seg_work) draws the same samples either way
         "plain_edges_equal": plain_edges == batch_edges,
-        "replicas_per_s_batched": S / t_batch,
-        "replicas_per_s_batched_incl_prepare": S / (t_batch + t_prepare),
+        # like for like: both write every edge to HBM
+        "replicas_per_s_batched": S / t_batch_edges,
         "replicas_per_s_plain": S / t_plain_async,
+        "speedup_vs_plain": t_plain_async / t_batch_edges,
+        "output": "edge lists (plain: src, dst; batched: src, dst and the sample index, in "
+                  f"{len(groups)} launches of up to {group_cap} edges)",
+        "batched_edges_equal": edge_total == plain_edges,
+        "edges_per_s_batched": edge_total / t_batch_edges,
+        "ms_batched_edges_total": t_batch_edges * 1e3,
         "replicas_per_s_plain_sync": S / t_plain,
-        "speedup_vs_plain": t_plain_async / t_batch,
-        "speedup_vs_plain_sync": t_plain / t_batch,
-        "edges_per_s_batched": batch_edges / t_batch,
-        "ms_batched_launch": t_batch * 1e3,
         "ms_prepare": t_prepare * 1e3,
         "ms_plain_total": t_plain_async * 1e3,
         "ms_plain_sync_total": t_plain * 1e3,
-        "output": "degree sink (per-sample degree sequences)",
+        "replicas_per_s_batched_incl_prepare": S / (t_batch_edges + t_prepare),
+        # a different output: per-sample degree sequences, no edge list
+        "degree_sink": {"replicas_per_s": S / t_batch, "ms_graph_launch": t_batch * 1e3,
+                        "edges_per_s": batch_edges / t_batch,
+                        "speedup_vs_plain_edge_output": t_plain_async / t_batch,
+                        # no published figure exists for this rate: the ceiling is measured
+                        "atomic_ceiling": {"bound": "atomic", "achieved": batch_edges / t_batch, "ceiling": ceiling,
+                                           "unit": "int32 atomic adds/s", "frac": batch_edges / t_batch / ceiling,
+                                           "work_per_launch": f"{batch_edges} column adds (one per edge; per-row "
+                                                              "adds not counted)",
+                                           "ceiling_source": "measured here (libmh_probe.so): 2048 x 256 lanes x "
+                                                             "256 random int32 atomic adds into 2^22 counters"}},
         "tuned": tuned,
-        "atomic_roofline": {"bound": "atomic", "achieved": batch_edges / t_batch, "peak": ceiling,
-                            "unit": "int32 atomic adds/s", "frac": batch_edges / t_batch / ceiling,
-                            "work_per_launch": f"{batch_edges} column adds (one per edge; per-row adds not counted)",
-                            "peak_source": "measured here (libmh_probe.so): 2048 x 256 lanes x 256 random int32 "
-                                           "atomic adds into 2^22 counters"},
     }
 
 
@@ -487,12 +646,16 @@ def main():
     ap.add_argument("--bip-rows", type=int, default=1_000_000,
                     help="rows of the bipartite measurement, with half as many columns (0: skip it)")
     ap.add_argument("--bip-seg-work", type=int, default=8, help="seg_work of the two-set measurement")
+    ap.add_argument("--accuracy-replicas", type=int, default=64,
+                    help="replicas of the degree-accuracy comparison of MH and brute force")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="copy a buffer of this many MiB once first (reference for HBM byte counters)")
     ap.add_argument("--batch-networks", type=int, default=256)
     ap.add_argument("--batch-replicas", type=int, default=16)
+    ap.add_argument("--batch-edge-buffer", type=int, default=1_500_000_000,
+                    help="edges per launch of the batched edge-output measurement")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -514,14 +677,22 @@ def main():
         bcopy.copy_(a)
         torch.cuda.synchronize()
         del a, bcopy
+    # the timed input: x fitted on the CPU to the power-law targets (stored,
+    # one value per degree class); the device fit of the same targets runs
+    # beside it (untimed) and is reported against it
     k_target = workloads.cfg2_degrees(seed=2, n=args.n)
+    x_np = workloads.cfg2_fitted_x() if args.n == 1_000_000 else None
     t0 = time.perf_counter()
     fit = fit_ubcm(k_target, tol=1e-10)
     t_fit = time.perf_counter() - t0
-    x_np = fit.x
+    if x_np is None:
+        x_np = fit.x
+    fit_info = {"device_fit_iterations": fit.iterations, "device_fit_residual": fit.residual,
+                "device_fit_s": t_fit,
+                "device_fit_max_rel_diff_from_input": float(np.max(np.abs(fit.x - x_np) / x_np))}
     x = torch.as_tensor(x_np, device=dev)
     n = x.numel()
-    print(f"# fit: {fit.iterations} iterations, residual {fit.residual:.2e}, {t_fit:.2f} s", file=sys.stderr,
+    print(f"# device fit: {fit.iterations} iterations, residual {fit.residual:.2e}, {t_fit:.2f} s", file=sys.stderr,
           flush=True)
 
     L = mh.lib()
@@ -607,15 +778,17 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "UBCM, N=1,000,000, power-law target degrees (exponent 2.1, k in [1, 10^4]), "
-                               "x fitted (class-compressed fixed point), one sample per step, samples issued "
-                               "back to back on one stream",
+                               "x fitted (class-compressed fixed point, residual 1e-10, stored CPU fit), one "
+                               "sample per step, samples issued back to back on one stream",
                    "n": n, "seg_work": args.seg_work, "mean_edges_per_sample": edges / args.steps,
-                   "fit_residual": fit.residual},
+                   "input_sha256": workloads.sha256(x_np)},
+        "fit": fit_info,
         "stages_ms": {"order": stage[0] / args.steps, "bound_plan": stage[1] / args.steps, "sweep": sweep_ms},
         "sweep_steps_per_sample": steps_total / args.steps,
         "sweep_only_edges_per_s": edges_per_sweep / (sweep_ms * 1e-3),
         "roofline": roof,
     }
+    out["small"] = small_bench(args, dev)
     if not args.skip_batched:
         out["batched"] = batched_ensemble(args, dev)
     if args.bf_prefix > 0:
@@ -627,7 +800,15 @@ def main():
     if args.deg_n > 0:
         out["expected_degree"] = expected_degree_bench(args, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x_np, args.seed, args.seg_work, args.cpu_budget)
+        def gpu_sample(replica):
+            s_, d_ = mh.sample_unweighted(x, seed=args.seed, replica=replica, seg_work=args.seg_work,
+                                          out=(src, dst), workspace=ws, grid_blocks=args.grid_blocks)
+            return s_.cpu().numpy(), d_.cpu().numpy()
+
+        # the timed samples' (seed, replica) pairs first, then further replicas
+        out["cpu_baseline"] = cpu_baseline(x_np, args.seed, args.seg_work, args.cpu_budget,
+                                           replicas + [1000 + args.steps + i for i in range(500)], gpu_sample)
+        out["parity"] = out["cpu_baseline"]["parity"]
     print(json.dumps(out), flush=True)
 
 

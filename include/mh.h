@@ -12,8 +12,16 @@
  *   - Pointers named without a _host suffix are device pointers (HIP global
  *     memory) usable on `stream`; *_host pointers are host memory.
  *   - The caller owns every buffer, including the workspace; the library
- *     allocates no memory and keeps no state between calls.  Calls on
- *     different streams with different workspaces may run concurrently.
+ *     allocates no memory.  Its only state: per-device facts it caches (the
+ *     number of CUs, kernels' occupancy).
+ *   - Concurrency: the order step of a network of at most 256 tiles of 4096
+ *     nodes (and no more tiles than the GPU has CUs: n <= 1,048,576 on an
+ *     MI355X) exchanges digit counts between all of its tiles, which must be
+ *     resident at once.  Run such calls alone on the GPU: a kernel running
+ *     beside them (another stream, another process) can keep a tile from
+ *     starting, and the sort then waits until its spin limit and returns
+ *     MH_EHIP.  Larger networks use a look-back that tolerates it.  Calls
+ *     must not share a workspace unless they are ordered on one stream.
  *   - Node ids are int32 (n <= 2^31 - 1); counts are int64.
  *   - Parameters must be finite with x >= 0, y >= 0; (max z)^2 must be finite
  *     (z = x, or z = x*y weighted); weighted models need y_(1) y_(2) < 1 (the

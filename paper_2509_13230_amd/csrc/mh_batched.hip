@@ -53,12 +53,19 @@ __global__ __launch_bounds__(kThreads) void k_batch_zero_degrees(const NetDesc* 
     }
 }
 
+// Start of a sampling call: clears the edge count and statistics, and the
+// status of any earlier call; a preparation error (invalid networks) stays.
 __global__ void k_batch_init(Counters* c) {
     if (threadIdx.x == 0) {
         c->n_edges = 0;
         for (int i = 0; i < ST_COUNT; ++i) c->stats[i].v = 0;
-        c->pad = 0;  // status is kept: it records invalid networks found by the preparation
+        c->status = c->prep_status;
     }
+}
+
+// End of a preparation: its status becomes the batch's preparation status.
+__global__ void k_batch_seal(Counters* c) {
+    if (threadIdx.x == 0) c->prep_status = c->status;
 }
 
 struct BatchLayout {
@@ -161,6 +168,8 @@ mh_status mh_batch_prepare(const mh_network* nets, int32_t n_networks, int32_t m
         descs[i] = net_desc(L.bufs[i]);
     }
     MH_HIP_TRY(hipMemcpyAsync(L.nets, descs.data(), sizeof(NetDesc) * n_networks, hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_batch_seal, dim3(1), dim3(64), 0, stream, L.ctr);
+    MH_HIP_TRY(hipGetLastError());
     Counters hc;
     MH_HIP_TRY(hipMemcpyAsync(&hc, L.ctr, sizeof(hc), hipMemcpyDeviceToHost, stream));
     MH_HIP_TRY(hipStreamSynchronize(stream));

@@ -1,13 +1,17 @@
-// Measurement probe, not part of the sampler: the rate at which the GPU
-// performs device-scope int32 atomic adds at random addresses.  The degree
-// sink of the batched sampler issues one such add per sampled edge, so this
-// rate is the ceiling its throughput is compared against.
-//
-// Built into its own library (libmh_probe.so); only the benchmark loads it.
+// Measurement and test probes, not part of the sampler, built into their own
+// library (libmh_probe.so), which only the benchmark and the tests load:
+//  - the rate at which the GPU performs device-scope int32 atomic adds at
+//    random addresses (the degree sink of the batched sampler issues one such
+//    add per sampled edge, so this rate is the ceiling it is compared against);
+//  - the sweep's own logarithms (log_fast, log1p_fast of mh_common.hpp)
+//    evaluated on the device, so that tests can bound their error against the
+//    host's log and log1p.
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+
+#include "mh_common.hpp"
 
 namespace {
 
@@ -24,9 +28,36 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_atomic_adds(int32_t* __
     }
 }
 
+// out_log[i] = log_fast(u[i]) and out_log1p[i] = log1p_fast(t[i]), the
+// device functions the sweep calls for the skip (U in (0, 1], t >= 0 finite).
+__global__ __launch_bounds__(kProbeThreads) void k_probe_logs(const double* __restrict__ u,
+                                                              const double* __restrict__ t, int64_t n,
+                                                              double* __restrict__ out_log,
+                                                              double* __restrict__ out_log1p) {
+    const int64_t i = (int64_t)blockIdx.x * kProbeThreads + threadIdx.x;
+    if (i >= n) return;
+    out_log[i] = mh::log_fast(u[i]);
+    out_log1p[i] = mh::log1p_fast(t[i]);
+}
+
 }  // namespace
 
 extern "C" {
+
+// Evaluates the sweep's logarithms on n inputs (device arrays of float64):
+// out_log = log_fast(u), u normal and positive; out_log1p = log1p_fast(t),
+// t finite and >= 0.  Asynchronous on `stream`; 0, -1 for invalid arguments,
+// -2 for a failed launch.
+int mhp_sweep_logs(const double* u, const double* t, int64_t n, double* out_log, double* out_log1p,
+                   hipStream_t stream) {
+    if (n < 0 || (n > 0 && (!u || !t || !out_log || !out_log1p))) return -1;
+    if (n == 0) return 0;
+    const int64_t blocks = (n + kProbeThreads - 1) / kProbeThreads;
+    if (blocks > 0x7FFFFFFF) return -1;
+    hipLaunchKernelGGL(k_probe_logs, dim3((unsigned)blocks), dim3(kProbeThreads), 0, stream, u, t, n, out_log,
+                       out_log1p);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
 
 // Launches blocks x 256 lanes, each adding 1 to `iters` pseudo-random counters
 // of `counters` (device memory of `slots` int32, slots a power of two, 1 to

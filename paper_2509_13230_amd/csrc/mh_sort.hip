@@ -382,7 +382,7 @@ __device__ int64_t wave_run_start(const uint32_t* __restrict__ hi, int64_t r) {
 constexpr int kFixThreads = 1024;
 constexpr int kFixWaves = kFixThreads / kWave;
 constexpr int kFixLds = 4096;  // runs up to this long are sorted in LDS (block_lds_run), longer ones by block_lsd_run
-constexpr int kFixWaveRun = 256;  // runs up to this long are sorted by one wave (wave_lds_run)
+constexpr int kFixWaveRun = 256;  // runs up to this long are sorted by one wave (wave_sort_run)
 // A block of k_fix_runs takes chunks of ranks: small chunks spread the runs
 // longer than a wave (each sorted by the whole block) over many blocks.  Chunks
 // are 1024 ranks where every chunk then has a block of its own, else 2048
@@ -545,89 +545,74 @@ __device__ void block_lsd_run(uint64_t* __restrict__ pay, uint64_t* __restrict__
     }
 }
 
-// Stable sort by the high 32 bits of the run of equal hi (= h) that starts at
-// a, by one wave, if the run ends within kFixWaveRun ranks of a (its first 64
-// ranks are known to be in it); returns false (nothing written) if it is
-// longer.  Each lane holds 4 values in registers; the digits are those of
-// block_lds_run; a pass ranks them with the wave's 256 digit counts (s_c) and
-// scatters them through s_b (kFixWaveRun values), both the wave's own LDS.
-__device__ bool wave_lds_run(const uint32_t* __restrict__ hi, uint64_t* __restrict__ pay, int64_t n, int64_t a,
-                             uint32_t h, uint64_t* s_b, uint32_t* s_c) {
-    constexpr int K = kFixWaveRun / kWave;
+// Sorts up to 64 K values held K a lane (element k * 64 + lane in v[k]; absent
+// ones hold ~0) ascending: a bitonic network over 64 K elements, partners 64 or
+// more apart in two registers of the same lane, nearer ones in the same
+// register of two lanes (shuffles).  Registers only: no LDS.
+template <int K>
+__device__ __forceinline__ void wave_bitonic_regs(uint64_t (&v)[K]) {
     const int lane = threadIdx.x & 63;
-    const uint64_t lt = lanemask_lt();
-    int len = -1;
-    for (int k = 1; k <= K && len < 0; ++k) {
-        const int i = k * kWave + lane;
-        const bool past = i <= kFixWaveRun && (a + i >= n || hi[a + i] != h);
-        const uint64_t m = __ballot(past);
-        if (m) len = k * kWave + __ffsll((unsigned long long)m) - 1;
+#pragma unroll
+    for (int s = 2; s <= K * kWave; s <<= 1) {
+#pragma unroll
+        for (int j = s >> 1; j > 0; j >>= 1) {
+            if (j >= kWave) {
+                const int kj = j / kWave;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (k & kj) continue;  // the pair (k, k + kj)
+                    const bool up = ((k * kWave + lane) & s) == 0;
+                    const uint64_t lo = v[k], hi2 = v[k + kj];
+                    const bool swap = up ? lo > hi2 : lo < hi2;
+                    v[k] = swap ? hi2 : lo;
+                    v[k + kj] = swap ? lo : hi2;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint64_t u = __shfl_xor(v[k], j, kWave);
+                    const bool up = ((k * kWave + lane) & s) == 0;
+                    const bool low = (lane & j) == 0;
+                    v[k] = (low == up) ? (u < v[k] ? u : v[k]) : (u > v[k] ? u : v[k]);
+                }
+            }
+        }
     }
-    if (len < 0) return false;  // the same for every lane of the wave
+}
+
+// Loads the len values pay[a, a + len) K a lane, sorts them by the whole
+// 64-bit payload (in a run of equal high halves the payload's low word rises
+// with the input order, so this is the stable order by its high word) and
+// writes them back.
+template <int K>
+__device__ __forceinline__ void wave_sort_run(uint64_t* __restrict__ pay, int64_t a, int len) {
+    const int lane = threadIdx.x & 63;
     uint64_t v[K];
-    uint32_t mn = ~0u, mx = 0u;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = k * kWave + lane;
-        v[k] = i < len ? pay[a + i] : 0ull;
-        if (i < len) {
-            const uint32_t hv = (uint32_t)(v[k] >> 32);
-            mn = hv < mn ? hv : mn;
-            mx = hv > mx ? hv : mx;
-        }
+        v[k] = i < len ? pay[a + i] : ~0ull;
     }
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t on = __shfl_xor(mn, d, kWave), ox = __shfl_xor(mx, d, kWave);
-        mn = on < mn ? on : mn;
-        mx = ox > mx ? ox : mx;
-    }
-    const uint32_t spread = mx - mn;
-    const int npass = spread == 0 ? 0 : (spread >> 8) == 0 ? 1 : (spread >> 16) == 0 ? 2 : (spread >> 24) == 0 ? 3 : 4;
-    for (int pass = 0; pass < npass; ++pass) {
-        const int shift = 8 * pass;
-#pragma unroll
-        for (int k = 0; k < K; ++k) s_c[k * kWave + lane] = 0;
-        __builtin_amdgcn_wave_barrier();
-        uint32_t dg[K], rk[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const bool valid = k * kWave + lane < len;
-            dg[k] = ((((uint32_t)(v[k] >> 32)) - mn) >> shift) & 255u;
-            const uint64_t m = match_digit(dg[k], valid);
-            const uint32_t prior = s_c[dg[k]];
-            rk[k] = prior + (uint32_t)__popcll(m & lt);
-            __builtin_amdgcn_wave_barrier();
-            if (valid && (m & lt) == 0) s_c[dg[k]] = prior + (uint32_t)__popcll(m);
-            __builtin_amdgcn_wave_barrier();
-        }
-        // digit starts: lane l scans digits 4l .. 4l + 3
-        const uint32_t c0 = s_c[4 * lane], c1 = s_c[4 * lane + 1], c2 = s_c[4 * lane + 2], c3 = s_c[4 * lane + 3];
-        const uint32_t tot = c0 + c1 + c2 + c3;
-        const uint32_t pre = wave_inclusive_scan(tot) - tot;
-        __builtin_amdgcn_wave_barrier();
-        s_c[4 * lane] = pre;
-        s_c[4 * lane + 1] = pre + c0;
-        s_c[4 * lane + 2] = pre + c0 + c1;
-        s_c[4 * lane + 3] = pre + c0 + c1 + c2;
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (k * kWave + lane < len) s_b[s_c[dg[k]] + rk[k]] = v[k];
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = k * kWave + lane;
-            v[k] = i < len ? s_b[i] : 0ull;
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
+    wave_bitonic_regs<K>(v);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = k * kWave + lane;
         if (i < len) pay[a + i] = v[k];
     }
-    return true;
+}
+
+// Length of the run of equal hi (= h) that starts at a, if it ends within
+// kFixWaveRun ranks of a (its first 64 ranks are known to be in it), else -1;
+// the same in every lane of the wave.
+__device__ int wave_run_length(const uint32_t* __restrict__ hi, int64_t n, int64_t a, uint32_t h) {
+    const int lane = threadIdx.x & 63;
+    for (int k = 1; k <= kFixWaveRun / kWave; ++k) {
+        const int i = k * kWave + lane;
+        const bool past = i <= kFixWaveRun && (a + i >= n || hi[a + i] != h);
+        const uint64_t m = __ballot(past);
+        if (m) return k * kWave + __ffsll((unsigned long long)m) - 1;
+    }
+    return -1;
 }
 
 // Stable sort by the high 32 bits of the run of equal hi that starts at a, in
@@ -749,7 +734,8 @@ __device__ bool block_lds_run(const uint32_t* __restrict__ hi, uint64_t* __restr
 // read that run's values mid-sort, which can only make them try the claim
 // again, and fail.  The block's claimed runs are sorted by single waves at
 // once up to kFixWaveRun ranks (bitonic over the lanes below 64, else
-// wave_lds_run), longer ones by the whole block: in LDS up to kFixLds
+// wave_sort_run: a bitonic network in registers), longer ones by the whole
+// block: in LDS up to kFixLds
 // (block_lds_run), else by block_lsd_run through alt.
 __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __restrict__ hi,
                                                           uint64_t* __restrict__ pay, uint64_t* __restrict__ alt,
@@ -766,7 +752,6 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
     __shared__ uint32_t s_scan[kFixWaves];
     __shared__ uint32_t s_flag[4];
     static_assert(kFixWaves * 256 + 4 * 256 <= 2 * kFixLds, "digit counts fit in the run buffer");
-    static_assert(kFixWaves * kFixWaveRun <= kFixLds, "every wave has a slice of the second run buffer");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < n; c0 += (int64_t)gridDim.x * chunk) {
         const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
@@ -816,9 +801,16 @@ __global__ __launch_bounds__(kFixThreads) void k_fix_runs(const uint32_t* __rest
             const bool in = r < n && hi[r] == h;
             const uint64_t inm = __ballot(in);
             if (inm == ~0ull) {
-                if (!wave_lds_run(hi, pay, n, a, h, s_run2 + wave * kFixWaveRun, s_wcnt + wave * 256) && lane == 0) {
-                    const uint32_t slot = atomicAdd(&s_nlist, 1u);
-                    if (slot < kFixList) s_list[slot] = a;
+                const int len = wave_run_length(hi, n, a, h);
+                if (len < 0) {
+                    if (lane == 0) {
+                        const uint32_t slot = atomicAdd(&s_nlist, 1u);
+                        if (slot < kFixList) s_list[slot] = a;
+                    }
+                } else if (len <= 2 * kWave) {
+                    wave_sort_run<2>(pay, a, len);
+                } else {
+                    wave_sort_run<4>(pay, a, len);
                 }
             } else {
                 // run of length < 64: lanes below the first differing lane

@@ -40,7 +40,7 @@ __global__ void k_init_counters(Counters* c) {
         c->n_edges = 0;
         for (int i = 0; i < ST_COUNT; ++i) c->stats[i].v = 0;
         c->status = 0;
-        c->pad = 0;
+        c->prep_status = 0;
     }
 }
 

@@ -40,8 +40,8 @@ struct alignas(256) StatSlot {
 
 struct Counters {
     unsigned long long n_edges;
-    int32_t status;
-    int32_t pad;
+    int32_t status;       // first error of the current call (0: none)
+    int32_t prep_status;  // a batch's preparation error, restored into status by every call on it
     StatSlot stats[ST_COUNT];
 };
 

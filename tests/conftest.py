@@ -24,3 +24,14 @@ def oracle_lib():
 
     oracle.build()
     return oracle
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    # divergence totals of the edge-list parity comparisons run in this session
+    import parity
+
+    s = parity.summary()
+    if s["comparisons"]:
+        terminalreporter.write_line(
+            "edge parity: {comparisons} comparisons, {edges_compared} edges compared, {divergences} divergences "
+            "({near_tie_rows} near-tie rows in the oracle's traces)".format(**s))

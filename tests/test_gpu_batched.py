@@ -1,14 +1,17 @@
 """GPU parity of the batched persistent sampler against the oracle.
 
 Sample (network i, replica r) of a batch must equal the oracle's sample of
-network i with the same seed, replica and plan parameter, edge for edge; the
-degree-sink mode must equal the degree sequences of those samples; a captured
-hipGraph replays to the same result as the eager call.
+network i with the same seed, replica and plan parameter, edge for edge (the
+bar of tests/parity.py: counted divergences in the oracle's near-tie rows
+only); the degree-sink mode must equal the degree sequences of those samples;
+a captured hipGraph replays to the same result as the eager call.  Every
+sample of a batch is compared.
 """
 import numpy as np
 import pytest
 
 import oracle
+import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +50,24 @@ def _keys(src, dst, n, w=None):
     return key[o], np.asarray(w)[o]
 
 
+def _compare_sample(src, dst, w, sel, ora, n, label):
+    """Edges of one sample of a batch (rows `sel` of the batch's lists) against
+    the oracle's sample."""
+    return parity.edge_divergences(src[sel], dst[sel], None if w is None else w[sel], ora.src, ora.dst,
+                                   ora.w if w is not None else None, n, ora.tie_rows, label=label)
+
+
+def _compare_degrees(deg, ora, n, label):
+    """A degree-sink sequence against the oracle sample's degrees: identical,
+    or (near-tie rows only) differing by at most two units per allowed
+    divergence."""
+    ref = np.bincount(ora.src, minlength=n) + np.bincount(ora.dst, minlength=n)
+    if len(ora.tie_rows) == 0:
+        assert np.array_equal(deg, ref), label
+        return
+    assert int(np.abs(deg.astype(np.int64) - ref).sum()) <= 2 * parity.allowed_divergences(len(ora.src)), label
+
+
 @pytest.mark.parametrize("seg_work", [0, 8])
 def test_batch_edges_match_oracle(mh, seg_work):
     sizes = [1, 2, 300, 2500, 40, 1800]
@@ -56,12 +77,12 @@ def test_batch_edges_match_oracle(mh, seg_work):
     rep = [r for _ in sizes for r in (0, 5, 9)]
     src, dst, _, sid = b.sample_edges(net, rep, seed=17)
     src, dst, sid = src.cpu().numpy(), dst.cpu().numpy(), sid.cpu().numpy()
+    compared = 0
     for s, (i, r) in enumerate(zip(net, rep)):
-        sel = sid == s
         ora = oracle.sample_mh(xs[i], None, seed=17, replica=r, seg_work=seg_work)
-        if len(ora.tie_rows):
-            continue
-        assert np.array_equal(_keys(src[sel], dst[sel], sizes[i])[0], _keys(ora.src, ora.dst, sizes[i])[0]), (i, r)
+        _compare_sample(src, dst, None, sid == s, ora, sizes[i], f"batch net {i} replica {r}")
+        compared += 1
+    assert compared == len(net)
 
 
 @pytest.mark.parametrize("weighted", [False, True])
@@ -78,16 +99,12 @@ def test_batch_edges_labelled_when_lanes_cross_samples(mh, weighted):
         src, dst, w, sid = b.sample_edges(net, rep, seed=11, grid_blocks=grid)
         src, dst, sid = src.cpu().numpy(), dst.cpu().numpy(), sid.cpu().numpy()
         w = None if w is None else w.cpu().numpy()
+        compared = 0
         for s, (i, r) in enumerate(zip(net, rep)):
-            sel = sid == s
             ora = oracle.sample_mh(xs[i], ys[i] if weighted else None, seed=11, replica=r, seg_work=4)
-            if len(ora.tie_rows):
-                continue
-            kg, wg = _keys(src[sel], dst[sel], sizes[i], None if w is None else w[sel])
-            ko, wo = _keys(ora.src, ora.dst, sizes[i], ora.w if weighted else None)
-            assert np.array_equal(kg, ko), (grid, s)
-            if weighted:
-                assert np.array_equal(wg, wo), (grid, s)
+            _compare_sample(src, dst, w, sid == s, ora, sizes[i], f"grid {grid} sample {s}")
+            compared += 1
+        assert compared == len(net)
 
 
 def test_batch_weighted_edges_match_oracle(mh):
@@ -97,14 +114,12 @@ def test_batch_weighted_edges_match_oracle(mh):
     net, rep = [0, 1, 2, 1], [0, 0, 3, 7]
     src, dst, w, sid = b.sample_edges(net, rep, seed=3)
     src, dst, w, sid = (t.cpu().numpy() for t in (src, dst, w, sid))
+    compared = 0
     for s, (i, r) in enumerate(zip(net, rep)):
-        sel = sid == s
         ora = oracle.sample_mh(xs[i], ys[i], seed=3, replica=r, seg_work=4)
-        if len(ora.tie_rows):
-            continue
-        kg, wg = _keys(src[sel], dst[sel], sizes[i], w[sel])
-        ko, wo = _keys(ora.src, ora.dst, sizes[i], ora.w)
-        assert np.array_equal(kg, ko) and np.array_equal(wg, wo)
+        _compare_sample(src, dst, w, sid == s, ora, sizes[i], f"weighted batch sample {s}")
+        compared += 1
+    assert compared == len(net)
 
 
 def test_batch_degrees_match_oracle(mh):
@@ -116,9 +131,7 @@ def test_batch_degrees_match_oracle(mh):
     deg = deg.cpu().numpy()
     for s, (i, r) in enumerate(zip(net, rep)):
         ora = oracle.sample_mh(xs[i], None, seed=5, replica=r, seg_work=16)
-        ref = np.bincount(ora.src, minlength=sizes[i]) + np.bincount(ora.dst, minlength=sizes[i])
-        if len(ora.tie_rows) == 0:
-            assert np.array_equal(deg[off[s]:off[s + 1]], ref)
+        _compare_degrees(deg[off[s]:off[s + 1]], ora, sizes[i], f"degree sink sample {s}")
 
 
 def test_graph_replays_match_eager(mh):
@@ -171,8 +184,8 @@ def test_autotune_then_parity(mh):
     assert best["seg_work"] in (4, 16, 64) and best["ms"] > 0
     src, dst, _, sid = b.sample_edges([2], [4], seed=8)
     ora = oracle.sample_mh(xs[2], None, seed=8, replica=4, seg_work=best["seg_work"])
-    if len(ora.tie_rows) == 0:
-        assert np.array_equal(_keys(src.cpu().numpy(), dst.cpu().numpy(), 4000)[0], _keys(ora.src, ora.dst, 4000)[0])
+    src, dst = src.cpu().numpy(), dst.cpu().numpy()
+    _compare_sample(src, dst, None, np.ones(len(src), bool), ora, 4000, "autotuned batch")
 
 
 def test_bad_network_index(mh):
@@ -180,3 +193,34 @@ def test_bad_network_index(mh):
     b = mh.Batch([dev(xs[0])], max_samples=4)
     with pytest.raises(mh.MHError):
         b.sample_degrees([3], [0])
+    # the error belongs to that call: the next call on the batch succeeds
+    deg, off = b.sample_degrees([0], [0], seed=2)
+    ora = oracle.sample_mh(xs[0], None, seed=2, replica=0, seg_work=mh.DEFAULT_SEG_WORK)
+    _compare_degrees(deg.cpu().numpy(), ora, 100, "after a failed call")
+
+
+def test_batch_largest_ensemble_networks_match_oracle(mh):
+    # the three largest networks of the 256-network ensemble (N near 2e5,
+    # x = exp(Normal(-5, 2)), ~3e7 edges a sample) at the segment length the
+    # ensemble's autotuner picks on the bench (32), default grid: every sample
+    # edge for edge, and its degree-sink sequence
+    import workloads
+
+    nets = workloads.cfg4_networks(seed=4)
+    big = sorted(range(len(nets)), key=lambda i: -len(nets[i].x))[:3]
+    xs = [nets[i].x for i in big]
+    assert min(len(x) for x in xs) >= 100_000
+    b = mh.Batch([dev(x) for x in xs], seg_work=32, max_samples=8)
+    net, rep = [0, 1, 2], [0, 7, 15]
+    ora = [oracle.sample_mh(xs[i], None, seed=1, replica=r, seg_work=32, capacity=40_000_000)
+           for i, r in zip(net, rep)]
+    cap = sum(o.n_edges for o in ora) + (1 << 20)
+    src, dst, _, sid = b.sample_edges(net, rep, seed=1, capacity=cap)
+    src, dst, sid = src.cpu().numpy(), dst.cpu().numpy(), sid.cpu().numpy()
+    for s, (i, r) in enumerate(zip(net, rep)):
+        _compare_sample(src, dst, None, sid == s, ora[s], len(xs[i]), f"ensemble network {big[i]} replica {r}")
+    del src, dst, sid
+    deg, off = b.sample_degrees(net, rep, seed=1)
+    deg = deg.cpu().numpy()
+    for s, (i, r) in enumerate(zip(net, rep)):
+        _compare_degrees(deg[off[s]:off[s + 1]], ora[s], len(xs[i]), f"ensemble degrees {big[i]} replica {r}")

@@ -1,11 +1,12 @@
 """GPU parity of the bipartite / directed sampler (Sec. 2.6) against the CPU
-oracle, through the C-ABI.  Same bar as the one-set sampler: identical edge
-multisets (and weights) outside the rows of the oracle's near-tie trace, and
-identical counters when the trace is empty."""
+oracle, through the C-ABI.  Same bar as the one-set sampler (tests/parity.py):
+identical edge lists and weights but for counted divergences in the rows of the
+oracle's near-tie trace, and identical counters when the trace is empty."""
 import numpy as np
 import pytest
 
 import oracle
+import parity
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -35,30 +36,15 @@ def keys(src, dst, nc, w=None):
     return k[o], np.asarray(w)[o]
 
 
-def compare(res, ora, nc, weighted=False):
+def compare(res, ora, nc, weighted=False, label="bipartite"):
     gs, gd = res.src.cpu().numpy(), res.dst.cpu().numpy()
     gw = res.w.cpu().numpy() if weighted else None
-    os_, od, ow = ora.src, ora.dst, ora.w
-    excluded = 0
-    if len(ora.tie_rows):
-        bad = np.isin(gs, ora.tie_rows)
-        bado = np.isin(os_, ora.tie_rows)
-        excluded = int(bado.sum())
-        gs, gd = gs[~bad], gd[~bad]
-        os_, od = os_[~bado], od[~bado]
-        if weighted:
-            gw, ow = gw[~bad], ow[~bado]
-    kg, wg = keys(gs, gd, nc, gw)
-    ko, wo = keys(os_, od, nc, ow)
-    assert len(kg) == len(ko), (len(kg), len(ko))
-    assert np.array_equal(kg, ko)
-    if weighted:
-        assert np.array_equal(wg, wo)
-    assert excluded <= max(1, (len(ko) + excluded) // 10_000_000) * 64
+    n_div = parity.edge_divergences(gs, gd, gw, ora.src, ora.dst, ora.w if weighted else None, nc, ora.tie_rows,
+                                    label=label)
     if len(ora.tie_rows) == 0 and res.stats is not None:
         for k in ("steps", "proposals", "accepts", "segments", "saturated_w"):
             assert res.stats[k] == ora.stats[k], k
-    return excluded
+    return n_div
 
 
 def run(mh, xr, xc, yr=None, yc=None, exclude_self=False, seed=1, replica=0, seg_work=16, **kw):

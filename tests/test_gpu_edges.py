@@ -71,3 +71,24 @@ def test_hub_beyond_lds_and_ragged_sizes(mh):
         a = rng.integers(0, 1 << 31, m, dtype=np.int64)
         b = rng.integers(0, 1 << 31, m, dtype=np.int64)
         check(mh, a, b, rng.integers(1, 1000, m))
+
+
+def test_runs_of_every_length_up_to_the_wave_limit(mh):
+    # sources with 2 to 300 edges each (every length from 2 to 300 several
+    # times, in random order): runs up to 64 are sorted by a wave over its
+    # lanes, up to 128 and 256 by a wave's register network, longer ones by the
+    # block; destinations drawn so that some runs hold equal high bytes
+    rng = np.random.default_rng(6)
+    lens = np.concatenate([np.arange(2, 301)] * 6)
+    rng.shuffle(lens)
+    src = np.repeat(np.arange(len(lens)) * 3 + 11, lens)
+    dst = np.concatenate([rng.choice(1 << int(rng.integers(9, 31)), size=L, replace=False) for L in lens])
+    p = rng.permutation(src.size)
+    check(mh, src[p], dst[p])
+    # already ordered within runs except for one swapped pair
+    src2, dst2 = src.copy(), np.concatenate([np.sort(rng.choice(1 << 20, size=L, replace=False)) for L in lens])
+    off = np.concatenate([[0], np.cumsum(lens)])
+    for r in range(0, len(lens), 7):
+        i = off[r] + int(rng.integers(0, lens[r] - 1))
+        dst2[i], dst2[i + 1] = dst2[i + 1], dst2[i]
+    check(mh, src2, dst2)

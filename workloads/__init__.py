@@ -12,6 +12,7 @@ generator is a pure function of its arguments.
 from __future__ import annotations
 
 import hashlib
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -23,6 +24,7 @@ __all__ = [
     "uecm_recipe",
     "cfg1_small",
     "cfg2_degrees",
+    "cfg2_fitted_x",
     "cfg3_targets",
     "cfg4_networks",
     "cfg5_targets",
@@ -104,6 +106,30 @@ def cfg2_degrees(seed: int = 2, n: int = 1_000_000) -> np.ndarray:
     """Target degrees for the N = 1M unweighted case: power law 2.1 on [1, 10^4]."""
     rng = np.random.default_rng(seed)
     return powerlaw_degrees(rng, n, 2.1, 1, 10_000)
+
+
+FITTED_X_CFG2 = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
+                             "ubcm_fit_n1e6.txt")
+
+
+def cfg2_fitted_x(path: str = FITTED_X_CFG2) -> np.ndarray:
+    """x for the N = 1M targets of cfg2_degrees(), one value per degree class,
+    read from the stored CPU fit (tests/golden/make_fitted_x.py writes it):
+    every node takes its class's value.  The class sizes are checked against
+    the draw."""
+    k = cfg2_degrees()
+    table = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            deg, cnt, xh = line.split()
+            table[int(deg)] = (int(cnt), float.fromhex(xh))
+    kc, cnt = np.unique(k, return_counts=True)
+    if len(kc) != len(table) or any(table.get(int(a), (-1,))[0] != int(b) for a, b in zip(kc, cnt)):
+        raise ValueError(f"{path} does not match the degree classes of cfg2_degrees()")
+    xc = np.array([table[int(a)][1] for a in kc], dtype=np.float64)
+    return xc[np.searchsorted(kc, k)]
 
 
 def cfg3_targets(seed: int = 3, n: int = 200_000) -> tuple[np.ndarray, np.ndarray]:
