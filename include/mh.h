@@ -13,7 +13,8 @@
  *     memory) usable on `stream`; *_host pointers are host memory.
  *   - The caller owns every buffer, including the workspace; the library
  *     allocates no memory.  Its only state: per-device facts it caches (the
- *     number of CUs, kernels' occupancy).
+ *     number of CUs, kernels' occupancy) and the scratch array of
+ *     mh_sample_unweighted_noalloc.
  *   - Concurrency: the order step of a network of at most 256 tiles of 4096
  *     nodes (and no more tiles than the GPU has CUs: n <= 1,048,576 on an
  *     MI355X) exchanges digit counts between all of its tiles, which must be
@@ -142,6 +143,27 @@ mh_status mh_sample_weighted_async(const double* x, const double* y, int64_t n, 
  * invalid parameters or a stalled step. */
 mh_status mh_sample_result(const void* workspace, size_t ws_bytes, int64_t capacity,
                            int64_t* n_edges_host, hipStream_t stream);
+
+/* Allocation-free sampler, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): mh_sample_unweighted without the workspace argument.  Its
+ * scratch is a device array of the library itself, MH_NOALLOC_SCRATCH_BYTES
+ * on each GPU the library runs on, held until the process ends; the call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * The caller still owns x and the outputs.
+ *   n <= MH_NOALLOC_MAX_NODES (else MH_EINVAL); a plan whose workspace would
+ *   exceed the scratch returns MH_EWORKSPACE (never at n <= MH_NOALLOC_MAX_NODES).
+ * Every call on a GPU uses that GPU's one scratch array, which keeps the
+ * last call's contents (each call clears what must start at zero), so calls
+ * that overlap on one GPU (other host threads, other streams) race: callers
+ * serialise them.  Otherwise as mh_sample_unweighted: synchronous, same
+ * edges, same statistics. */
+#define MH_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define MH_NOALLOC_MAX_NODES 262144
+mh_status mh_sample_unweighted_noalloc(const double* x, int64_t n, uint64_t seed, uint32_t replica,
+                                       const mh_plan_params* plan, int32_t* src, int32_t* dst,
+                                       int64_t capacity, int64_t* n_edges_host, mh_stats* stats_host,
+                                       hipStream_t stream);
 
 /* Two node sets: bipartite and directed networks (Sec. 2.6).  Rows are the
  * "+" set (x_rows, y_rows, n_rows), columns the "-" set (x_cols, y_cols,

@@ -79,6 +79,8 @@ def lib() -> ctypes.CDLL:
         "mh_sample_weighted_async": ([vp, vp, i64, u64, u32, P(PlanParams), vp, vp, vp, i64, vp, sz, vp],
                                      ctypes.c_int),
         "mh_sample_result": ([vp, sz, i64, P(i64), vp], ctypes.c_int),
+        "mh_sample_unweighted_noalloc": ([vp, i64, u64, u32, P(PlanParams), vp, vp, i64, P(i64), P(Stats), vp],
+                                         ctypes.c_int),
         "mh_bipartite_workspace_bytes": ([i64, i64, ctypes.c_int, P(PlanParams)], sz),
         "mh_sample_bipartite": ([vp, vp, i64, vp, vp, i64, u32, u64, u32, P(PlanParams), vp, vp, vp, i64, P(i64), vp,
                                  sz, P(Stats), vp], ctypes.c_int),
@@ -234,6 +236,29 @@ def sample_async(x: torch.Tensor, y: torch.Tensor | None, out, workspace: torch.
                                             _ptr(dst), _ptr(w), cap, _ptr(workspace), workspace.numel(), stream)
     _check(status, "mh_sample_async")
     return cap
+
+
+NOALLOC_MAX_NODES = 262144  # MH_NOALLOC_MAX_NODES
+
+
+def sample_unweighted_noalloc(x: torch.Tensor, out, seed: int = 1, replica: int = 0,
+                              seg_work: int = DEFAULT_SEG_WORK, stats: bool = False, grid_blocks: int = 0):
+    """mh_sample_unweighted_noalloc: one unweighted sample into the caller's
+    ``out = (src, dst)`` with the library's own scratch (no workspace, no
+    allocation in the call; n <= NOALLOC_MAX_NODES).  Returns (src, dst) views
+    of the edges (and a stats dict when stats=True); MH_ECAPACITY raises."""
+    x = _dev_f64(x, "x")
+    src, dst = out
+    cap = min(src.numel(), dst.numel())
+    plan = PlanParams(int(seg_work), 0, int(grid_blocks), 0, None)
+    nedge = ctypes.c_int64(0)
+    st = Stats()
+    _check(lib().mh_sample_unweighted_noalloc(_ptr(x), x.numel(), seed, replica, ctypes.byref(plan), _ptr(src),
+                                              _ptr(dst), cap, ctypes.byref(nedge),
+                                              ctypes.byref(st) if stats else None, _stream(x.device)),
+           "mh_sample_unweighted_noalloc")
+    m = int(nedge.value)
+    return (src[:m], dst[:m], st.as_dict()) if stats else (src[:m], dst[:m])
 
 
 def sample_result(workspace: torch.Tensor, capacity: int) -> int:

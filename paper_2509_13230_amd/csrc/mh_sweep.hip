@@ -1,6 +1,8 @@
 // Single-sample entry points: node order, bound, plan of row segments, and
 // the per-segment rejection sweep (Sec. 2.3-2.5, Alg. 1; the sweep itself is
 // in mh_sweep_core.hpp).
+#include <mutex>
+
 #include "mh_common.hpp"
 #include "mh_internal.hpp"
 #include "mh_lookback.hpp"
@@ -650,6 +652,33 @@ mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed
     return read_counters(static_cast<const Counters*>(workspace), capacity, n_edges_host, stats_host, stream);
 }
 
+// ---- the allocation-free sampler's scratch ----
+// Device memory of the library itself for callers that cannot allocate: one
+// copy per GPU, held from the library's load on that GPU until the process
+// ends.  Host code never passes `scratch` itself to a kernel (in host code
+// the name stands for a host-side shadow): it takes each device's address of
+// the array once, with that device current, and uses that address.
+__device__ __align__(256) unsigned char scratch[MH_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kScratchDevices];  // the array's address on each device, once taken
+
+mh_status device_scratch(void** out) {
+    int dev = -1;
+    MH_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) return MH_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return MH_EHIP;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return MH_OK;
+}
+
 }  // namespace
 
 // ---- plan counts entry (also used by the C-ABI) ----
@@ -948,6 +977,22 @@ mh_status mh_sample_weighted(const double* x, const double* y, int64_t n, uint64
     }
     return mh::sample_impl(x, y, n, seed, replica, plan, src, dst, w, capacity, n_edges_host, workspace, ws_bytes,
                            stats_host, stream);
+}
+
+mh_status mh_sample_unweighted_noalloc(const double* x, int64_t n, uint64_t seed, uint32_t replica,
+                                       const mh_plan_params* plan, int32_t* src, int32_t* dst, int64_t capacity,
+                                       int64_t* n_edges_host, mh_stats* stats_host, hipStream_t stream) {
+    if (!n_edges_host) return MH_EINVAL;
+    *n_edges_host = 0;
+    if (stats_host) *stats_host = mh_stats{0, 0, 0, 0, 0, 0};
+    if (n < 0 || n > MH_NOALLOC_MAX_NODES) return MH_EINVAL;
+    const int32_t T = plan ? plan->seg_work : mh::kDefaultSegWork;
+    if (T < 0 || mh::sample_workspace_bytes(n, false, T) > (size_t)MH_NOALLOC_SCRATCH_BYTES) return MH_EWORKSPACE;
+    void* ws = nullptr;
+    const mh_status st = mh::device_scratch(&ws);
+    if (st != MH_OK) return st;
+    return mh::sample_impl(x, nullptr, n, seed, replica, plan, src, dst, nullptr, capacity, n_edges_host, ws,
+                           (size_t)MH_NOALLOC_SCRATCH_BYTES, stats_host, stream);
 }
 
 mh_status mh_sample_unweighted_async(const double* x, int64_t n, uint64_t seed, uint32_t replica,
