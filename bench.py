@@ -436,6 +436,118 @@ def bipartite_bench(args, dev) -> dict:
     }
 
 
+def chung_lu_bench(args, dev) -> dict:
+    """The Chung-Lu comparison model (Sec. 2.1, 2.3) and its bias.
+
+    Speed: the Chung-Lu sampler on the N = 1M degrees (w = k / sqrt(2M)),
+    samples back to back; the rank-count sink and the triangle count of those
+    samples.  Bias (Fig. 1): a Holme-Kim network (5,000 nodes, m = 10, triad
+    probability 0.1) gives the degrees; R samples of the Chung-Lu model and of
+    the unbiased model fitted to the same degrees (device fit) are reduced to
+    the density of edges among the top alpha of nodes and to triangle counts."""
+    import torch
+
+    import paper_2509_13230_amd as mh
+    import workloads
+    from paper_2509_13230_amd.fit import fit_ubcm
+
+    k = workloads.cfg2_degrees(seed=2, n=args.n).astype(np.float64)
+    w = torch.as_tensor(k / np.sqrt(k.sum()), device=dev)
+    n = w.numel()
+    L = mh.lib()
+    plan = mh.PlanParams(args.seg_work, 0, 0, 0, None)
+    ws = torch.empty(L.mh_workspace_bytes(n, 0, ctypes.byref(plan)), dtype=torch.uint8, device=dev)
+    s0, _ = mh.sample_chung_lu(w, seed=args.seed, replica=0, seg_work=args.seg_work, workspace=ws)
+    cap = int(s0.numel() * 1.1) + 65536
+    out = (torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev))
+    reps = 10
+    for r in range(2):
+        mh.sample_chung_lu(w, seed=args.seed, replica=r, seg_work=args.seg_work, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    edges = 0
+    for r in range(reps):
+        s_, _ = mh.sample_chung_lu(w, seed=args.seed, replica=2000 + r, seg_work=args.seg_work, out=out, workspace=ws)
+        edges += s_.numel()
+    torch.cuda.synchronize()
+    t_cl = (time.perf_counter() - t0) / reps
+    cnt = torch.empty(n, dtype=torch.int32, device=dev)
+    t0 = time.perf_counter()
+    for r in range(reps):
+        mh.rank_counts(w, model=mh.MH_MODEL_CHUNG_LU, seed=args.seed, replica=2000 + r, seg_work=args.seg_work,
+                       out=cnt, workspace=ws)
+    torch.cuda.synchronize()
+    t_rank = (time.perf_counter() - t0) / reps
+    s_, d_ = mh.sample_chung_lu(w, seed=args.seed, replica=2000, seg_work=args.seg_work, out=out, workspace=ws)
+    tws = torch.empty(L.mh_triangles_workspace_bytes(n, s_.numel()), dtype=torch.uint8, device=dev)
+    mh.count_triangles(s_, d_, n, workspace=tws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tri_big = mh.count_triangles(s_, d_, n, workspace=tws)
+    t_tri = time.perf_counter() - t0
+
+    # the bias on Holme-Kim degrees
+    hs, hd = workloads.holme_kim()
+    hn = 5000
+    hk = (np.bincount(hs, minlength=hn) + np.bincount(hd, minlength=hn)).astype(np.float64)
+    hw = torch.as_tensor(hk / np.sqrt(hk.sum()), device=dev)
+    fit = fit_ubcm(hk, tol=1e-10)
+    hx = torch.as_tensor(fit.x, device=dev)
+    order = np.argsort(-hk, kind="stable")
+    alphas = [0.005, 0.01, 0.02, 0.05, 0.1]
+    sizes = [max(2, int(round(a * hn))) for a in alphas]
+
+    def density(c_np):
+        cs = np.cumsum(c_np)
+        return [float(cs[K - 1]) / (K * (K - 1) / 2) for K in sizes]
+
+    rank_hk = np.empty(hn, dtype=np.int64)
+    rank_hk[order] = np.arange(hn)
+    hk_hi = np.maximum(rank_hk[hs], rank_hk[hd])
+    hk_counts = np.bincount(hk_hi, minlength=hn)
+    R = args.bias_replicas
+    stats = {}
+    hws = torch.empty(L.mh_workspace_bytes(hn, 0, ctypes.byref(plan)), dtype=torch.uint8, device=dev)
+    htw = torch.empty(L.mh_triangles_workspace_bytes(hn, 4 * len(hs)), dtype=torch.uint8, device=dev)
+    for name, par, model, sampler in (("chung_lu", hw, mh.MH_MODEL_CHUNG_LU, mh.sample_chung_lu),
+                                      ("ubcm", hx, mh.MH_MODEL_UBCM, mh.sample_unweighted)):
+        dens, tris, ms = [], [], []
+        for r in range(R):
+            c, m_ = mh.rank_counts(par, model=model, seed=args.seed, replica=r, seg_work=args.seg_work, workspace=hws)
+            dens.append(density(c.cpu().numpy()))
+            src_, dst_ = sampler(par, seed=args.seed, replica=r, seg_work=args.seg_work, workspace=hws)
+            tris.append(mh.count_triangles(src_, dst_, hn, workspace=htw))
+            ms.append(m_)
+        dens = np.array(dens)
+        stats[name] = {"rich_club_density": {f"{a:g}": [float(dens[:, i].mean()), float(dens[:, i].std())]
+                                             for i, a in enumerate(alphas)},
+                       "triangles": [float(np.mean(tris)), float(np.std(tris))],
+                       "edges": [float(np.mean(ms)), float(np.std(ms))]}
+    return {
+        "workload": f"Chung-Lu model on the N={n} power-law degrees (w = k / sqrt(2M)); samples through the "
+                    "synchronous call",
+        "ms_per_sample": t_cl * 1e3,
+        "edges_per_s": edges / reps / t_cl,
+        "mean_edges_per_sample": edges / reps,
+        "ms_per_rank_count_sample": t_rank * 1e3,
+        "ms_triangle_count": t_tri * 1e3,
+        "triangles_one_sample": tri_big,
+        "bias": {"network": "Holme-Kim, 5000 nodes, m = 10, triad probability 0.1 (seeded)",
+                 "replicas": R, "ubcm_fit_residual": fit.residual,
+                 "holme_kim": {"rich_club_density": {f"{a:g}": v for a, v in zip(alphas, density(hk_counts))},
+                               "triangles": hk_triangles(mh, hs, hd, hn, dev), "edges": int(len(hs))},
+                 **stats,
+                 "reading": "[mean, sd] over the replicas; rich-club density = edges among the top alpha of nodes "
+                            "by degree / pairs among them"},
+    }
+
+
+def hk_triangles(mh, s, d, n, dev) -> int:
+    import torch
+
+    return mh.count_triangles(torch.as_tensor(s, device=dev), torch.as_tensor(d, device=dev), n)
+
+
 def atomic_add_rate(dev, slots: int = 1 << 22, blocks: int = 2048, iters: int = 256) -> float:
     """Random int32 atomic adds per second on this GPU, from the probe library
     (libmh_probe.so): blocks x 256 lanes, each adding 1 to `iters` random
@@ -648,6 +760,8 @@ def main():
     ap.add_argument("--bip-seg-work", type=int, default=8, help="seg_work of the two-set measurement")
     ap.add_argument("--accuracy-replicas", type=int, default=64,
                     help="replicas of the degree-accuracy comparison of MH and brute force")
+    ap.add_argument("--bias-replicas", type=int, default=100,
+                    help="replicas of the Chung-Lu bias statistics (0: skip the Chung-Lu measurement)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -797,6 +911,8 @@ def main():
         out["weighted"] = weighted_bench(args, dev)
     if args.bip_rows > 0:
         out["bipartite"] = bipartite_bench(args, dev)
+    if args.bias_replicas > 0:
+        out["chung_lu"] = chung_lu_bench(args, dev)
     if args.deg_n > 0:
         out["expected_degree"] = expected_degree_bench(args, dev)
     if not args.no_cpu_baseline:

@@ -331,6 +331,48 @@ size_t mh_sort_edges_workspace_bytes(int64_t n_edges);
 mh_status mh_sort_edges(int32_t* src, int32_t* dst, int32_t* w, int64_t n_edges, void* workspace,
                         size_t ws_bytes, hipStream_t stream);
 
+/* ---- The Chung-Lu comparison model and the statistics of its bias ----
+ * The Chung-Lu model read as edge probabilities, p_ij = min(w_i w_j, 1) with
+ * w_i = k_i / sqrt(2M) (Sec. 2.1), is what the Miller-Hagberg algorithm samples
+ * (Sec. 2.3); the paper contrasts it with the unbiased model on the density of
+ * edges among the largest-degree nodes (Fig. 1A) and on triangle counts
+ * (Fig. 1B). */
+#define MH_MODEL_UBCM 0
+#define MH_MODEL_CHUNG_LU 1
+
+/* One Chung-Lu sample: as mh_sample_unweighted with w in place of x (device
+ * float64 [n], finite, >= 0, (max w)^2 finite) and the chain of Sec. 2.3:
+ * proposal q = min(t_q, 1), skip L = floor(-log U1 / -log1p(-t_q)) (0 when
+ * t_q >= 1), accept iff U2 q < min(t, 1).  Same order, plan, counters,
+ * workspace (mh_workspace_bytes(n, 0, plan)) and errors. */
+mh_status mh_sample_chung_lu(const double* w, int64_t n, uint64_t seed, uint32_t replica,
+                             const mh_plan_params* plan, int32_t* src, int32_t* dst, int64_t capacity,
+                             int64_t* n_edges_host, void* workspace, size_t ws_bytes, mh_stats* stats_host,
+                             hipStream_t stream);
+
+/* One unweighted sample (model MH_MODEL_UBCM: x as mh_sample_unweighted;
+ * MH_MODEL_CHUNG_LU: x as w above) reduced in the sweep to counts by rank, no
+ * edge list: rank_counts[j] (device int32 [n], cleared by the call) = number
+ * of edges whose endpoint of larger rank has rank j, ranks being positions in
+ * the node order (descending x, ties by ascending id; mh_order gives it).  The
+ * edges among the K nodes of largest x number rank_counts[0] + ... +
+ * rank_counts[K-1], the numerator of the rich-club density of Fig. 1A.
+ * *n_edges_host = the sample's edge count.  Same sample as the edge-list call
+ * with the same arguments.  Synchronous; workspace mh_workspace_bytes(n, 0, plan). */
+mh_status mh_sample_rank_counts(const double* x, int64_t n, int32_t model, uint64_t seed, uint32_t replica,
+                                const mh_plan_params* plan, int32_t* rank_counts, int64_t* n_edges_host,
+                                void* workspace, size_t ws_bytes, mh_stats* stats_host, hipStream_t stream);
+
+/* Number of triangles of a simple undirected graph: src, dst device int32
+ * [n_edges], each edge once in either orientation, ids in [0, n), no loops
+ * (MH_EINVAL otherwise; a pair listed twice is counted as two edges).  Each
+ * triangle is counted once, at its two smallest ids.  *triangles_host
+ * receives the count.  Synchronous; workspace mh_triangles_workspace_bytes(n,
+ * n_edges) bytes (about 40 bytes per edge and 8 per node), owned by the caller. */
+size_t mh_triangles_workspace_bytes(int64_t n, int64_t n_edges);
+mh_status mh_count_triangles(const int32_t* src, const int32_t* dst, int64_t n_edges, int64_t n,
+                             uint64_t* triangles_host, void* workspace, size_t ws_bytes, hipStream_t stream);
+
 const char* mh_status_string(mh_status s);
 
 #ifdef __cplusplus

@@ -95,6 +95,12 @@ def lib() -> ctypes.CDLL:
         "mh_expected_degree_bwd": ([vp, vp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "mh_sort_edges_workspace_bytes": ([i64], sz),
         "mh_sort_edges": ([vp, vp, vp, i64, vp, sz, vp], ctypes.c_int),
+        "mh_sample_chung_lu": ([vp, i64, u64, u32, P(PlanParams), vp, vp, i64, P(i64), vp, sz, P(Stats), vp],
+                               ctypes.c_int),
+        "mh_sample_rank_counts": ([vp, i64, i32, u64, u32, P(PlanParams), vp, P(i64), vp, sz, P(Stats), vp],
+                                  ctypes.c_int),
+        "mh_triangles_workspace_bytes": ([i64, i64], sz),
+        "mh_count_triangles": ([vp, vp, i64, i64, P(u64), vp, sz, vp], ctypes.c_int),
         "mh_status_string": ([ctypes.c_int], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -145,7 +151,12 @@ class SampleResult:
     stats: dict | None
 
 
-def _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stage_events=None, grid_blocks=0):
+MH_MODEL_UBCM = 0
+MH_MODEL_CHUNG_LU = 1
+
+
+def _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stage_events=None, grid_blocks=0,
+            chung_lu=False):
     x = _dev_f64(x, "x")
     if y is not None:
         y = _dev_f64(y, "y")
@@ -172,7 +183,10 @@ def _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stag
             dst = torch.empty(cap, dtype=torch.int32, device=dev)
             w = torch.empty(cap, dtype=torch.int32, device=dev) if y is not None else None
         sp = ctypes.byref(st) if stats else None
-        if y is None:
+        if chung_lu:
+            status = L.mh_sample_chung_lu(_ptr(x), n, seed, replica, ctypes.byref(plan), _ptr(src), _ptr(dst), cap,
+                                          ctypes.byref(nedge), _ptr(ws), ws.numel(), sp, _stream(dev))
+        elif y is None:
             status = L.mh_sample_unweighted(_ptr(x), n, seed, replica, ctypes.byref(plan), _ptr(src), _ptr(dst), cap,
                                             ctypes.byref(nedge), _ptr(ws), ws.numel(), sp, _stream(dev))
         else:
@@ -182,7 +196,8 @@ def _sample(x, y, seed, replica, seg_work, capacity, stats, out, workspace, stag
             cap = int(nedge.value)
             src = None
             continue
-        _check(status, "mh_sample_weighted" if y is not None else "mh_sample_unweighted")
+        _check(status, "mh_sample_chung_lu" if chung_lu else
+               "mh_sample_weighted" if y is not None else "mh_sample_unweighted")
         break
     m = int(nedge.value)
     return SampleResult(src[:m], dst[:m], None if w is None else w[:m], st.as_dict() if stats else None)
@@ -197,6 +212,52 @@ def sample_unweighted(x: torch.Tensor, seed: int = 1, replica: int = 0, seg_work
     address of an array of 4 hipEvent_t recorded at the stage boundaries."""
     r = _sample(x, None, seed, replica, seg_work, capacity, stats, out, workspace, stage_events, grid_blocks)
     return (r.src, r.dst, r.stats) if stats else (r.src, r.dst)
+
+
+def sample_chung_lu(w: torch.Tensor, seed: int = 1, replica: int = 0, seg_work: int = DEFAULT_SEG_WORK,
+                    capacity: int | None = None, stats: bool = False, out=None, workspace=None,
+                    stage_events=None, grid_blocks: int = 0):
+    """One sample of the Chung-Lu model read as probabilities, p = min(w_i w_j, 1)
+    (Sec. 2.1), by the Miller-Hagberg chain (Sec. 2.3): (src, dst[, stats])."""
+    r = _sample(w, None, seed, replica, seg_work, capacity, stats, out, workspace, stage_events, grid_blocks,
+                chung_lu=True)
+    return (r.src, r.dst, r.stats) if stats else (r.src, r.dst)
+
+
+def rank_counts(x: torch.Tensor, model: int = MH_MODEL_UBCM, seed: int = 1, replica: int = 0,
+                seg_work: int = DEFAULT_SEG_WORK, out: torch.Tensor | None = None, workspace=None,
+                stats: bool = False):
+    """One unweighted sample (UBCM, or Chung-Lu with model=MH_MODEL_CHUNG_LU)
+    reduced to counts by rank: counts[j] = edges whose endpoint of larger rank
+    (in the node order) has rank j.  Returns (counts int32[n], n_edges[, stats])."""
+    x = _dev_f64(x, "x")
+    n = x.numel()
+    L = lib()
+    plan = PlanParams(int(seg_work), 0, 0, 0, None)
+    wsb = L.mh_workspace_bytes(n, 0, ctypes.byref(plan))
+    ws = workspace if workspace is not None and workspace.numel() >= wsb else _workspace(wsb, x.device)
+    cnt = out if out is not None else torch.empty(max(n, 1), dtype=torch.int32, device=x.device)
+    nedge = ctypes.c_int64(0)
+    st = Stats()
+    _check(L.mh_sample_rank_counts(_ptr(x), n, int(model), seed, replica, ctypes.byref(plan), _ptr(cnt),
+                                   ctypes.byref(nedge), _ptr(ws), ws.numel(), ctypes.byref(st) if stats else None,
+                                   _stream(x.device)), "mh_sample_rank_counts")
+    return (cnt[:n], int(nedge.value), st.as_dict()) if stats else (cnt[:n], int(nedge.value))
+
+
+def count_triangles(src: torch.Tensor, dst: torch.Tensor, n: int, workspace=None) -> int:
+    """Triangles of the simple undirected graph with these edges (each once)."""
+    if src.dtype != torch.int32 or dst.dtype != torch.int32 or not src.is_cuda or src.numel() != dst.numel():
+        raise ValueError("src and dst must be CUDA int32 tensors of equal length")
+    src, dst = src.contiguous(), dst.contiguous()
+    L = lib()
+    m = src.numel()
+    wsb = L.mh_triangles_workspace_bytes(int(n), m)
+    ws = workspace if workspace is not None and workspace.numel() >= wsb else _workspace(wsb, src.device)
+    tri = ctypes.c_uint64(0)
+    _check(L.mh_count_triangles(_ptr(src), _ptr(dst), m, int(n), ctypes.byref(tri), _ptr(ws), ws.numel(),
+                                _stream(src.device)), "mh_count_triangles")
+    return int(tri.value)
 
 
 def sample_weighted(x: torch.Tensor, y: torch.Tensor, seed: int = 1, replica: int = 0,

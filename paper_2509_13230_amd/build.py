@@ -39,7 +39,7 @@ HIPCC_FLAGS = [
 ]
 
 SOURCES = ["mh_scan.hip", "mh_sort.hip", "mh_order.hip", "mh_sweep.hip", "mh_bf.hip", "mh_degree.hip",
-           "mh_api.hip", "mh_batched.hip", "mh_edges.hip"]
+           "mh_api.hip", "mh_batched.hip", "mh_edges.hip", "mh_triangles.hip"]
 
 
 def hipcc() -> str:

@@ -46,10 +46,9 @@ constexpr uint64_t kFlagAggregate = 1ull << 32;
 constexpr uint64_t kFlagPrefix = 2ull << 32;
 constexpr uint32_t kSpinLimit = 1u << 20;
 constexpr int kLookWindow = 8;
-// Column exchange: a column of at most kXchgTiles tiles per 256 threads, so a
-// block scans kXchgCols digit columns at once.
+// Column exchange: at most kXchgTiles tiles (a digit column of the tiles'
+// counts is scanned by up to 256 threads).
 constexpr int kXchgTiles = 256;
-constexpr int kXchgCols = kSortThreads / kXchgTiles;
 // The counting kernel adds its block histograms into kHistCopies copies (block
 // b into copy b % kHistCopies); readers sum the copies.
 constexpr int kHistCopies = kRadixHistCopies;
@@ -212,17 +211,23 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
     uint32_t excl = 0;
     if (XCHG) {
         // Every tile is resident (at most kXchgTiles): instead of a chain of
-        // look-backs, block b scans the digit columns b, b + G, b + 2G, ...
-        // (G blocks; kXchgCols columns at once, 256 threads each, one tile per
-        // thread) over all tiles' published counts, and writes each tile the
-        // count of that digit in the tiles before it (flag 2 over the count
-        // word, which only this block reads) and, when the pass has no digit
-        // totals of its own, the column's total to dtot; then every tile reads
-        // its 256 words back.  Two round trips per pass when G >= 256 / kXchgCols.
+        // look-backs, the blocks scan the digit columns over all tiles'
+        // published counts, a column by tpc threads (one per tile, tpc the
+        // tile count rounded up to a power of two) and kSortThreads / tpc
+        // columns per block at once: block b takes columns b, b + G, b + 2G, ...
+        // (G blocks).  Each column's scan writes every tile the count of that
+        // digit in the tiles before it (flag 2 over the count word, which only
+        // this block reads) and, when the pass has no digit totals of its own,
+        // the column's total to dtot; then every tile reads its 256 words
+        // back.  Two round trips per pass, however few the tiles.
         const int nt = (int)gridDim.x;
-        const int tcol = threadIdx.x & (kXchgTiles - 1);  // this thread's tile in the column
-        for (int c0 = blockIdx.x; c0 < kRadix; c0 += kXchgCols * nt) {
-            const int col = c0 + (int)(threadIdx.x / kXchgTiles) * nt;
+        int tpc = 1;
+        while (tpc < nt) tpc <<= 1;
+        const int cpb = kSortThreads / tpc;      // columns per block at once
+        const int tcol = threadIdx.x & (tpc - 1);  // this thread's tile in the column
+        const int wpc = tpc > kWave ? tpc / kWave : 1;  // waves per column (tpc > 64)
+        for (int c0 = blockIdx.x; c0 < kRadix; c0 += cpb * nt) {
+            const int col = c0 + (int)(threadIdx.x / tpc) * nt;
             const bool mine = tcol < nt && col < kRadix;
             uint64_t* cw = status + (int64_t)tcol * kRadix + col;
             uint32_t c = 0;
@@ -241,20 +246,31 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
                     __builtin_amdgcn_s_sleep(1);
                 }
             }
-            // exclusive scan over each column's 256 threads (4 waves)
-            const uint32_t inc = wave_inclusive_scan(c);
-            if (lane == 63) s_scan[wave] = inc;
-            __syncthreads();
-            const int w0 = wave & ~(kXchgTiles / kWave - 1);
-            uint32_t before = inc - c;
-            for (int w = w0; w < wave; ++w) before += s_scan[w];
-            if (mine) __hip_atomic_store(cw, kFlagPrefix | before, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (FROMX && tcol == 0 && col < kRadix) {
-                uint32_t coltotal = 0;
-                for (int w = w0; w < w0 + kXchgTiles / kWave; ++w) coltotal += s_scan[w];
-                __hip_atomic_store(dtot + col, kFlagPrefix | coltotal, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t before, coltotal = 0;
+            if (tpc <= kWave) {
+                // inclusive scan within each group of tpc lanes
+                uint32_t inc = c;
+                for (int dd = 1; dd < tpc; dd <<= 1) {
+                    const uint32_t u = __shfl_up(inc, (unsigned)dd, tpc);
+                    if (tcol >= dd) inc += u;
+                }
+                before = inc - c;
+                if (FROMX) coltotal = __shfl(inc, lane | (tpc - 1), kWave);
+            } else {
+                // a column over wpc waves
+                const uint32_t inc = wave_inclusive_scan(c);
+                if (lane == 63) s_scan[wave] = inc;
+                __syncthreads();
+                const int w0 = wave & ~(wpc - 1);
+                before = inc - c;
+                for (int w = w0; w < wave; ++w) before += s_scan[w];
+                if (FROMX && tcol == 0)
+                    for (int w = w0; w < w0 + wpc; ++w) coltotal += s_scan[w];
             }
-            __syncthreads();
+            if (mine) __hip_atomic_store(cw, kFlagPrefix | before, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (FROMX && tcol == 0 && col < kRadix)
+                __hip_atomic_store(dtot + col, kFlagPrefix | coltotal, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tpc > kWave) __syncthreads();  // s_scan is rewritten by the next round
         }
         if (dig) {
             uint32_t spins = 0;

@@ -552,9 +552,9 @@ size_t sample_workspace_bytes(int64_t n, bool weighted, int32_t T) {
     return s.used + network_bytes(n, weighted, T) + prepare_scratch_bytes(n) + 512;
 }
 
-template <bool W, bool S, bool BIP = false>
+template <bool W, bool S, bool BIP = false, int OUT = OUT_EDGES, bool CL = false>
 void launch_sweep(const SweepLaunch& A, int64_t n, int32_t grid_blocks, hipStream_t stream) {
-    auto kern = k_sweep<W, S, false, OUT_EDGES, BIP>;
+    auto kern = k_sweep<W, S, false, OUT, BIP, CL>;
     int64_t want = (n + kWave - 1) / kWave;
     if (want < 16) want = 16;
     // Default: every block that fits at once (4 per CU unweighted, 3 weighted:
@@ -586,15 +586,27 @@ mh_status read_counters(const Counters* ctr, int64_t capacity, int64_t* n_edges_
     return MH_OK;
 }
 
+__global__ __launch_bounds__(kThreads) void k_zero_i32(int32_t* __restrict__ a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) a[i] = 0;
+}
+
 // Checks the arguments and enqueues a whole sample on `stream`; the counters
 // (edge count, status, statistics) are left at the start of the workspace.
+// chung_lu: the Chung-Lu chain (unweighted).  rank_cnt: counts by rank
+// instead of the edge list (src, dst, w unused; cleared here).
 mh_status enqueue_sample(const double* x, const double* y, int64_t n, uint64_t seed, uint32_t replica,
                          const mh_plan_params* plan, int32_t* src, int32_t* dst, int32_t* w, int64_t capacity,
-                         void* workspace, size_t ws_bytes, bool stats, hipStream_t stream) {
+                         void* workspace, size_t ws_bytes, bool stats, hipStream_t stream, bool chung_lu = false,
+                         int32_t* rank_cnt = nullptr) {
     const bool weighted = (y != nullptr);
     if (n < 0 || n > 0x7FFFFFFFll || capacity < 0) return MH_EINVAL;
     if (!x && n > 0) return MH_EINVAL;
-    if (capacity > 0 && (!src || !dst || (weighted && !w))) return MH_EINVAL;
+    if (chung_lu && weighted) return MH_EINVAL;
+    if (rank_cnt) {
+        if (weighted) return MH_EINVAL;
+    } else if (capacity > 0 && (!src || !dst || (weighted && !w))) {
+        return MH_EINVAL;
+    }
     const int32_t T = plan ? plan->seg_work : kDefaultSegWork;
     if (T < 0 || (plan && (plan->flags != 0 || plan->grid_blocks < 0))) return MH_EINVAL;
     if (!workspace || ws_bytes < sample_workspace_bytes(n, weighted, T)) return MH_EWORKSPACE;
@@ -622,11 +634,23 @@ mh_status enqueue_sample(const double* x, const double* y, int64_t n, uint64_t s
     A.replica = replica;
     A.key0 = (uint32_t)seed;
     A.key1 = (uint32_t)(seed >> 32);
-    A.out = EdgeOut{src, dst, w, capacity, &ctr->n_edges};
+    A.out = EdgeOut{src, dst, w, rank_cnt ? 0 : capacity, &ctr->n_edges};
     A.sid = nullptr;
+    A.rank_cnt = rank_cnt;
     A.ctr = ctr;
     const int32_t gb = plan ? plan->grid_blocks : 0;
-    if (weighted) {
+    if (rank_cnt) {
+        // statistics always: the edge count is the number of accepts
+        const int64_t zb = (n + kThreads - 1) / kThreads;
+        hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)(zb < 1024 ? zb : 1024)), dim3(kThreads), 0, stream, rank_cnt,
+                           n);
+        MH_HIP_TRY(hipGetLastError());
+        if (chung_lu) launch_sweep<false, true, false, OUT_RANKS, true>(A, n, gb, stream);
+        else launch_sweep<false, true, false, OUT_RANKS, false>(A, n, gb, stream);
+    } else if (chung_lu) {
+        if (stats) launch_sweep<false, true, false, OUT_EDGES, true>(A, n, gb, stream);
+        else launch_sweep<false, false, false, OUT_EDGES, true>(A, n, gb, stream);
+    } else if (weighted) {
         if (stats) launch_sweep<true, true>(A, n, gb, stream);
         else launch_sweep<true, false>(A, n, gb, stream);
     } else {
@@ -641,15 +665,41 @@ mh_status enqueue_sample(const double* x, const double* y, int64_t n, uint64_t s
 mh_status sample_impl(const double* x, const double* y, int64_t n, uint64_t seed, uint32_t replica,
                       const mh_plan_params* plan, int32_t* src, int32_t* dst, int32_t* w, int64_t capacity,
                       int64_t* n_edges_host, void* workspace, size_t ws_bytes, mh_stats* stats_host,
-                      hipStream_t stream) {
+                      hipStream_t stream, bool chung_lu = false) {
     if (!n_edges_host) return MH_EINVAL;
     *n_edges_host = 0;
     if (stats_host) *stats_host = mh_stats{0, 0, 0, 0, 0, 0};
     if (n == 0) return (n >= 0 && capacity >= 0) ? MH_OK : MH_EINVAL;
     mh_status st = enqueue_sample(x, y, n, seed, replica, plan, src, dst, w, capacity, workspace, ws_bytes,
-                                  stats_host != nullptr, stream);
+                                  stats_host != nullptr, stream, chung_lu);
     if (st != MH_OK) return st;
     return read_counters(static_cast<const Counters*>(workspace), capacity, n_edges_host, stats_host, stream);
+}
+
+// Counts by rank of one unweighted sample (UBCM or Chung-Lu): the edge count is
+// the statistics' accepts.
+mh_status rank_counts_impl(const double* x, int64_t n, bool chung_lu, uint64_t seed, uint32_t replica,
+                           const mh_plan_params* plan, int32_t* rank_cnt, int64_t* n_edges_host, void* workspace,
+                           size_t ws_bytes, mh_stats* stats_host, hipStream_t stream) {
+    if (!n_edges_host) return MH_EINVAL;
+    *n_edges_host = 0;
+    if (stats_host) *stats_host = mh_stats{0, 0, 0, 0, 0, 0};
+    if (n < 0) return MH_EINVAL;
+    if (n == 0) return MH_OK;
+    if (!rank_cnt) return MH_EINVAL;
+    mh_status st = enqueue_sample(x, nullptr, n, seed, replica, plan, nullptr, nullptr, nullptr, 0, workspace,
+                                  ws_bytes, true, stream, chung_lu, rank_cnt);
+    if (st != MH_OK) return st;
+    mh_stats sh;
+    int64_t unused = 0;
+    st = read_counters(static_cast<const Counters*>(workspace), INT64_MAX, &unused, &sh, stream);
+    if (st != MH_OK) return st;
+    *n_edges_host = sh.accepts;
+    if (stats_host) {
+        *stats_host = sh;
+        stats_host->n_edges = sh.accepts;
+    }
+    return MH_OK;
 }
 
 // ---- the allocation-free sampler's scratch ----
@@ -977,6 +1027,21 @@ mh_status mh_sample_weighted(const double* x, const double* y, int64_t n, uint64
     }
     return mh::sample_impl(x, y, n, seed, replica, plan, src, dst, w, capacity, n_edges_host, workspace, ws_bytes,
                            stats_host, stream);
+}
+
+mh_status mh_sample_chung_lu(const double* w, int64_t n, uint64_t seed, uint32_t replica, const mh_plan_params* plan,
+                             int32_t* src, int32_t* dst, int64_t capacity, int64_t* n_edges_host, void* workspace,
+                             size_t ws_bytes, mh_stats* stats_host, hipStream_t stream) {
+    return mh::sample_impl(w, nullptr, n, seed, replica, plan, src, dst, nullptr, capacity, n_edges_host, workspace,
+                           ws_bytes, stats_host, stream, true);
+}
+
+mh_status mh_sample_rank_counts(const double* x, int64_t n, int32_t model, uint64_t seed, uint32_t replica,
+                                const mh_plan_params* plan, int32_t* rank_counts, int64_t* n_edges_host,
+                                void* workspace, size_t ws_bytes, mh_stats* stats_host, hipStream_t stream) {
+    if (model != MH_MODEL_UBCM && model != MH_MODEL_CHUNG_LU) return MH_EINVAL;
+    return mh::rank_counts_impl(x, n, model == MH_MODEL_CHUNG_LU, seed, replica, plan, rank_counts, n_edges_host,
+                                workspace, ws_bytes, stats_host, stream);
 }
 
 mh_status mh_sample_unweighted_noalloc(const double* x, int64_t n, uint64_t seed, uint32_t replica,

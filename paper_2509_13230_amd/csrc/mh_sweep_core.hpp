@@ -143,7 +143,10 @@ struct BatchRef {
     const int64_t* deg_off;     // [n_samples] start of each sample's degree array
 };
 
-enum SweepOut { OUT_EDGES = 0, OUT_DEGREES = 1 };
+// Output of a sweep: the edge list; per-node degrees (batched); or, for one
+// network, counts by rank: cnt[j] += 1 for every edge whose endpoint of larger
+// rank is j (the edges among the first K ranks number cnt[0] + ... + cnt[K-1]).
+enum SweepOut { OUT_EDGES = 0, OUT_DEGREES = 1, OUT_RANKS = 2 };
 
 struct SweepLaunch {
     NetDesc net;        // single-sample network (unused in batch launches)
@@ -152,6 +155,7 @@ struct SweepLaunch {
     uint32_t key0, key1;
     EdgeOut out;
     int32_t* sid;       // batch edge output: sample id per edge (may be null)
+    int32_t* rank_cnt;  // OUT_RANKS: counts by the larger endpoint's rank [n]
     Counters* ctr;
 };
 
@@ -160,12 +164,17 @@ enum : uint32_t { S_IDLE = 0, S_REC, S_LOAD, S_STEP, S_DONE };
 
 // BIP: two node sets (single-sample launches only); the column arrays and the
 // chain start differ, and NET_NO_SELF rejects the candidate with the row's id.
+// CL: the Chung-Lu model read as probabilities, p = min(t, 1) (Sec. 2.1), by
+// the Miller-Hagberg chain of Sec. 2.3 (unweighted, one node set): proposal
+// q = min(t_q, 1), skip -log U1 / -log(1 - q), 0 when q = 1, accept U2 q < p.
 // Returns the number of edges left in the wave's stage (written by the caller).
 // STATS: the wave's counts are left in st_out[ST_COUNT] (LDS) for the block.
-template <bool WEIGHTED, bool STATS, bool BATCH, int OUT, bool BIP>
+template <bool WEIGHTED, bool STATS, bool BATCH, int OUT, bool BIP, bool CL = false>
 __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_src, int32_t* s_dst, int32_t* s_w,
                                            int32_t* s_sid, unsigned long long* st_out) {
     static_assert(!(BIP && BATCH), "two-set networks are sampled one at a time");
+    static_assert(!(CL && (WEIGHTED || BIP || BATCH)), "the Chung-Lu chain is unweighted, one set, one sample");
+    static_assert(OUT != OUT_RANKS || !(BATCH || BIP), "counts by rank are kept for one network");
     const int wave = threadIdx.x >> 6;
     const int64_t gwave = (int64_t)blockIdx.x * kSweepWaves + wave;
     const int64_t nwaves = (int64_t)gridDim.x * kSweepWaves;
@@ -232,7 +241,10 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
         if (state == S_STEP) {
             const double t = s * ra.z;
             double lhs, rhs;
-            if (WEIGHTED) {
+            if (CL) {
+                lhs = U2 * (tq < 1.0 ? tq : 1.0);
+                rhs = t < 1.0 ? t : 1.0;
+            } else if (WEIGHTED) {
                 const double e = 1.0 - ysr * ry;
                 lhs = (U2 * tq) * (e + t);
                 rhs = t * (cr + tq);
@@ -311,6 +323,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
             ++row_deg;
             atomicAdd(&deg[dst_id], 1);
         }
+        if (OUT == OUT_RANKS && acc) atomicAdd(&A.rank_cnt[pos], 1);  // pos: the accepted column's rank
         // the accepted edge's sample: step 4 may move the lane to an item of the next sample
         const int32_t acc_sample = sample;
         // 3. the skip: candidate pos + 1 + floor(-log U1 / -log(1 - q)), or the end of the segment
@@ -318,8 +331,14 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
             bool ended = true;
             if (tq != 0.0) {
                 ++st_steps;
-                const double lq = WEIGHTED ? log1p_fast(tq / cr) : log1p_fast(tq);
-                const double d = E / lq;
+                double d;
+                if (CL) {
+                    // -log(1 - q) = -log1p(-t_q) for t_q < 1; every column is a candidate at q = 1
+                    d = tq >= 1.0 ? 0.0 : E / -log1p_fast(-tq);
+                } else {
+                    const double lq = WEIGHTED ? log1p_fast(tq / cr) : log1p_fast(tq);
+                    d = E / lq;
+                }
                 const double room = (double)(end - 1 - pos);
                 if (d < room) {
                     ended = false;
@@ -416,12 +435,13 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
     return stage.fill;
 }
 
-template <bool WEIGHTED, bool STATS, bool BATCH, int OUT, bool BIP = false>
+template <bool WEIGHTED, bool STATS, bool BATCH, int OUT, bool BIP = false, bool CL = false>
 __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepLaunch A) {
-    __shared__ int32_t s_src[kSweepWaves][kStageEdges];
-    __shared__ int32_t s_dst[kSweepWaves][kStageEdges];
-    __shared__ int32_t s_w[WEIGHTED ? kSweepWaves : 1][WEIGHTED ? kStageEdges : 1];
-    __shared__ int32_t s_sid[BATCH ? kSweepWaves : 1][BATCH ? kStageEdges : 1];
+    constexpr int kStage = OUT == OUT_EDGES ? kStageEdges : 1;
+    __shared__ int32_t s_src[kSweepWaves][kStage];
+    __shared__ int32_t s_dst[kSweepWaves][kStage];
+    __shared__ int32_t s_w[WEIGHTED ? kSweepWaves : 1][WEIGHTED ? kStage : 1];
+    __shared__ int32_t s_sid[BATCH ? kSweepWaves : 1][BATCH ? kStage : 1];
     __shared__ uint32_t s_fill[kSweepWaves];
     __shared__ uint32_t s_arrived;
     __shared__ unsigned long long s_st[STATS ? kSweepWaves : 1][ST_COUNT];
@@ -429,7 +449,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepLaunch A) {
     if (threadIdx.x == 0) s_arrived = 0;
     __syncthreads();
     const int wave = threadIdx.x >> 6;
-    const uint32_t fill = sweep_body<WEIGHTED, STATS, BATCH, OUT, BIP>(
+    const uint32_t fill = sweep_body<WEIGHTED, STATS, BATCH, OUT, BIP, CL>(
         A, s_src[wave], s_dst[wave], WEIGHTED ? s_w[wave] : nullptr, BATCH ? s_sid[wave] : nullptr,
         STATS ? s_st[wave] : nullptr);
     bool last = false;

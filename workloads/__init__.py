@@ -30,6 +30,7 @@ __all__ = [
     "cfg5_targets",
     "bipartite_params",
     "directed_params",
+    "holme_kim",
     "sha256",
     "Network",
 ]
@@ -200,3 +201,54 @@ def directed_params(seed: int = 7, n: int = 500_000, weighted: bool = False):
     yo = rng.uniform(0.05, 0.95, n)
     yi = rng.uniform(0.05, 0.95, n)
     return ko / e / yo, ki / e / yi, yo, yi
+
+
+def holme_kim(n: int = 5000, m: int = 10, p_triad: float = 0.1, seed: int = 8) -> tuple[np.ndarray, np.ndarray]:
+    """Edge list (src, dst; each edge once, src < dst) of a Holme-Kim network
+    (Holme and Kim, Phys. Rev. E 65, 026107, 2002): growth by preferential
+    attachment with triad formation, the clustered power-law network of the
+    paper's Fig. 1 (5,000 nodes, m = 10, triad probability 0.1).
+
+    The first m nodes start without edges and node m links to all of them.
+    Each later node v makes m links: the first to a node drawn with
+    probability proportional to its degree; each further one, with probability
+    p_triad, to a random neighbour of the node of the previous preferential
+    link that v is not yet linked to (if there is one), and otherwise again by
+    preferential attachment.  No multi-edges, no self-loops."""
+    rng = np.random.default_rng(seed)
+    ends: list[int] = []  # every edge's two ends: a uniform draw is a degree-proportional one
+    nbr: list[list[int]] = [[] for _ in range(n)]
+    src, dst = [], []
+
+    def pref(v, linked):
+        # at least m + 1 nodes have edges once node m has linked, and v is
+        # linked to at most m - 1 of them: the draw ends
+        while True:
+            u = int(ends[rng.integers(len(ends))])
+            if u != v and u not in linked:
+                return u
+
+    def link(u, v):
+        nbr[u].append(v)
+        nbr[v].append(u)
+        ends.extend((u, v))
+        src.append(min(u, v))
+        dst.append(max(u, v))
+
+    for u in range(min(m, n - 1)):
+        link(u, m)
+    for v in range(m + 1, n):
+        linked: set[int] = set()
+        last_pref = None
+        for k in range(m):
+            u = None
+            if k > 0 and last_pref is not None and rng.random() < p_triad:
+                cand = [w for w in nbr[last_pref] if w != v and w not in linked]
+                if cand:
+                    u = cand[int(rng.integers(len(cand)))]
+            if u is None:
+                u = pref(v, linked)
+                last_pref = u
+            linked.add(u)
+            link(u, v)
+    return np.asarray(src, dtype=np.int32), np.asarray(dst, dtype=np.int32)
