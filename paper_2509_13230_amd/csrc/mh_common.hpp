@@ -195,8 +195,10 @@ __device__ __forceinline__ double log_fast(double x) {
     return log_reduced(m, k);
 }
 
-// log(1 + t) for finite t >= 0: log of u = 1 + t rounded, plus the rounding
-// error c = t - (u - 1) (exact) divided by u.
+// log(1 + t) for finite t > -1 (1 + t rounded to a normal number): log of
+// u = 1 + t rounded, plus the rounding error c = t - (u - 1) divided by u (c
+// is exact for |t| <= 1, Fast2Sum; for larger t, c / u is far below an ulp of
+// log u).
 __device__ __forceinline__ double log1p_fast(double t) {
     const double u = 1.0 + t;
     const double c = t - (u - 1.0);

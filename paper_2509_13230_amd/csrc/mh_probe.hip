@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_atomic_adds(int32_t* __
 }
 
 // out_log[i] = log_fast(u[i]) and out_log1p[i] = log1p_fast(t[i]), the
-// device functions the sweep calls for the skip (U in (0, 1], t >= 0 finite).
+// device functions the sweep calls for the skip (U in (0, 1], t > -1 finite).
 __global__ __launch_bounds__(kProbeThreads) void k_probe_logs(const double* __restrict__ u,
                                                               const double* __restrict__ t, int64_t n,
                                                               double* __restrict__ out_log,
@@ -46,7 +46,7 @@ extern "C" {
 
 // Evaluates the sweep's logarithms on n inputs (device arrays of float64):
 // out_log = log_fast(u), u normal and positive; out_log1p = log1p_fast(t),
-// t finite and >= 0.  Asynchronous on `stream`; 0, -1 for invalid arguments,
+// t finite and > -1 (1 + t rounded to a normal number).  Asynchronous on `stream`; 0, -1 for invalid arguments,
 // -2 for a failed launch.
 int mhp_sweep_logs(const double* u, const double* t, int64_t n, double* out_log, double* out_log1p,
                    hipStream_t stream) {

@@ -4,7 +4,8 @@ most 3 ulp apart over the skip's whole domain, U in (0, 1] (the 53-bit
 uniforms of the sampler, end points included) and t_q from 1e-300 to 1e300.
 The skip length floor(-log U / log1p(t_q)) can only differ between host and
 device where the quotient lies within a few ulp of an integer: far inside the
-1e-12 margin of the oracle's near-tie trace."""
+1e-12 margin of the oracle's near-tie trace.  The Chung-Lu chain's log1p of
+negative arguments (-t_q, t_q in (0, 1)) is checked the same way."""
 import ctypes
 import math
 import os
@@ -72,3 +73,17 @@ def test_sweep_logs_within_3_ulp(probe):
     # exact where the result is exact: log 1 = 0; log1p(t) = t below 2^-53 relative
     assert lg[7] == 0.0
     assert lp[0] == 0.0 and lp[1] == 1e-300
+
+
+def test_log1p_of_negative_arguments_within_3_ulp(probe):
+    # the Chung-Lu skip takes -log1p(-t_q) for t_q in (0, 1)
+    rng = np.random.default_rng(18)
+    n = 1 << 18
+    t = -(10.0 ** rng.uniform(-300, 0, n))
+    t = np.maximum(t, -(1.0 - 2.0**-53))
+    t[:6] = [-1e-300, -2.0**-53, -0.5, -0.9, -(1.0 - 2.0**-53), -0.29289321881345254]
+    u = np.full(n, 0.5)
+    _, lp = device_logs(probe, u, t)
+    ref = np.array([math.log1p(v) for v in t])
+    e = ulps(lp, ref)
+    assert e.max() <= MAX_ULP, (e.max(), t[np.argmax(e)])
