@@ -316,18 +316,30 @@ def expected_degree_bench(args, dev) -> dict:
     }
 
 
-def weighted_bench(args, dev) -> dict:
+def weighted_bench(args, dev, fitted: bool = False) -> dict:
     """The weighted sampler on the UECM N = 200,000 workload (power-law degrees
-    2.3 on [1, 5000], strengths k (1 + Gamma(2, 3)); parameters from the
-    sparse-limit recipe): samples issued back to back on one stream, edges/s,
-    and the stage times (order, bound + plan, sweep) of an untimed repeat."""
+    2.3 on [1, 5000], strengths k (1 + Gamma(2, 3))): samples issued back to
+    back on one stream, edges/s, and the stage times (order, bound + plan,
+    sweep) of an untimed repeat.  Parameters from the sparse-limit recipe, or
+    (fitted) from the device fit of the targets (Newton-CG on the likelihood,
+    untimed; its residuals are reported)."""
     import torch
 
     import paper_2509_13230_amd as mh
     import workloads
+    from paper_2509_13230_amd.fit import fit_uecm
 
     k, st = workloads.cfg3_targets(seed=3, n=args.w_n)
-    xn, yn = workloads.uecm_recipe(k, st)
+    fit_info = None
+    if fitted:
+        t0 = time.perf_counter()
+        f = fit_uecm(k, st, tol=1e-8, max_newton=args.w_fit_newton)
+        fit_info = {"iterations": f.iterations, "residual_k": f.residual, "residual_s": f.residual_s,
+                    "seconds": time.perf_counter() - t0, "y_max": float(f.y.max()),
+                    "y_above_0.999": int((f.y > 0.999).sum())}
+        xn, yn = f.x, f.y
+    else:
+        xn, yn = workloads.uecm_recipe(k, st)
     x = torch.as_tensor(xn, device=dev)
     y = torch.as_tensor(yn, device=dev)
     n = x.numel()
@@ -371,7 +383,10 @@ def weighted_bench(args, dev) -> dict:
         raise RuntimeError(f"timed and repeated weighted sample differ: {last_edges} vs {stt['n_edges']} edges")
     return {
         "workload": f"UECM N={n}, power-law degrees (exponent 2.3, k in [1, 5000]), strengths k (1 + Gamma(2, 3)), "
-                    "sparse-limit parameters; samples issued back to back on one stream",
+                    + ("parameters from the device fit of these targets" if fitted else "sparse-limit parameters")
+                    + "; samples issued back to back on one stream",
+        "fit": fit_info,
+        "proposals_per_edge": wprops / max(edges, 1),
         "samples": steps,
         "seg_work": args.w_seg_work,
         "ms_per_sample": elapsed / steps * 1e3,
@@ -753,6 +768,8 @@ def main():
     ap.add_argument("--deg-n", type=int, default=200_000,
                     help="nodes of the expected-degree measurement (0: skip it)")
     ap.add_argument("--w-n", type=int, default=200_000, help="nodes of the weighted measurement (0: skip it)")
+    ap.add_argument("--w-fit-newton", type=int, default=200,
+                    help="Newton steps of the weighted fit for the fitted-parameter measurement (0: skip it)")
     ap.add_argument("--w-seg-work", type=int, default=32,
                     help="seg_work of the weighted measurement (the best of 8-128 on that workload)")
     ap.add_argument("--bip-rows", type=int, default=1_000_000,
@@ -909,6 +926,8 @@ def main():
         out["bruteforce"] = bruteforce_vs_mh(args, x, dev)
     if args.w_n > 0:
         out["weighted"] = weighted_bench(args, dev)
+        if args.w_fit_newton > 0:
+            out["weighted_fitted"] = weighted_bench(args, dev, fitted=True)
     if args.bip_rows > 0:
         out["bipartite"] = bipartite_bench(args, dev)
     if args.bias_replicas > 0:

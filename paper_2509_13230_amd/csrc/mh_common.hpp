@@ -201,6 +201,9 @@ __device__ __forceinline__ double log_fast(double x) {
 // is exact for |t| <= 1, Fast2Sum; for larger t, c / u is far below an ulp of
 // log u).
 __device__ __forceinline__ double log1p_fast(double t) {
+    // |t| < 2^-27: t - t^2/2 is log1p(t) to within t^3/3 < 2^-54 |t|, one
+    // rounding (below, 1 + t would cancel against log u for negative t)
+    if (fabs(t) < 0x1.0p-27) return fma(-0.5 * t, t, t);
     const double u = 1.0 + t;
     const double c = t - (u - 1.0);
     double r = __builtin_amdgcn_rcp(u);

@@ -46,9 +46,10 @@ constexpr uint64_t kFlagAggregate = 1ull << 32;
 constexpr uint64_t kFlagPrefix = 2ull << 32;
 constexpr uint32_t kSpinLimit = 1u << 20;
 constexpr int kLookWindow = 8;
-// Column exchange: at most kXchgTiles tiles (a digit column of the tiles'
-// counts is scanned by up to 256 threads).
+// Column exchange: at most kXchgTiles tiles; above 64 tiles a digit column of
+// the tiles' counts is scanned by 256 threads, kXchgCols columns a block at once.
 constexpr int kXchgTiles = 256;
+constexpr int kXchgCols = kSortThreads / kXchgTiles;
 // The counting kernel adds its block histograms into kHistCopies copies (block
 // b into copy b % kHistCopies); readers sum the copies.
 constexpr int kHistCopies = kRadixHistCopies;
@@ -77,6 +78,21 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* lds_wa
         if (w < wave) before += lds_wave[w];
     __syncthreads();
     return before + inc - v;
+}
+
+// A tile's published count of one digit (flag and value in one word),
+// waited for with a bounded spin: a stall raises MH_EHIP and reads 0.
+__device__ __forceinline__ uint32_t xchg_wait_count(uint64_t* cw, int32_t* err) {
+    uint32_t spins = 0;
+    for (;;) {
+        const uint64_t w = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (w & ~0xFFFFFFFFull) return (uint32_t)w;
+        if (++spins > kSpinLimit) {
+            raise_status(err, MH_EHIP);
+            return 0u;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
 }
 
 // Zeroes three ranges of u64 words (any may be empty).
@@ -212,65 +228,63 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
     if (XCHG) {
         // Every tile is resident (at most kXchgTiles): instead of a chain of
         // look-backs, the blocks scan the digit columns over all tiles'
-        // published counts, a column by tpc threads (one per tile, tpc the
-        // tile count rounded up to a power of two) and kSortThreads / tpc
-        // columns per block at once: block b takes columns b, b + G, b + 2G, ...
-        // (G blocks).  Each column's scan writes every tile the count of that
-        // digit in the tiles before it (flag 2 over the count word, which only
-        // this block reads) and, when the pass has no digit totals of its own,
-        // the column's total to dtot; then every tile reads its 256 words
-        // back.  Two round trips per pass, however few the tiles.
+        // published counts, one thread per tile of a column: block b takes
+        // columns b, b + G, b + 2G, ... (G blocks), several at once.  Each
+        // column's scan writes every tile the count of that digit in the
+        // tiles before it (flag 2 over the count word, which only this block
+        // reads) and, when the pass has no digit totals of its own, the
+        // column's total to dtot; then every tile reads its 256 words back.
+        // Two round trips per pass, however few the tiles.
         const int nt = (int)gridDim.x;
-        int tpc = 1;
-        while (tpc < nt) tpc <<= 1;
-        const int cpb = kSortThreads / tpc;      // columns per block at once
-        const int tcol = threadIdx.x & (tpc - 1);  // this thread's tile in the column
-        const int wpc = tpc > kWave ? tpc / kWave : 1;  // waves per column (tpc > 64)
-        for (int c0 = blockIdx.x; c0 < kRadix; c0 += cpb * nt) {
-            const int col = c0 + (int)(threadIdx.x / tpc) * nt;
-            const bool mine = tcol < nt && col < kRadix;
-            uint64_t* cw = status + (int64_t)tcol * kRadix + col;
-            uint32_t c = 0;
-            if (mine) {
-                uint32_t spins = 0;
-                for (;;) {
-                    const uint64_t w = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (w & ~0xFFFFFFFFull) {
-                        c = (uint32_t)w;
-                        break;
-                    }
-                    if (++spins > kSpinLimit) {
-                        raise_status(err, MH_EHIP);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+        if (nt > kWave) {
+            // a column by 256 threads (4 waves), 4 columns at once
+            const int tcol = threadIdx.x & (kXchgTiles - 1);  // this thread's tile in the column
+            for (int c0 = blockIdx.x; c0 < kRadix; c0 += kXchgCols * nt) {
+                const int col = c0 + (int)(threadIdx.x / kXchgTiles) * nt;
+                const bool mine = tcol < nt && col < kRadix;
+                uint64_t* cw = status + (int64_t)tcol * kRadix + col;
+                const uint32_t c = mine ? xchg_wait_count(cw, err) : 0u;
+                // exclusive scan over each column's 256 threads (4 waves)
+                const uint32_t inc = wave_inclusive_scan(c);
+                if (lane == 63) s_scan[wave] = inc;
+                __syncthreads();
+                const int w0 = wave & ~(kXchgTiles / kWave - 1);
+                uint32_t before = inc - c;
+                for (int w = w0; w < wave; ++w) before += s_scan[w];
+                if (mine) __hip_atomic_store(cw, kFlagPrefix | before, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (FROMX && tcol == 0 && col < kRadix) {
+                    uint32_t coltotal = 0;
+                    for (int w = w0; w < w0 + kXchgTiles / kWave; ++w) coltotal += s_scan[w];
+                    __hip_atomic_store(dtot + col, kFlagPrefix | coltotal, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
                 }
+                __syncthreads();
             }
-            uint32_t before, coltotal = 0;
-            if (tpc <= kWave) {
-                // inclusive scan within each group of tpc lanes
-                uint32_t inc = c;
+        } else {
+            // at most 64 tiles: a column by tpc lanes of a wave (the tile count
+            // rounded up to a power of two), kSortThreads / tpc columns at once
+            int lg = 0;
+            while ((1 << lg) < nt) ++lg;
+            const int tpc = 1 << lg;
+            const int tcol = threadIdx.x & (tpc - 1);
+            for (int c0 = blockIdx.x; c0 < kRadix; c0 += (kSortThreads >> lg) * nt) {
+                const int col = c0 + (int)(threadIdx.x >> lg) * nt;
+                const bool mine = tcol < nt && col < kRadix;
+                uint64_t* cw = status + (int64_t)tcol * kRadix + col;
+                const uint32_t c = mine ? xchg_wait_count(cw, err) : 0u;
+                uint32_t inc = c;  // inclusive scan within each group of tpc lanes
                 for (int dd = 1; dd < tpc; dd <<= 1) {
                     const uint32_t u = __shfl_up(inc, (unsigned)dd, tpc);
                     if (tcol >= dd) inc += u;
                 }
-                before = inc - c;
-                if (FROMX) coltotal = __shfl(inc, lane | (tpc - 1), kWave);
-            } else {
-                // a column over wpc waves
-                const uint32_t inc = wave_inclusive_scan(c);
-                if (lane == 63) s_scan[wave] = inc;
-                __syncthreads();
-                const int w0 = wave & ~(wpc - 1);
-                before = inc - c;
-                for (int w = w0; w < wave; ++w) before += s_scan[w];
-                if (FROMX && tcol == 0)
-                    for (int w = w0; w < w0 + wpc; ++w) coltotal += s_scan[w];
+                if (mine) __hip_atomic_store(cw, kFlagPrefix | (inc - c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (FROMX) {
+                    const uint32_t coltotal = __shfl(inc, lane | (tpc - 1), kWave);
+                    if (tcol == 0 && col < kRadix)
+                        __hip_atomic_store(dtot + col, kFlagPrefix | coltotal, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
-            if (mine) __hip_atomic_store(cw, kFlagPrefix | before, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (FROMX && tcol == 0 && col < kRadix)
-                __hip_atomic_store(dtot + col, kFlagPrefix | coltotal, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (tpc > kWave) __syncthreads();  // s_scan is rewritten by the next round
         }
         if (dig) {
             uint32_t spins = 0;

@@ -65,6 +65,8 @@ def _model():
         return reduced(m, k)
 
     def log1p_fast(t):
+        if abs(t) < 2.0 ** -27:
+            return (-0.5 * t) * t + t  # the kernel's single fma rounds once; this model twice
         u = 1.0 + t
         c = t - (u - 1.0)
         return c * (1.0 / u) + log_fast(u)
@@ -86,9 +88,11 @@ def test_model_within_a_few_ulp(seed):
         worst = max(worst, _ulps(log_fast(u), math.log(u)))
         t = 10.0 ** rng.uniform(-14, 4)  # t_q over the range of the workloads
         worst1 = max(worst1, _ulps(log1p_fast(t), math.log1p(t)))
+        t = -(10.0 ** rng.uniform(-20, -0.5))  # -t_q of the Chung-Lu skip
+        worst1 = max(worst1, _ulps(log1p_fast(t), math.log1p(t)))
     for u in (2.0 ** -53, 0.5, 0.70710678118654752440, 1.0 - 2.0 ** -53):
         worst = max(worst, _ulps(log_fast(u), math.log(u)))
     assert log_fast(1.0) == 0.0
-    for t in (2.0 ** -60, 1e-9, 0.41421356, 1.0, 3.0, 1e6):
+    for t in (2.0 ** -60, 1e-9, 0.41421356, 1.0, 3.0, 1e6, 2.0 ** -27, -(2.0 ** -27), -1.79e-16, -0.5):
         worst1 = max(worst1, _ulps(log1p_fast(t), math.log1p(t)))
     assert worst <= 3.0 and worst1 <= 3.0, (worst, worst1)
