@@ -40,10 +40,34 @@ HBM_PEAK_GBS = 8000.0
 
 # VALU instructions of one step of the sweep on its common path, counted in the
 # gfx950 code of k_sweep<false,false>: the draw (Philox block, the two
-# uniforms, the log of U1) 109, the acceptance test 15, the skip (log1p, the
+# uniforms, the log of U1) 93, the acceptance test 15, the skip (log1p, the
 # division, the next candidate's address) 67, the candidate load 1; loop,
 # refill and staging instructions are not counted as work.
-SWEEP_VALU_PER_STEP = 192
+SWEEP_VALU_PER_STEP = 176
+
+# HBM bytes of one unweighted k_sweep launch on the timed workload (stored fit,
+# seg_work 8), from two rocprofv3 --pmc runs: FETCH_SIZE and WRITE_SIZE in KiB
+# per dispatch (medians over the timed samples), scaled by what the same
+# counters read for a 256 MiB copy (fetched bytes = 2 x FETCH_SIZE, written =
+# 1 x WRITE_SIZE).  They hold for the sweep built from the sources hashed in
+# SWEEP_SOURCES only; for any other build or input the bench reports null.
+SWEEP_COUNTERS = {"fetch_kib": 107104, "write_kib": 16365, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sources_sha256": "977157ed0f20a8f6a86737451400fb3c80639abc273c9e61840991d3bd05acc6",
+                  "input_sha256": "bc9851eaa93191638377524467d37dbbae5a37d6523e29d9c327d955e13c3ef6",
+                  "seg_work": 8}
+SWEEP_SOURCES = ["paper_2509_13230_amd/csrc/" + f for f in
+                 ("mh_sweep.hip", "mh_sweep_core.hpp", "mh_stage.hpp", "mh_common.hpp", "mh_prepare.hpp",
+                  "mh_internal.hpp", "mh_lookback.hpp")] + ["include/mh.h"]
+
+
+def sweep_sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 class HipEvents:
@@ -180,8 +204,9 @@ def small_bench(args, dev) -> dict:
 
 # VALU instructions per pair of the brute-force sampler's loop (Philox block,
 # the column's z, the uniform and the test), counted in the gfx950 code of
-# k_bruteforce<false>; staging of accepted pairs is not counted as work.
-BF_VALU_PER_PAIR = 65
+# k_bruteforce<false> (the Philox rounds' three-input xors one v_bitop3_b32
+# each); staging of accepted pairs is not counted as work.
+BF_VALU_PER_PAIR = 51
 
 
 def bruteforce_vs_mh(args, x, dev) -> dict:
@@ -781,6 +806,7 @@ def main():
                     help="replicas of the Chung-Lu bias statistics (0: skip the Chung-Lu measurement)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-small", action="store_true", help="skip the N=2,000 timings")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="copy a buffer of this many MiB once first (reference for HBM byte counters)")
     ap.add_argument("--batch-networks", type=int, default=256)
@@ -886,9 +912,21 @@ def main():
     # the sweep's edge output against HBM bandwidth (8 B per edge written)
     edges_per_sweep = edges_timed_sweeps / len(timed_sweeps)
     write_gbs = edges_per_sweep * 8 / (sweep_ms * 1e-3) / 1e9
+    # algorithmic bytes of one sweep launch: every node record (16 B) read once,
+    # every edge (8 B) written once
+    alg_bytes = 16 * n + edges_per_sweep * 8
+    traffic = None
+    if (sweep_sources_sha256() == SWEEP_COUNTERS["sources_sha256"]
+            and workloads.sha256(x_np) == SWEEP_COUNTERS["input_sha256"]
+            and args.seg_work == SWEEP_COUNTERS["seg_work"]):
+        traffic = (SWEEP_COUNTERS["fetch_kib"] * 1024 * SWEEP_COUNTERS["fetch_scale"]
+                   + SWEEP_COUNTERS["write_kib"] * 1024 * SWEEP_COUNTERS["write_scale"])
     roof = {"bound": "alu", "kernel": "k_sweep (unweighted)",
             "achieved": achieved_lane_ops / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
-            "frac": achieved_lane_ops / PEAK_LANE_OPS, "traffic": None,
+            "frac": achieved_lane_ops / PEAK_LANE_OPS, "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes": alg_bytes,
+            "traffic_over_algorithmic": traffic / alg_bytes if traffic is not None else None,
             "work_per_launch": f"{steps_per_sweep:.0f} steps x {SWEEP_VALU_PER_STEP} VALU lane-ops",
             "timed_launches": len(timed_sweeps),
             "avg_launch_ms": sweep_ms,
@@ -919,7 +957,8 @@ def main():
         "sweep_only_edges_per_s": edges_per_sweep / (sweep_ms * 1e-3),
         "roofline": roof,
     }
-    out["small"] = small_bench(args, dev)
+    if not args.skip_small:
+        out["small"] = small_bench(args, dev)
     if not args.skip_batched:
         out["batched"] = batched_ensemble(args, dev)
     if args.bf_prefix > 0:
