@@ -95,20 +95,26 @@ size_t radix_workspace_bytes(int64_t n);
 // kRadixPasses x 256 counts of the bytes of hi (copy c, pass p, digit d at
 // [(c * kRadixPasses + p) * 256 + d]); a counting block adds into copy
 // blockIdx % kRadixHistCopies.
-// e1, e2: further ranges of u64 words zeroed by the same kernel.
+// e1, e2: further ranges of u64 words zeroed by the same kernel.  x (and y)
+// non-null: the same kernel also takes the least and largest sort key of every
+// tile of the node parameters, for a first pass that makes the keys itself.
 mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream,
-                        ZeroRange e1 = {}, ZeroRange e2 = {});
+                        ZeroRange e1 = {}, ZeroRange e2 = {}, const double* x = nullptr, const double* y = nullptr);
 // Sorts hi[0..n) / pay[0..n) using alt buffers of the same size (the result
 // ends in hi / pay); the histograms must hold the counts.  err (optional,
 // device) receives MH_EHIP if a look-back or exchange ever stalls.
 // x (and y) non-null: the first pass makes the keys itself from the node
 // parameters (z = x or x y, checks raising MH_EINVAL into err) and counts the
 // later passes' digits, so hi / pay need no preparation and the histograms
-// only need to be zero; allowed when radix_prepares_keys(n).
+// only need to be zero; allowed when radix_prepares_keys(n), with the same x
+// and y given to radix_prepare.  The keys are then sorted less their least
+// value (*kbase, a device word, receives it: hi ends as key >> 32 minus
+// *kbase) by as many passes as their spread needs; otherwise *kbase is null.
 bool radix_prepares_keys(int64_t n);
 mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint64_t* pay_alt, int64_t n,
                              void* ws, size_t ws_bytes, int32_t* err, hipStream_t stream,
-                             const double* x = nullptr, const double* y = nullptr);
+                             const double* x = nullptr, const double* y = nullptr,
+                             const uint32_t** kbase = nullptr);
 
 // ---- sampler pieces ----
 struct SortedView {

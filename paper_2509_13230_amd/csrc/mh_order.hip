@@ -68,12 +68,13 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_keys(const double* __rest
         if (h[i]) atomicAdd(&copy[i], h[i]);
 }
 
-// The sorted key and id at a rank, from the split sort's arrays.
+// The sorted key and id at a rank, from the split sort's arrays (whose high
+// halves are the keys' less kb).
 __device__ __forceinline__ double sorted_z(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ vals,
-                                           int64_t r, uint32_t* id) {
+                                           int64_t r, uint32_t kb, uint32_t* id) {
     const uint64_t v = vals[r];
     *id = (uint32_t)v;
-    return key_value(((uint64_t)keys[r] << 32) | (v >> 32));
+    return key_value(((uint64_t)(keys[r] + kb) << 32) | (v >> 32));
 }
 
 __global__ __launch_bounds__(kThreads) void k_finish_order(const uint32_t* __restrict__ keys,
@@ -82,11 +83,11 @@ __global__ __launch_bounds__(kThreads) void k_finish_order(const uint32_t* __res
                                                            NodeRec* __restrict__ node,
                                                            const double* __restrict__ y, double* __restrict__ ys,
                                                            uint64_t* __restrict__ mass, int32_t check_square,
-                                                           int32_t* status) {
+                                                           const uint32_t* kbase, int32_t* status) {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= n) return;
     uint32_t id;
-    const double z = sorted_z(keys, vals, r, &id);
+    const double z = sorted_z(keys, vals, r, kbase ? *kbase : 0u, &id);
     if (node) {
         node[r].z = z;
         node[r].id = (int32_t)id;
@@ -110,8 +111,10 @@ __global__ __launch_bounds__(kLbThreads) void k_finish_order_scan(const uint32_t
                                                                   double* __restrict__ ys, uint64_t* __restrict__ P,
                                                                   int64_t tiles, uint64_t* state,
                                                                   uint64_t* samples, double* zsamples,
-                                                                  int32_t check_square, int32_t* status) {
+                                                                  int32_t check_square, const uint32_t* kbase,
+                                                                  int32_t* status) {
     __shared__ LbShared sh;
+    const uint32_t kb = kbase ? *kbase : 0u;
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int64_t base = tile * kLbTile;
 #pragma unroll 4
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(kLbThreads) void k_finish_order_scan(const uint32_t
             uint64_t m = 0;
             if (r < n) {
                 uint32_t id;
-                const double z = sorted_z(keys, vals, r, &id);
+                const double z = sorted_z(keys, vals, r, kb, &id);
                 node[r].z = z;
                 node[r].id = (int32_t)id;
                 if (ys) ys[r] = y[id];
@@ -298,19 +301,20 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
     void* sort_ws = ar.base + off;
     const size_t sort_bytes = ws_bytes > off ? ws_bytes - off : 0;
     uint32_t* hist = nullptr;
-    mh_status st = radix_prepare(sort_ws, sort_bytes, n, &hist, stream, e1, e2);
-    if (st != MH_OK) return st;
     // keys and histograms: made by the first radix pass itself when the sort
     // exchanges digit counts between resident tiles, else by k_prep_keys
     const bool fused = radix_prepares_keys(n);
+    mh_status st = radix_prepare(sort_ws, sort_bytes, n, &hist, stream, e1, e2, fused ? x : nullptr, y);
+    if (st != MH_OK) return st;
     if (!fused) {
         const unsigned tiles = (unsigned)((n + kPrepTile - 1) / kPrepTile);
         hipLaunchKernelGGL(k_prep_keys, dim3(tiles), dim3(kPrepThreads), 0, stream, x, y, n, keys, vals, hist,
                            status);
         MH_HIP_TRY(hipGetLastError());
     }
+    const uint32_t* kbase = nullptr;  // the keys' least high half, when the sort subtracted it
     st = radix_sort_split64(keys, vals, keys_alt, vals_alt, n, sort_ws, sort_bytes, status, stream,
-                            fused ? x : nullptr, y);
+                            fused ? x : nullptr, y, &kbase);
     if (st != MH_OK) return st;
     if (mass_prefix && node && n <= (int64_t)1 << 30) {
         // records and the masses' prefix sums in one pass (sums stay below 2^62)
@@ -319,13 +323,13 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
         const int64_t grid = tiles < resident ? tiles : resident;
         hipLaunchKernelGGL(k_finish_order_scan, dim3((unsigned)grid), dim3(kLbThreads), 0, stream,
                            (const uint32_t*)keys, (const uint64_t*)vals, n, node, y, y ? ys : nullptr, mass_prefix,
-                           tiles, mass_state, mass_samples, z_samples, (int32_t)check_square, status);
+                           tiles, mass_state, mass_samples, z_samples, (int32_t)check_square, kbase, status);
         MH_HIP_TRY(hipGetLastError());
         return MH_OK;
     }
     const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_finish_order, dim3(grid), dim3(kThreads), 0, stream, keys, vals, n, perm, zs, node, y,
-                       y ? ys : nullptr, mass_prefix, (int32_t)check_square, status);
+                       y ? ys : nullptr, mass_prefix, (int32_t)check_square, kbase, status);
     MH_HIP_TRY(hipGetLastError());
     if (mass_prefix) return scan_exclusive_u64(mass_prefix, mass_prefix, n, ws, ws_bytes, stream);
     return MH_OK;

@@ -4,7 +4,10 @@
 // order.  The caller passes hi = key >> 32 as the sort key and pay = (low half
 // << 32) | payload, so sorting a run of equal hi by pay orders it by (key,
 // payload); with payloads distinct (node ids) that is the order of a full
-// stable sort.
+// stable sort.  A first pass that makes the keys from node parameters sorts
+// them less their least high half, found by the zeroing kernel before it, with
+// only the passes their spread needs (fitted degrees within a factor 2^15
+// span 24 bits: 3 passes); the passes it does not need return at once.
 //
 // Passes ("one-sweep"): the digit histograms of all passes come from one
 // counting kernel (fused into key preparation by the caller).  In a pass, each
@@ -95,29 +98,96 @@ __device__ __forceinline__ uint32_t xchg_wait_count(uint64_t* cw, int32_t* err) 
     }
 }
 
-// Zeroes three ranges of u64 words (any may be empty).
-__global__ __launch_bounds__(kSortThreads) void k_zero_u64(ZeroRange a, ZeroRange b, ZeroRange c) {
+// Node parameters whose sort keys a first pass will make (x null: none), and
+// where the least and largest key (high halves) of each tile go.
+struct KeySpan {
+    const double* x = nullptr;
+    const double* y = nullptr;
+    int64_t n = 0;
+    uint64_t* part = nullptr;  // tile t: largest << 32 | least
+};
+
+// Zeroes three ranges of u64 words (any may be empty); with a key span, block
+// t < tiles also writes the range of tile t's keys (the grid covers both).
+__global__ __launch_bounds__(kSortThreads) void k_zero_u64(ZeroRange a, ZeroRange b, ZeroRange c, KeySpan ks) {
     const int64_t stride = (int64_t)gridDim.x * kSortThreads;
     const int64_t t = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
     for (int64_t i = t; i < a.n; i += stride) a.p[i] = 0;
     for (int64_t i = t; i < b.n; i += stride) b.p[i] = 0;
     for (int64_t i = t; i < c.n; i += stride) c.p[i] = 0;
+    const int64_t base = (int64_t)blockIdx.x * kTileKeys;
+    if (!ks.x || base >= ks.n) return;  // uniform over the block
+    __shared__ uint32_t s_mn[kSortWaves], s_mx[kSortWaves];
+    uint32_t mn = ~0u, mx = 0u;
+#pragma unroll
+    for (int q = 0; q < kKeysPerLane; ++q) {
+        const int64_t i = base + (int64_t)q * kSortThreads + threadIdx.x;
+        if (i < ks.n) {
+            bool ok;  // an invalid node sorts as z = 0, as in the first pass
+            const double z = node_z(ks.x[i], ks.y != nullptr, ks.y ? ks.y[i] : 0.0, &ok);
+            const uint32_t h = (uint32_t)(desc_key(z) >> 32);
+            mn = h < mn ? h : mn;
+            mx = h > mx ? h : mx;
+        }
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t on = __shfl_xor(mn, d, kWave), ox = __shfl_xor(mx, d, kWave);
+        mn = on < mn ? on : mn;
+        mx = ox > mx ? ox : mx;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_mn[wave] = mn;
+        s_mx[wave] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kSortWaves; ++w) {
+            mn = s_mn[w] < mn ? s_mn[w] : mn;
+            mx = s_mx[w] > mx ? s_mx[w] : mx;
+        }
+        ks.part[blockIdx.x] = ((uint64_t)mx << 32) | mn;
+    }
+}
+
+// Radix passes that keys spanning [0, spread] need (8 bits each; one at least).
+__device__ __forceinline__ uint32_t passes_for(uint32_t spread) {
+    return spread < (1u << 8) ? 1u : spread < (1u << 16) ? 2u : spread < (1u << 24) ? 3u : 4u;
 }
 
 // FROMX (first pass, column exchange only): the pass prepares its own keys from
 // the parameters x (and y) as the key-preparation kernel would, adds the digit
 // histograms of the later passes to hist_all, and takes its own digit totals
 // from the exchange (column owners publish them in dtot) instead of ghist.
+// It also reduces the tiles' key ranges (part) to the least key and the
+// spread, sorts every key less the least (so keys spanning 24 bits need 3
+// passes, not 4), and writes meta = {least key, passes}.  With meta (passes
+// after such a first pass), a pass beyond the count returns at once, and with
+// an odd count every pass swaps its input and output arrays, so that the last
+// pass still writes the arrays the caller passed as the sort's input.
 template <bool XCHG, bool FROMX>
-__global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __restrict__ kin,
-                                                           const uint64_t* __restrict__ vin,
-                                                           uint32_t* __restrict__ kout, uint64_t* __restrict__ vout,
+__global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* kin, const uint64_t* vin, uint32_t* kout,
+                                                           uint64_t* vout,
                                                            int64_t n, int shift, const uint32_t* __restrict__ ghist,
                                                            uint64_t* status, uint32_t* ticket, bool use_ticket,
                                                            int32_t* err, const double* __restrict__ x,
                                                            const double* __restrict__ y,
-                                                           uint32_t* __restrict__ hist_all, uint64_t* dtot) {
+                                                           uint32_t* __restrict__ hist_all, uint64_t* dtot,
+                                                           uint32_t* meta, const uint64_t* __restrict__ part) {
     static_assert(!FROMX || XCHG, "a pass preparing its keys takes its digit totals from the exchange");
+    if (!FROMX && meta) {
+        const uint32_t npass = meta[1];
+        if ((uint32_t)(shift >> 3) >= npass) return;  // the whole grid: nothing left to sort
+        if (npass & 1u) {
+            const uint32_t* kt = kin;
+            kin = kout;
+            kout = const_cast<uint32_t*>(kt);
+            const uint64_t* vt = vin;
+            vin = vout;
+            vout = const_cast<uint64_t*>(vt);
+        }
+    }
     __shared__ uint32_t s_keys[kTileKeys];
     __shared__ uint64_t s_vals[kTileKeys];
     __shared__ uint32_t cnt[kSortWaves][kRadix];
@@ -126,6 +196,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
     __shared__ uint32_t s_scan[kSortWaves];
     __shared__ uint32_t s_later[FROMX ? (kPasses - 1) * kRadix : 1];
     __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_kmin[FROMX ? kSortWaves : 1], s_kmax[FROMX ? kSortWaves : 1];
 
     // Tiles are taken in ticket order unless the whole grid is resident at once
     // (then every block runs concurrently and its index serves, sparing 1 atomic
@@ -161,6 +232,37 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
             xv[r] = i < n ? x[i] : 0.0;
             yv[r] = (y && i < n) ? y[i] : 0.0;
         }
+        // least and largest key over all tiles (the zeroing kernel's ranges)
+        {
+            const uint64_t pw = threadIdx.x < gridDim.x ? part[threadIdx.x] : 0x00000000FFFFFFFFull;
+            uint32_t mn = (uint32_t)pw, mx = (uint32_t)(pw >> 32);
+#pragma unroll
+            for (int dd = 1; dd < kWave; dd <<= 1) {
+                const uint32_t on = __shfl_xor(mn, dd, kWave), ox = __shfl_xor(mx, dd, kWave);
+                mn = on < mn ? on : mn;
+                mx = ox > mx ? ox : mx;
+            }
+            if (lane == 0) {
+                s_kmin[wave] = mn;
+                s_kmax[wave] = mx;
+            }
+        }
+        __syncthreads();
+        uint32_t kmin = s_kmin[0], kmax = s_kmax[0];
+#pragma unroll
+        for (int w = 1; w < kSortWaves; ++w) {
+            kmin = s_kmin[w] < kmin ? s_kmin[w] : kmin;
+            kmax = s_kmax[w] > kmax ? s_kmax[w] : kmax;
+        }
+        const uint32_t npass = passes_for(kmax - kmin);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            meta[0] = kmin;
+            meta[1] = npass;
+        }
+        if (npass & 1u) {  // the last pass writes the input arrays
+            kout = const_cast<uint32_t*>(kin);
+            vout = const_cast<uint64_t*>(vin);
+        }
         bool bad = false;
 #pragma unroll
         for (int r = 0; r < kKeysPerLane; ++r) {
@@ -173,6 +275,7 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
                 const double z = node_z(xv[r], y != nullptr, yv[r], &ok);
                 bad = bad || !ok;
                 split_key(z, i, &k[r], &v[r]);
+                k[r] -= kmin;
             }
             count_key_digits(s_later, k[r], valid, 1, kPasses);
         }
@@ -371,8 +474,11 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(const uint32_t* __res
         const uint32_t dd = (key >> shift) & (kRadix - 1);
         const uint32_t pos = s_goff[dd] + (uint32_t)i;
         if (pos < (uint64_t)n) {  // always, unless a look-back gave up (then the error is raised)
-            kout[pos] = key;
-            vout[pos] = s_vals[i];
+            // device-scope stores: written through to the device's coherence
+            // point, so the kernel's end has no dirty L2 lines to write back
+            // (the next pass starts ~1.5 us sooner after 12 MB)
+            __hip_atomic_store(&kout[pos], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&vout[pos], s_vals[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -876,6 +982,8 @@ struct SortScratch {
     uint32_t* bits;
     uint64_t* dtot;  // the first pass's digit totals when it prepares its own keys
     int32_t* err;
+    uint64_t* part;  // per tile: the range of the keys a first pass will make
+    uint32_t* meta;  // {least key, passes} of a first pass that made its keys
     int64_t words;  // u64 words to zero
 };
 
@@ -887,6 +995,8 @@ SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) {
     const int64_t bit_words = tie_words(n) / 2;
     uint64_t* block = ar.take<uint64_t>(status_words + hist_words + bit_words + kRadix);
     int32_t* err = ar.take<int32_t>(1);
+    uint64_t* part = ar.take<uint64_t>(nb);
+    uint32_t* meta = ar.take<uint32_t>(2);
     *ok = !ar.overflow;
     SortScratch s{};
     if (!*ok) return s;
@@ -896,6 +1006,8 @@ SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) {
     s.bits = reinterpret_cast<uint32_t*>(block + status_words + hist_words);
     s.dtot = block + status_words + hist_words + bit_words;
     s.err = err;
+    s.part = part;
+    s.meta = meta;
     s.words = status_words + hist_words + bit_words + kRadix;
     return s;
 }
@@ -914,11 +1026,13 @@ size_t radix_workspace_bytes(int64_t n) {
     s.take<uint64_t>((size_t)kPasses * sort_blocks(n) * kRadix + kHistCopies * kPasses * kRadix / 2 + kPasses +
                      tie_words(n) / 2 + kRadix);
     s.take<int32_t>(1);
+    s.take<uint64_t>(sort_blocks(n));
+    s.take<uint32_t>(2);
     return s.used + 256;
 }
 
 mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, hipStream_t stream,
-                        ZeroRange e1, ZeroRange e2) {
+                        ZeroRange e1, ZeroRange e2, const double* x, const double* y) {
     bool ok = false;
     SortScratch s = sort_scratch(ws, ws_bytes, n, &ok);
     if (!ok) return MH_EWORKSPACE;
@@ -928,8 +1042,13 @@ mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, h
     most = most > e2.n ? most : e2.n;
     int64_t blocks = (most + kSortThreads - 1) / kSortThreads;
     if (blocks > 1024) blocks = 1024;
+    KeySpan ks{};
+    if (x && radix_prepares_keys(n)) {
+        ks = KeySpan{x, y, n, s.part};
+        if (blocks < sort_blocks(n)) blocks = sort_blocks(n);
+    }
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), dim3(kSortThreads), 0, stream,
-                       ZeroRange{s.status, s.words}, e1, e2);
+                       ZeroRange{s.status, s.words}, e1, e2, ks);
     MH_HIP_TRY(hipGetLastError());
     *hist = s.hist;
     return MH_OK;
@@ -939,7 +1058,8 @@ bool radix_prepares_keys(int64_t n) { return n > 1 && n <= (int64_t)0xFFFFFFFFll
 
 mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint64_t* pay_alt, int64_t n,
                              void* ws, size_t ws_bytes, int32_t* err, hipStream_t stream, const double* x,
-                             const double* y) {
+                             const double* y, const uint32_t** kbase) {
+    if (kbase) *kbase = nullptr;
     if (n <= 1) return MH_OK;
     if (n > (int64_t)0xFFFFFFFFll) return MH_EINVAL;
     bool ok = false;
@@ -951,6 +1071,9 @@ mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint
     // ticket unless the whole grid is resident
     const bool xchg = use_exchange(n);
     if (x && !xchg) return MH_EINVAL;  // keys from x need the exchange (radix_prepares_keys)
+    // a first pass making its keys sets the pass count, which the later passes read
+    uint32_t* meta = x ? s.meta : nullptr;
+    if (kbase) *kbase = meta;
     const bool use_ticket = !xchg && nb > resident_blocks(k_onesweep<false, false>, kSortThreads);
     uint32_t* kin = hi;
     uint64_t* vin = pay;
@@ -961,11 +1084,13 @@ mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint
                          : k_onesweep<false, false>;
         hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, kin, vin, kout, vout, n, pass * 8,
                            s.hist + pass * kRadix, s.status + (int64_t)pass * nb * kRadix, s.tickets + pass,
-                           use_ticket, err, x, y, s.hist, s.dtot);
+                           use_ticket, err, x, y, s.hist, s.dtot, meta, (const uint64_t*)s.part);
         MH_HIP_TRY(hipGetLastError());
         uint32_t* tk = kin; kin = kout; kout = tk;
         uint64_t* tv = vin; vin = vout; vout = tv;
     }
+    // 4 passes end in the input arrays; a first pass that sets an odd count
+    // swaps the arrays of every pass, with the same result
     static_assert(kPasses % 2 == 0, "the passes end in the input arrays");
     // runs of equal high halves out of order by the low halves
     const int64_t cus = device_cus();

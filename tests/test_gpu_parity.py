@@ -68,6 +68,47 @@ def test_order_matches_oracle(mh, n):
     assert np.array_equal(zs.cpu().numpy(), x[ref])
 
 
+def _spread_passes(z):
+    hi = (np.asarray(z, np.float64).view(np.uint64) >> np.uint64(32)).astype(np.int64)
+    spread = int(hi.max() - hi.min())
+    return 1 if spread < 1 << 8 else 2 if spread < 1 << 16 else 3 if spread < 1 << 24 else 4
+
+
+@pytest.mark.parametrize("passes", [1, 2, 3, 4])
+@pytest.mark.parametrize("n", [5000, 300_000, 1_048_576])
+def test_order_every_pass_count_matches_oracle(mh, passes, n):
+    # the sort takes the keys less their least and as many 8-bit passes as
+    # their spread needs (an odd count swaps every pass's arrays): keys whose
+    # high halves span 8, 16, 24 and 32 bits, ties among them
+    rng = np.random.default_rng(passes * 7 + n)
+    width = {1: 2.0 ** -13, 2: 2.0 ** -5, 3: 2.0 ** 3, 4: None}[passes]
+    if width is None:
+        x = rng.lognormal(-2, 1.5, n)
+        x[rng.integers(0, n, n // 100)] = 0.0
+    else:
+        x = 0.75 * (1.0 + rng.uniform(0.0, 1.0, n) * width) if passes < 3 else np.exp2(rng.uniform(-7.9, 0.0, n))
+    x[rng.integers(0, n, n // 10)] = x[rng.integers(0, n, n // 10)]  # ties
+    assert _spread_passes(x) == passes
+    perm, zs, _, status = mh.order(dev(x))
+    assert int(status.item()) == 0
+    ref = oracle.order(x)
+    assert np.array_equal(perm.cpu().numpy(), ref)
+    assert np.array_equal(zs.cpu().numpy(), x[ref])
+    if n == 5000:
+        # the same through the sampler (node records with the column masses)
+        # and weighted (z = fl(x y), the spread of the products)
+        src, dst = mh.sample_unweighted(dev(x * 0.02), seed=3, replica=passes, seg_work=8)
+        ora = oracle.sample_mh(x * 0.02, None, seed=3, replica=passes, seg_work=8)
+        parity.edge_divergences(src.cpu().numpy(), dst.cpu().numpy(), None, ora.src, ora.dst, None, n,
+                                ora.tie_rows, label=f"sample after {passes} sort passes")
+        y = np.full(n, 0.5)
+        perm, zs, ys, status = mh.order(dev(x), dev(y))
+        ref, zref, yref, _ = oracle.sorted_params(x, y)
+        assert _spread_passes(zref) == passes
+        assert np.array_equal(perm.cpu().numpy(), ref)
+        assert np.array_equal(zs.cpu().numpy(), zref)
+
+
 def test_order_beyond_count_tiles_matches_oracle(mh):
     # more tiles of 4096 keys than blocks resident at once: the sort's blocks
     # take their tiles by ticket
