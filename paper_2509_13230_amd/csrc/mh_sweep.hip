@@ -285,6 +285,7 @@ __global__ __launch_bounds__(kHrThreads) void k_heavy_records(NetDesc D, HeavyRe
                                                             const int32_t* status) {
     __shared__ uint64_t s_p[kHrSamples];
     __shared__ uint64_t s_h[kHrRows + 1];
+    __shared__ int32_t s_a[kHrThreads];
     if (*status != 0) return;
     const int64_t H = heavy_items(D);
     const int64_t lim = H < D.rec_cap ? H : D.rec_cap;
@@ -306,7 +307,7 @@ __global__ __launch_bounds__(kHrThreads) void k_heavy_records(NetDesc D, HeavyRe
     stage_lds<4>(s_p, np, [=](int64_t j) { return Psamp[j * pstep]; });
     for (int64_t round = blockIdx.x; round * kHrThreads < lim; round += gridDim.x) {
         const int64_t R0 = hbrow[round];
-        __syncthreads();  // s_h of the previous round is no longer read
+        __syncthreads();  // s_h and s_a of the previous round are no longer read
         const uint64_t* hoff = D.hoff;
         stage_lds<5>(s_h, kHrRows + 1, [=](int64_t j) {
             const uint64_t v = hoff[R0 + j <= n ? R0 + j : n];  // loaded unconditionally
@@ -314,77 +315,86 @@ __global__ __launch_bounds__(kHrThreads) void k_heavy_records(NetDesc D, HeavyRe
         });
         __syncthreads();
         const int64_t it = round * kHrThreads + threadIdx.x;
-        if (it >= lim) continue;
-        // row: hoff[r] <= it < hoff[r + 1], from the staged rows R0 .. R0 + kHrRows
-        int rl = 1, ru = kHrRows + 1;  // first staged index with hoff > it (s_h[0] <= it)
-        while (rl < ru) {
-            const int mid = (rl + ru) >> 1;
-            if (s_h[mid] > (uint64_t)it) ru = mid; else rl = mid + 1;
-        }
-        int64_t r, g, nsg;
-        if (rl <= kHrRows) {
-            r = R0 + rl - 1;
-            g = it - (int64_t)s_h[rl - 1];
-            nsg = (int64_t)(s_h[rl] - s_h[rl - 1]);
-        } else {  // a round spread over more rows than staged (rows without items in between)
-            r = first_above_u64(D.hoff, R0 + kHrRows, n + 1, (uint64_t)it) - 1;
-            g = it - (int64_t)D.hoff[r];
-            nsg = (int64_t)(D.hoff[r + 1] - D.hoff[r]);
-        }
-        const int64_t J = D.jend[r];
-        const int64_t first = bip ? 0 : r + 1;
-        const int64_t nd = (J - first + T - 1) / T;
-        int64_t a, b;
-        if (g < nd) {
-            a = first + g * T;
-            b = a + T < J ? a + T : J;
-        } else {
-            const int64_t kk = g - nd;
-            const int64_t ns = nsg - nd;
-            const uint64_t pb = D.P[J];
-            const uint64_t m = D.mq[r];
-            // The segment's two cuts: first j in [J, nc) with P[j] >= v (nc if
-            // none), v = pb + k m for k = kk, kk + 1; the first cut of the row
-            // is J and the last nc.  Both searches advance in lockstep, so
-            // their dependent loads overlap: bracket from the LDS samples,
-            // P[(q-1) ps] < v <= P[q ps], then binary search in global memory.
-            int64_t lo[2], hi[2];
-            uint64_t v[2];
+        const bool active = it < lim;
+        int64_t r = 0, g = 0, nsg = 0, a = 0, b = 0;
+        bool b_next = false;  // b is the next item's a (the next thread's search)
+        if (active) {
+            // row: hoff[r] <= it < hoff[r + 1], from the staged rows R0 .. R0 + kHrRows
+            int rl = 1, ru = kHrRows + 1;  // first staged index with hoff > it (s_h[0] <= it)
+            while (rl < ru) {
+                const int mid = (rl + ru) >> 1;
+                if (s_h[mid] > (uint64_t)it) ru = mid; else rl = mid + 1;
+            }
+            if (rl <= kHrRows) {
+                r = R0 + rl - 1;
+                g = it - (int64_t)s_h[rl - 1];
+                nsg = (int64_t)(s_h[rl] - s_h[rl - 1]);
+            } else {  // a round spread over more rows than staged (rows without items in between)
+                r = first_above_u64(D.hoff, R0 + kHrRows, n + 1, (uint64_t)it) - 1;
+                g = it - (int64_t)D.hoff[r];
+                nsg = (int64_t)(D.hoff[r + 1] - D.hoff[r]);
+            }
+            const int64_t J = D.jend[r];
+            const int64_t first = bip ? 0 : r + 1;
+            const int64_t nd = (J - first + T - 1) / T;
+            if (g < nd) {
+                a = first + g * T;
+                b = a + T < J ? a + T : J;
+            } else {
+                const int64_t kk = g - nd;
+                const int64_t ns = nsg - nd;
+                const uint64_t pb = D.P[J];
+                const uint64_t m = D.mq[r];
+                // The segment's two cuts: first j in [J, nc) with P[j] >= v (nc if
+                // none), v = pb + k m for k = kk, kk + 1; the first cut of the row
+                // is J and the last nc.  The second is the next item's first when
+                // that item (same row) is this round's next thread; otherwise both
+                // searches advance in lockstep, so their dependent loads overlap:
+                // bracket from the LDS samples, P[(q-1) ps] < v <= P[q ps], then a
+                // binary search in global memory.
+                b_next = kk + 1 < ns && threadIdx.x + 1 < kHrThreads && it + 1 < lim;
+                int64_t lo[2], hi[2];
+                uint64_t v[2];
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int64_t k2 = kk + e;
-                v[e] = pb + (uint64_t)k2 * m;
-                if ((e == 0 && k2 == 0) || (e == 1 && k2 == ns)) {
-                    lo[e] = hi[e] = (e == 0) ? J : nc;
-                    continue;
+                for (int e = 0; e < 2; ++e) {
+                    const int64_t k2 = kk + e;
+                    v[e] = pb + (uint64_t)k2 * m;
+                    if ((e == 0 && k2 == 0) || (e == 1 && (k2 == ns || b_next))) {
+                        lo[e] = hi[e] = (e == 0) ? J : nc;
+                        continue;
+                    }
+                    int ql = 0, qh = (int)np;
+                    while (ql < qh) {
+                        const int mid = (ql + qh) >> 1;
+                        if (s_p[mid] >= v[e]) qh = mid; else ql = mid + 1;
+                    }
+                    int64_t clo = J, chi = nc;
+                    if (ql > 0 && (int64_t)(ql - 1) * ps + 1 > clo) clo = (int64_t)(ql - 1) * ps + 1;
+                    if (ql < (int)np && (int64_t)ql * ps < chi) chi = (int64_t)ql * ps;
+                    if (clo > nc) clo = nc;
+                    if (chi < clo) chi = clo;
+                    lo[e] = clo;
+                    hi[e] = chi;
                 }
-                int ql = 0, qh = (int)np;
-                while (ql < qh) {
-                    const int mid = (ql + qh) >> 1;
-                    if (s_p[mid] >= v[e]) qh = mid; else ql = mid + 1;
+                while (lo[0] < hi[0] || lo[1] < hi[1]) {
+                    const int64_t m0 = lo[0] + (hi[0] - lo[0]) / 2, m1 = lo[1] + (hi[1] - lo[1]) / 2;
+                    const bool a0 = lo[0] < hi[0], a1 = lo[1] < hi[1];
+                    const uint64_t p0 = a0 ? D.P[m0] : 0, p1 = a1 ? D.P[m1] : 0;
+                    if (a0) {
+                        if (p0 >= v[0]) hi[0] = m0; else lo[0] = m0 + 1;
+                    }
+                    if (a1) {
+                        if (p1 >= v[1]) hi[1] = m1; else lo[1] = m1 + 1;
+                    }
                 }
-                int64_t clo = J, chi = nc;
-                if (ql > 0 && (int64_t)(ql - 1) * ps + 1 > clo) clo = (int64_t)(ql - 1) * ps + 1;
-                if (ql < (int)np && (int64_t)ql * ps < chi) chi = (int64_t)ql * ps;
-                if (clo > nc) clo = nc;
-                if (chi < clo) chi = clo;
-                lo[e] = clo;
-                hi[e] = chi;
+                a = lo[0];
+                b = lo[1];
             }
-            while (lo[0] < hi[0] || lo[1] < hi[1]) {
-                const int64_t m0 = lo[0] + (hi[0] - lo[0]) / 2, m1 = lo[1] + (hi[1] - lo[1]) / 2;
-                const bool a0 = lo[0] < hi[0], a1 = lo[1] < hi[1];
-                const uint64_t p0 = a0 ? D.P[m0] : 0, p1 = a1 ? D.P[m1] : 0;
-                if (a0) {
-                    if (p0 >= v[0]) hi[0] = m0; else lo[0] = m0 + 1;
-                }
-                if (a1) {
-                    if (p1 >= v[1]) hi[1] = m1; else lo[1] = m1 + 1;
-                }
-            }
-            a = lo[0];
-            b = lo[1];
         }
+        s_a[threadIdx.x] = (int32_t)a;
+        __syncthreads();
+        if (!active) continue;
+        if (b_next) b = s_a[threadIdx.x + 1];
         rec[it] = HeavyRec{(int32_t)r, (int32_t)g, (int32_t)a, (int32_t)b};
     }
 }
