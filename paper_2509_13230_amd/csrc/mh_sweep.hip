@@ -58,33 +58,71 @@ __global__ void k_init_counters(Counters* c) {
 // search for J takes its bracket from LDS and ends with log2(zstep) loads.
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanSamples = 4096;
+// z of the columns right after a tile's first row, staged with the samples:
+// the dense part of a hub row ends within a few thousand columns (J is where
+// s z_j drops below c_r, and only the largest z reach that far), so most
+// searches for J end in LDS.
+constexpr int kPlanHead = 4096;
 
 // z of every zstep-th column into LDS (zstep: the smallest power of two >= 256
 // that leaves at most kPlanSamples samples); returns zstep, sets *nz.  From
 // zsamp (z[256 k], contiguous) when given: a gather of one record per 4 KB
-// page costs an address translation each.
+// page costs an address translation each.  With s_zh, also z of the columns
+// [h0, h0 + nh) (nh = min(kPlanHead, nc - h0)), all loads in flight together.
 __device__ __forceinline__ int64_t stage_col_samples(const NodeRec* __restrict__ col, const double* zsamp,
-                                                     int64_t nc, double* s_z, int64_t* nz) {
+                                                     int64_t nc, double* s_z, int64_t* nz, double* s_zh = nullptr,
+                                                     int64_t h0 = 0, int64_t* nh = nullptr) {
     int64_t zstep = 256;
     while ((nc - 1) / zstep + 1 > kPlanSamples) zstep *= 2;
     *nz = (nc - 1) / zstep + 1;
-    static_assert(kPlanSamples <= 4 * kPlanThreads, "four samples per thread");
+    static_assert(kPlanSamples <= 4 * kPlanThreads && kPlanHead <= 4 * kPlanThreads, "four values per thread");
     const int64_t sstep = zstep >> kSampleShift;
-    if (zsamp) stage_lds<4>(s_z, *nz, [=](int64_t q) { return zsamp[q * sstep]; });
-    else stage_lds<4>(s_z, *nz, [=](int64_t q) { return col[q * zstep].z; });
+    const int64_t cnt = *nz;
+    const int64_t hcnt = s_zh ? (nc - h0 < kPlanHead ? nc - h0 : kPlanHead) : 0;
+    if (nh) *nh = hcnt > 0 ? hcnt : 0;
+    double v[4], w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t j = threadIdx.x + (int64_t)q * blockDim.x;
+        const int64_t jj = j < cnt ? j : cnt - 1;
+        v[q] = zsamp ? zsamp[jj * sstep] : col[jj * zstep].z;
+        const int64_t k = j < hcnt ? j : (hcnt > 0 ? hcnt - 1 : 0);
+        w[q] = hcnt > 0 ? col[h0 + k].z : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t j = threadIdx.x + (int64_t)q * blockDim.x;
+        if (j < cnt) s_z[j] = v[q];
+        if (j < hcnt) s_zh[j] = w[q];
+    }
     return zstep;
 }
 
 // J of a row with a dense part: first j in [first + 1, nc) with s z_j < cr
-// (nc if none), bracketed by the LDS samples, then a binary search.
+// (nc if none).  Within the staged head columns [h0, h0 + nh) when it lies
+// there (a binary search in LDS), else bracketed by the LDS samples and found
+// by a binary search in global memory.
 __device__ __forceinline__ int64_t dense_end(const NodeRec* __restrict__ col, int64_t nc, double s, double cr,
-                                             int64_t first, const double* s_z, int64_t nz, int64_t zstep) {
+                                             int64_t first, const double* s_z, int64_t nz, int64_t zstep,
+                                             const double* s_zh, int64_t h0, int64_t nh) {
+    int64_t from = first + 1;
+    if (nh > 0 && from >= h0 && from < h0 + nh) {
+        if (h0 + nh == nc || s * s_zh[nh - 1] < cr) {
+            int lo = (int)(from - h0), hi = (int)nh;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s * s_zh[mid] < cr) hi = mid; else lo = mid + 1;
+            }
+            return h0 + lo;
+        }
+        from = h0 + nh;  // s z_j >= cr over the whole window
+    }
     int ql = 0, qh = (int)nz;  // first sample where s z < cr
     while (ql < qh) {
         const int mid = (ql + qh) >> 1;
         if (s * s_z[mid] < cr) qh = mid; else ql = mid + 1;
     }
-    int64_t lo = first + 1;
+    int64_t lo = from;
     if (ql > 0 && (int64_t)(ql - 1) * zstep + 1 > lo) lo = (int64_t)(ql - 1) * zstep + 1;
     int64_t hi = nc;  // s z < cr holds at hi (or hi = nc)
     if (ql < (int)nz) hi = (int64_t)ql * zstep > lo ? (int64_t)ql * zstep : lo;
@@ -157,7 +195,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_row_plan(NodeRec* __restrict__
         int64_t nz;
         const int64_t zstep = stage_col_samples(col, zsamp, nc, s_z, &nz);
         __syncthreads();
-        if (dense) J = dense_end(col, nc, s, cr, first, s_z, nz, zstep);
+        if (dense) J = dense_end(col, nc, s, cr, first, s_z, nz, zstep, nullptr, 0, 0);
     }
     if (!in) return;
     const int64_t total = plan_row(node, r, s, cr, first, J, active, nc, T, P, jend, mq);
@@ -183,6 +221,7 @@ __global__ __launch_bounds__(kLbThreads) void k_row_plan_scan(NodeRec* __restric
                                                               int64_t rec_cap, int32_t* err) {
     __shared__ LbShared sh;
     __shared__ double s_z[kPlanSamples];
+    __shared__ double s_zh[kPlanHead];
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int64_t base = tile * kLbTile;
         double s[kLbItems], cr[kLbItems];
@@ -208,12 +247,13 @@ __global__ __launch_bounds__(kLbThreads) void k_row_plan_scan(NodeRec* __restric
             any = any || dense[k];
         }
         if (__syncthreads_or(any)) {
-            int64_t nz;
-            const int64_t zstep = stage_col_samples(col, zsamp, nc, s_z, &nz);
+            int64_t nz, nh;
+            const int64_t h0 = bip ? 0 : (base + 1 < nc ? base + 1 : nc);
+            const int64_t zstep = stage_col_samples(col, zsamp, nc, s_z, &nz, s_zh, h0, &nh);
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < kLbItems; ++k)
-                if (dense[k]) J[k] = dense_end(col, nc, s[k], cr[k], J[k], s_z, nz, zstep);
+                if (dense[k]) J[k] = dense_end(col, nc, s[k], cr[k], J[k], s_z, nz, zstep, s_zh, h0, nh);
         }
         uint64_t cnt[kLbItems];
 #pragma unroll

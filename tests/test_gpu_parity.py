@@ -429,6 +429,20 @@ def test_full_size_unweighted_matches_oracle(mh):
         compare_edges((src, dst), ora, len(x), ora.tie_rows)
 
 
+@pytest.mark.parametrize("head", [3000, 4600])
+def test_dense_rows_within_and_beyond_the_staged_columns(mh, head):
+    # rows whose dense part (s z_j >= 1) ends within the 4096 columns after
+    # the tile's first row, which the plan stages in LDS, or beyond them
+    rng = np.random.default_rng(head)
+    n = 12_000
+    x = np.concatenate([np.full(head, 1.1) * (1 + rng.uniform(0, 1e-3, head)), rng.lognormal(-5, 1, n - head)])
+    rng.shuffle(x)
+    for seg_work in (8, 64):
+        src, dst = mh.sample_unweighted(dev(x), seed=5, replica=head, seg_work=seg_work)
+        ora = oracle.sample_mh(x, None, seed=5, replica=head, seg_work=seg_work)
+        compare_edges((src, dst), ora, n, ora.tie_rows, label=f"dense head {head}, seg_work {seg_work}")
+
+
 def test_full_size_fitted_unweighted_matches_oracle(mh):
     # the timed workload itself: N = 1,000,000 power-law targets (2.1 on
     # [1, 1e4]) with x fitted on the CPU by the class-compressed fixed point (one
