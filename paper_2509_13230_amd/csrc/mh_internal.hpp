@@ -109,12 +109,15 @@ mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, h
 // only need to be zero; allowed when radix_prepares_keys(n), with the same x
 // and y given to radix_prepare.  The keys are then sorted less their least
 // value (*kbase, a device word, receives it: hi ends as key >> 32 minus
-// *kbase) by as many passes as their spread needs; otherwise *kbase is null.
+// *kbase) by as many passes as their spread needs, and *tile_mass receives
+// the column masses floor(z 2^32) summed per tile of 4096 nodes (device, one
+// word per tile: their total is the masses' sum in any order); otherwise both
+// are null.
 bool radix_prepares_keys(int64_t n);
 mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint64_t* pay_alt, int64_t n,
                              void* ws, size_t ws_bytes, int32_t* err, hipStream_t stream,
                              const double* x = nullptr, const double* y = nullptr,
-                             const uint32_t** kbase = nullptr);
+                             const uint32_t** kbase = nullptr, const uint64_t** tile_mass = nullptr);
 
 // ---- sampler pieces ----
 struct SortedView {
@@ -125,6 +128,14 @@ struct SortedView {
 };
 
 size_t order_workspace_bytes(int64_t n);
+// The sorted order before records are made from it (see order_nodes).
+struct SortedKeys {
+    const uint32_t* keys = nullptr;       // high halves of the sort keys, less *kbase
+    const uint64_t* vals = nullptr;       // low half << 32 | node id
+    const uint32_t* kbase = nullptr;      // device word
+    const uint64_t* tile_mass = nullptr;  // column masses summed per tile of 4096 nodes (input order)
+    int64_t tiles = 0;
+};
 // Writes the order either as packed records (node != null: z and id; nseg is
 // left for the plan) or as separate perm / zs arrays.  mass_prefix (optional,
 // n + 1 entries): P[r] = sum of the column masses floor(z 2^32) (2^32 for
@@ -134,11 +145,15 @@ size_t order_workspace_bytes(int64_t n);
 // e2), and then mass_samples (optional, lb_samples(n) words) receives
 // P[256 k] and z_samples (optional, (n - 1) / 256 + 1 values) z[256 k].  check_square: the largest z squared must be finite (one node
 // set, where it is the largest t).  e1, e2: u64 words zeroed by the first
-// kernel (look-back state of later steps, counters).
+// kernel (look-back state of later steps, counters).  sorted (optional):
+// when the sort made its keys from x (radix_prepares_keys), the order stops
+// there, leaving the sorted arrays (in ws) in *sorted for a caller that makes
+// the records itself; otherwise sorted->keys stays null and the order is
+// finished as above.
 mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm, double* zs, double* ys,
                       NodeRec* node, int32_t* status, uint64_t* mass_prefix, uint64_t* mass_state,
                       uint64_t* mass_samples, double* z_samples, void* ws, size_t ws_bytes, hipStream_t stream,
-                      bool check_square = true, ZeroRange e1 = {}, ZeroRange e2 = {});
+                      bool check_square = true, ZeroRange e1 = {}, ZeroRange e2 = {}, SortedKeys* sorted = nullptr);
 
 size_t bound_workspace_bytes(int64_t n);
 mh_status bound_suffix_top2(const double* ys, int64_t n, double* c, int32_t* status, void* ws, size_t ws_bytes,

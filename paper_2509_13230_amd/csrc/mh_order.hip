@@ -289,7 +289,8 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
                       NodeRec* node, int32_t* status, uint64_t* mass_prefix, uint64_t* mass_state,
                       uint64_t* mass_samples, double* z_samples, void* ws, size_t ws_bytes, hipStream_t stream,
                       bool check_square,
-                      ZeroRange e1, ZeroRange e2) {
+                      ZeroRange e1, ZeroRange e2, SortedKeys* sorted) {
+    if (sorted) *sorted = SortedKeys{};
     if (n <= 0) return MH_OK;
     Arena ar(ws, ws_bytes);
     uint32_t* keys = ar.take<uint32_t>(n);
@@ -313,9 +314,14 @@ mh_status order_nodes(const double* x, const double* y, int64_t n, int32_t* perm
         MH_HIP_TRY(hipGetLastError());
     }
     const uint32_t* kbase = nullptr;  // the keys' least high half, when the sort subtracted it
+    const uint64_t* tile_mass = nullptr;
     st = radix_sort_split64(keys, vals, keys_alt, vals_alt, n, sort_ws, sort_bytes, status, stream,
-                            fused ? x : nullptr, y, &kbase);
+                            fused ? x : nullptr, y, &kbase, &tile_mass);
     if (st != MH_OK) return st;
+    if (sorted && kbase && tile_mass) {
+        *sorted = SortedKeys{keys, vals, kbase, tile_mass, (n + kPrepTile - 1) / kPrepTile};
+        return MH_OK;
+    }
     if (mass_prefix && node && n <= (int64_t)1 << 30) {
         // records and the masses' prefix sums in one pass (sums stay below 2^62)
         const int64_t tiles = lb_tiles(n);

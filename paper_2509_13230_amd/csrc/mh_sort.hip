@@ -104,11 +104,14 @@ struct KeySpan {
     const double* x = nullptr;
     const double* y = nullptr;
     int64_t n = 0;
-    uint64_t* part = nullptr;  // tile t: largest << 32 | least
+    uint64_t* part = nullptr;  // tile t: largest << 32 | least; part[tiles + t]: the tile's column mass
+    int64_t tiles = 0;
 };
 
 // Zeroes three ranges of u64 words (any may be empty); with a key span, block
-// t < tiles also writes the range of tile t's keys (the grid covers both).
+// t < tiles also writes the range of tile t's keys and the sum of their column
+// masses floor(z 2^32) (the total over all tiles does not depend on the
+// order; the grid covers both jobs).
 __global__ __launch_bounds__(kSortThreads) void k_zero_u64(ZeroRange a, ZeroRange b, ZeroRange c, KeySpan ks) {
     const int64_t stride = (int64_t)gridDim.x * kSortThreads;
     const int64_t t = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
@@ -118,7 +121,9 @@ __global__ __launch_bounds__(kSortThreads) void k_zero_u64(ZeroRange a, ZeroRang
     const int64_t base = (int64_t)blockIdx.x * kTileKeys;
     if (!ks.x || base >= ks.n) return;  // uniform over the block
     __shared__ uint32_t s_mn[kSortWaves], s_mx[kSortWaves];
+    __shared__ uint64_t s_ms[kSortWaves];
     uint32_t mn = ~0u, mx = 0u;
+    uint64_t ms = 0;
 #pragma unroll
     for (int q = 0; q < kKeysPerLane; ++q) {
         const int64_t i = base + (int64_t)q * kSortThreads + threadIdx.x;
@@ -128,6 +133,7 @@ __global__ __launch_bounds__(kSortThreads) void k_zero_u64(ZeroRange a, ZeroRang
             const uint32_t h = (uint32_t)(desc_key(z) >> 32);
             mn = h < mn ? h : mn;
             mx = h > mx ? h : mx;
+            ms += mass_q(z);
         }
     }
 #pragma unroll
@@ -135,19 +141,23 @@ __global__ __launch_bounds__(kSortThreads) void k_zero_u64(ZeroRange a, ZeroRang
         const uint32_t on = __shfl_xor(mn, d, kWave), ox = __shfl_xor(mx, d, kWave);
         mn = on < mn ? on : mn;
         mx = ox > mx ? ox : mx;
+        ms += __shfl_xor(ms, d, kWave);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
         s_mn[wave] = mn;
         s_mx[wave] = mx;
+        s_ms[wave] = ms;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < kSortWaves; ++w) {
             mn = s_mn[w] < mn ? s_mn[w] : mn;
             mx = s_mx[w] > mx ? s_mx[w] : mx;
+            ms += s_ms[w];
         }
         ks.part[blockIdx.x] = ((uint64_t)mx << 32) | mn;
+        ks.part[ks.tiles + blockIdx.x] = ms;
     }
 }
 
@@ -995,7 +1005,7 @@ SortScratch sort_scratch(void* ws, size_t ws_bytes, int64_t n, bool* ok) {
     const int64_t bit_words = tie_words(n) / 2;
     uint64_t* block = ar.take<uint64_t>(status_words + hist_words + bit_words + kRadix);
     int32_t* err = ar.take<int32_t>(1);
-    uint64_t* part = ar.take<uint64_t>(nb);
+    uint64_t* part = ar.take<uint64_t>(2 * nb);
     uint32_t* meta = ar.take<uint32_t>(2);
     *ok = !ar.overflow;
     SortScratch s{};
@@ -1026,7 +1036,7 @@ size_t radix_workspace_bytes(int64_t n) {
     s.take<uint64_t>((size_t)kPasses * sort_blocks(n) * kRadix + kHistCopies * kPasses * kRadix / 2 + kPasses +
                      tie_words(n) / 2 + kRadix);
     s.take<int32_t>(1);
-    s.take<uint64_t>(sort_blocks(n));
+    s.take<uint64_t>(2 * sort_blocks(n));
     s.take<uint32_t>(2);
     return s.used + 256;
 }
@@ -1044,7 +1054,7 @@ mh_status radix_prepare(void* ws, size_t ws_bytes, int64_t n, uint32_t** hist, h
     if (blocks > 1024) blocks = 1024;
     KeySpan ks{};
     if (x && radix_prepares_keys(n)) {
-        ks = KeySpan{x, y, n, s.part};
+        ks = KeySpan{x, y, n, s.part, sort_blocks(n)};
         if (blocks < sort_blocks(n)) blocks = sort_blocks(n);
     }
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), dim3(kSortThreads), 0, stream,
@@ -1058,8 +1068,9 @@ bool radix_prepares_keys(int64_t n) { return n > 1 && n <= (int64_t)0xFFFFFFFFll
 
 mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint64_t* pay_alt, int64_t n,
                              void* ws, size_t ws_bytes, int32_t* err, hipStream_t stream, const double* x,
-                             const double* y, const uint32_t** kbase) {
+                             const double* y, const uint32_t** kbase, const uint64_t** tile_mass) {
     if (kbase) *kbase = nullptr;
+    if (tile_mass) *tile_mass = nullptr;
     if (n <= 1) return MH_OK;
     if (n > (int64_t)0xFFFFFFFFll) return MH_EINVAL;
     bool ok = false;
@@ -1074,6 +1085,7 @@ mh_status radix_sort_split64(uint32_t* hi, uint64_t* pay, uint32_t* hi_alt, uint
     // a first pass making its keys sets the pass count, which the later passes read
     uint32_t* meta = x ? s.meta : nullptr;
     if (kbase) *kbase = meta;
+    if (tile_mass && x) *tile_mass = s.part + nb;
     const bool use_ticket = !xchg && nb > resident_blocks(k_onesweep<false, false>, kSortThreads);
     uint32_t* kin = hi;
     uint64_t* vin = pay;

@@ -285,6 +285,205 @@ __global__ __launch_bounds__(kLbThreads) void k_row_plan_scan(NodeRec* __restric
     }
 }
 
+// ---- node records, column masses and row plan in one pass (one unweighted node set) ----
+// Made from the sorted keys directly: each tile of 4096 ranks makes its ranks'
+// z and id, scans their column masses (look-back 1: P), plans its rows from z
+// held in LDS, scans the heavy-item counts (look-back 2: hoff) and writes each
+// node record once, segment count included.  P[n], which every row's plan
+// needs, is the zeroing kernel's per-tile mass sums added up (their total does
+// not depend on the order).  J of a dense row is searched over the tile's
+// ranks and the next tile's first one in LDS, else in the sorted keys beyond;
+// P at such a J waits (bounded spin) for the inclusive prefix through the
+// tile before J's and adds the masses up to J, so every tile must be resident
+// (one block each).
+__device__ __forceinline__ double sorted_rank_z(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ vals,
+                                                int64_t j, uint32_t kb) {
+    return key_value(((uint64_t)(keys[j] + kb) << 32) | (vals[j] >> 32));
+}
+
+// First j in [first + 1, n) with s z_j < 1 (n if none), z of ranks base ..
+// base + kLbTile in s_zt.
+__device__ __forceinline__ int64_t fused_dense_end(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ vals,
+                                                   uint32_t kb, int64_t n, int64_t base, const double* s_zt, double s,
+                                                   int64_t first) {
+    const int64_t wend = base + kLbTile + 1 < n ? base + kLbTile + 1 : n;  // staged ranks [base, wend)
+    int64_t lo = first + 1;
+    if (lo < wend) {
+        if (wend == n || s * s_zt[wend - 1 - base] < 1.0) {
+            int a = (int)(lo - base), b = (int)(wend - base);
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (s * s_zt[mid] < 1.0) b = mid; else a = mid + 1;
+            }
+            return base + a;
+        }
+        lo = wend;  // s z >= 1 over every staged rank
+    }
+    int64_t hi = n;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (s * sorted_rank_z(keys, vals, mid, kb) < 1.0) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// P[J] for base + kLbTile < J < n: the inclusive prefix through the tile
+// before J's (this tile's own end1, or another tile's published word) plus the
+// masses of the ranks from J's tile's start up to J.
+__device__ __forceinline__ uint64_t fused_prefix_beyond(const uint32_t* __restrict__ keys,
+                                                        const uint64_t* __restrict__ vals, uint32_t kb, int64_t tile,
+                                                        uint64_t end1, const uint64_t* state1, int64_t J,
+                                                        int32_t* status) {
+    const int64_t u = J / kLbTile;  // J's tile, after this one
+    uint64_t acc = end1;
+    if (u - 1 != tile) {
+        uint32_t spins = 0;
+        for (;;) {
+            const uint64_t w = __hip_atomic_load(&state1[u - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((w & ~kLbValue) == kLbInc) {
+                acc = w & kLbValue;
+                break;
+            }
+            if (++spins > kLbSpinLimit) {
+                raise_status(status, MH_EHIP);
+                acc = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    for (int64_t j = u * kLbTile; j < J; ++j) acc += mass_q(sorted_rank_z(keys, vals, j, kb));
+    return acc;
+}
+
+__global__ __launch_bounds__(kLbThreads) void k_finish_plan_scan(
+    const uint32_t* __restrict__ keys, const uint64_t* __restrict__ vals, const uint32_t* __restrict__ kbase,
+    const uint64_t* __restrict__ tile_mass, int64_t n, NodeRec* __restrict__ node, uint64_t* __restrict__ P,
+    uint64_t* __restrict__ Psamp, double* __restrict__ Zsamp, int32_t T, int32_t* __restrict__ jend,
+    uint64_t* __restrict__ mq, uint64_t* __restrict__ hoff, int64_t tiles, uint64_t* state1, uint64_t* state2,
+    int32_t* __restrict__ hbrow, int64_t rec_cap, int32_t* status) {
+    __shared__ LbShared sh;
+    __shared__ double s_zt[kLbTile + 1];
+    __shared__ uint64_t s_pt[kLbTile + 1];
+    __shared__ uint64_t s_red[kLbThreads / kWave];
+    const uint32_t kb = *kbase;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // P[n]: the per-tile mass sums added up
+    uint64_t tm = 0;
+    for (int64_t t = threadIdx.x; t < tiles; t += kLbThreads) tm += tile_mass[t];
+    tm = wave_sum(tm);
+    if (lane == 0) s_red[wave] = tm;
+    __syncthreads();
+    uint64_t Ptot = 0;
+#pragma unroll
+    for (int w = 0; w < kLbThreads / kWave; ++w) Ptot += s_red[w];
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t base = tile * kLbTile;
+        double z[kLbItems];
+        int32_t id[kLbItems];
+        // 1. z, id and column mass of the tile's ranks
+#pragma unroll
+        for (int k = 0; k < kLbItems; ++k) {
+            const int idx = k * kLbThreads + threadIdx.x;
+            const int64_t r = base + idx;
+            z[k] = 0.0;
+            id[k] = 0;
+            uint64_t m = 0;
+            if (r < n) {
+                const uint64_t v = vals[r];
+                id[k] = (int32_t)(uint32_t)v;
+                z[k] = key_value(((uint64_t)(keys[r] + kb) << 32) | (v >> 32));
+                m = mass_q(z[k]);
+                if ((r & ((1 << kSampleShift) - 1)) == 0) Zsamp[r >> kSampleShift] = z[k];
+                if (r == 0 && !isfinite(z[k] * z[k])) raise_status(status, MH_EINVAL);
+            }
+            s_zt[idx] = z[k];
+            sh.items[lb_at(idx)] = m;
+        }
+        if (threadIdx.x == 0) s_zt[kLbTile] = base + kLbTile < n ? sorted_rank_z(keys, vals, base + kLbTile, kb) : 0.0;
+        // 2. P, the exclusive prefix of the masses (look-back 1)
+        const uint64_t end1 = lb_tile_scan(sh, tile, state1, status);
+#pragma unroll
+        for (int k = 0; k < kLbItems; ++k) {
+            const int idx = k * kLbThreads + threadIdx.x;
+            const int64_t r = base + idx;
+            const uint64_t v = sh.items[lb_at(idx)];
+            s_pt[idx] = v;
+            if (r < n) {
+                P[r] = v;
+                if ((r & ((1 << kSampleShift) - 1)) == 0) Psamp[r >> kSampleShift] = v;
+            }
+        }
+        if (threadIdx.x == 0) {
+            s_pt[kLbTile] = end1;  // P at base + kLbTile
+            if (base + kLbTile >= n) {
+                P[n] = end1;
+                if ((n & ((1 << kSampleShift) - 1)) == 0) Psamp[n >> kSampleShift] = end1;
+            }
+        }
+        __syncthreads();
+        // 3. the row plan, and the records
+        uint64_t cnt[kLbItems];
+#pragma unroll
+        for (int k = 0; k < kLbItems; ++k) {
+            const int idx = k * kLbThreads + threadIdx.x;
+            const int64_t r = base + idx;
+            const int64_t first = r + 1;
+            const double s = z[k];
+            const double cr = 1.0;
+            int64_t total = 0;
+            if (r < n && first < n && s != 0.0) {
+                if (T <= 0) {
+                    total = 1;
+                } else {
+                    int64_t J = first;
+                    uint64_t PJ = s_pt[idx + 1];  // P[r + 1]
+                    if (s * s_zt[idx + 1] >= cr) {
+                        J = fused_dense_end(keys, vals, kb, n, base, s_zt, s, first);
+                        if (J < n)
+                            PJ = J <= base + kLbTile ? s_pt[J - base]
+                                                     : fused_prefix_beyond(keys, vals, kb, tile, end1, state1, J, status);
+                    }
+                    const int64_t nd = J > first ? (int64_t)((uint32_t)(J - first + T - 1) / (uint32_t)T) : 0;
+                    int64_t ns = 0;
+                    uint64_t m = 0;
+                    if (J < n) {
+                        const double md = ((double)T * cr / s) * 4294967296.0;
+                        if (!(md < 4611686018427387904.0)) m = (uint64_t)1 << 62;
+                        else if (md < 1.0) m = 1;
+                        else m = (uint64_t)md;
+                        const uint64_t mass = Ptot - PJ;
+                        ns = (mass <= m) ? 1 : (int64_t)((mass + m - 1) / m);
+                    }
+                    total = nd + ns;
+                    if (total >= 2) {
+                        jend[r] = (int32_t)J;
+                        mq[r] = m;
+                    }
+                }
+            }
+            if (r < n) node[r] = NodeRec{s, id[k], total > 0x7FFFFFFF ? 0x7FFFFFFF : (int32_t)total};
+            cnt[k] = total >= 2 ? (uint64_t)total : 0ull;
+            sh.items[lb_at(idx)] = cnt[k];
+        }
+        // 4. hoff, the exclusive prefix of the heavy-item counts (look-back 2)
+        const uint64_t end2 = lb_tile_scan(sh, tile, state2, status);
+#pragma unroll
+        for (int k = 0; k < kLbItems; ++k) {
+            const int idx = k * kLbThreads + threadIdx.x;
+            const int64_t i = base + idx;
+            if (i < n) {
+                const uint64_t v = sh.items[lb_at(idx)];
+                hoff[i] = v;
+                const uint64_t stop = v + cnt[k] < (uint64_t)rec_cap ? v + cnt[k] : (uint64_t)rec_cap;
+                for (uint64_t b = (v + kHrThreads - 1) / kHrThreads; b * kHrThreads < stop; ++b)
+                    hbrow[b] = (int32_t)i;
+            }
+        }
+        if (threadIdx.x == 0 && base + kLbTile >= n) hoff[n] = end2;
+    }
+}
+
 static mh_status launch_row_plan(NodeRec* node, const double* c, int64_t n, const NodeRec* col, const double* zsamp,
                                  int64_t nc, int32_t bip, int32_t T, const uint64_t* P, int32_t* jend, uint64_t* mq,
                                  uint64_t* hn, hipStream_t stream) {
@@ -569,11 +768,28 @@ mh_status prepare_network(const double* x, const double* y, const NetBuffers& B,
     const int64_t n = B.n;
     if (n <= 0) return MH_OK;
     const bool seg = B.T > 0;
+    // one unweighted node set, segmented, every tile resident: records, P and
+    // the row plan in one kernel from the sorted keys
+    const int64_t tiles = lb_tiles(n);
+    const bool try_fused = !B.weighted && seg && n <= (int64_t)1 << 30 && radix_prepares_keys(n) &&
+                           tiles <= resident_blocks(k_finish_plan_scan, kLbThreads);
+    SortedKeys sk;
     mh_status st = order_nodes(x, B.weighted ? y : nullptr, n, nullptr, nullptr, B.ys, B.node, status, B.P,
                                B.scan_state, B.Psamp, B.Zsamp, scratch, scratch_bytes, stream, true,
-                               ZeroRange{B.scan_state, B.scan_words}, counters);
+                               ZeroRange{B.scan_state, B.scan_words}, counters, try_fused ? &sk : nullptr);
     if (st != MH_OK) return st;
     if (ev && ev[1]) MH_HIP_TRY(hipEventRecord(ev[1], stream));
+    if (sk.keys) {
+        if (sk.tiles != tiles) return MH_EINVAL;
+        hipLaunchKernelGGL(k_finish_plan_scan, dim3((unsigned)tiles), dim3(kLbThreads), 0, stream, sk.keys, sk.vals,
+                           sk.kbase, sk.tile_mass, n, B.node, B.P, B.Psamp, B.Zsamp, B.T, B.jend, B.mq, B.hoff, tiles,
+                           B.scan_state, B.scan_state + tiles, B.hbrow, B.rec_cap, status);
+        MH_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_heavy_records, dim3(heavy_grid(B.rec_cap)), dim3(kHrThreads), 0, stream, net_desc(B),
+                           B.rec, (const uint64_t*)B.Psamp, (const int32_t*)B.hbrow, (const int32_t*)status);
+        MH_HIP_TRY(hipGetLastError());
+        return MH_OK;
+    }
     if (B.weighted) {
         st = bound_suffix_top2(B.ys, n, B.c, status, scratch, scratch_bytes, stream);
         if (st != MH_OK) return st;

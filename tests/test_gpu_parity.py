@@ -429,10 +429,12 @@ def test_full_size_unweighted_matches_oracle(mh):
         compare_edges((src, dst), ora, len(x), ora.tie_rows)
 
 
-@pytest.mark.parametrize("head", [3000, 4600])
+@pytest.mark.parametrize("head", [3000, 4600, 9000])
 def test_dense_rows_within_and_beyond_the_staged_columns(mh, head):
     # rows whose dense part (s z_j >= 1) ends within the 4096 columns after
-    # the tile's first row, which the plan stages in LDS, or beyond them
+    # the tile's first row, which the plan stages in LDS, beyond them in the
+    # next tile, or two tiles on (where the plan takes the column-mass prefix
+    # another tile publishes)
     rng = np.random.default_rng(head)
     n = 12_000
     x = np.concatenate([np.full(head, 1.1) * (1 + rng.uniform(0, 1e-3, head)), rng.lognormal(-5, 1, n - head)])
