@@ -4,7 +4,8 @@
 // prefixes, so a plan array is produced and scanned in one pass.
 //
 // Each tile publishes one word: a flag in the top two bits (1 = the tile's own
-// sum, 2 = the inclusive prefix through the tile) and the value in the low 62.
+// sum, 2 = the inclusive prefix through the tile, 3 = the same once the
+// producer has written the tile's prefixes out) and the value in the low 62.
 // Flag and value travel in one relaxed atomic, so no fence is needed between
 // them (an agent-scope release would write back the L2 of an XCD).  Prefix sums
 // must stay below 2^62.  Blocks take tiles blockIdx, blockIdx + gridDim, ...
@@ -22,6 +23,9 @@ constexpr int kLbItems = 4;
 constexpr int kLbTile = kLbThreads * kLbItems;  // 4096
 constexpr uint64_t kLbAgg = 1ull << 62;
 constexpr uint64_t kLbInc = 2ull << 62;
+// A producer may later mark its inclusive word 3: the same prefix, and the
+// tile's scanned values written out (see k_finish_plan_scan).
+constexpr uint64_t kLbDone = 3ull << 62;
 constexpr uint64_t kLbValue = kLbAgg - 1;
 constexpr uint32_t kLbSpinLimit = 1u << 20;
 
@@ -88,7 +92,7 @@ __device__ inline uint64_t lb_tile_scan(LbShared& sh, int64_t tile, uint64_t* st
                 (tt >= 0) ? __hip_atomic_load(&state[tt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kLbInc;
             const uint64_t f = w & ~kLbValue;
             const uint64_t none = __ballot(f == 0);
-            const uint64_t incl = __ballot(f == kLbInc);
+            const uint64_t incl = __ballot(f >= kLbInc);  // an inclusive prefix (flag 2 or 3)
             const int first_none = none ? (int)__ffsll((unsigned long long)none) - 1 : kWave;
             const int first_incl = incl ? (int)__ffsll((unsigned long long)incl) - 1 : kWave;
             const bool finish = first_incl < first_none;

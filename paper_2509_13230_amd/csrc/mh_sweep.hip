@@ -293,9 +293,13 @@ __global__ __launch_bounds__(kLbThreads) void k_row_plan_scan(NodeRec* __restric
 // needs, is the zeroing kernel's per-tile mass sums added up (their total does
 // not depend on the order).  J of a dense row is searched over the tile's
 // ranks and the next tile's first one in LDS, else in the sorted keys beyond;
-// P at such a J waits (bounded spin) for the inclusive prefix through the
-// tile before J's and adds the masses up to J, so every tile must be resident
-// (one block each).
+// P at such a J is read from J's tile once that tile has written its P: it
+// stores P through to the device's coherence point and then marks its
+// look-back word done with a release, which the reader waits for (bounded
+// spin) and acquires; so every tile must be resident (one block each).  Only
+// a tile that some row's dense part can reach does so: J >= base needs
+// s z_(base - 1) >= 1 for a row's s <= z_0, so a tile with
+// z_0 z_(base - 1) < 1 is never read this way (fl(s z) <= fl(z_0 z)).
 __device__ __forceinline__ double sorted_rank_z(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ vals,
                                                 int64_t j, uint32_t kb) {
     return key_value(((uint64_t)(keys[j] + kb) << 32) | (vals[j] >> 32));
@@ -327,33 +331,23 @@ __device__ __forceinline__ int64_t fused_dense_end(const uint32_t* __restrict__ 
     return lo;
 }
 
-// P[J] for base + kLbTile < J < n: the inclusive prefix through the tile
-// before J's (this tile's own end1, or another tile's published word) plus the
-// masses of the ranks from J's tile's start up to J.
-__device__ __forceinline__ uint64_t fused_prefix_beyond(const uint32_t* __restrict__ keys,
-                                                        const uint64_t* __restrict__ vals, uint32_t kb, int64_t tile,
-                                                        uint64_t end1, const uint64_t* state1, int64_t J,
+// P[J] for base + kLbTile < J < n, from J's tile (a later one) once it is
+// done writing P.
+__device__ __forceinline__ uint64_t fused_prefix_beyond(const uint64_t* P, const uint64_t* state1, int64_t J,
                                                         int32_t* status) {
     const int64_t u = J / kLbTile;  // J's tile, after this one
-    uint64_t acc = end1;
-    if (u - 1 != tile) {
-        uint32_t spins = 0;
-        for (;;) {
-            const uint64_t w = __hip_atomic_load(&state1[u - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((w & ~kLbValue) == kLbInc) {
-                acc = w & kLbValue;
-                break;
-            }
-            if (++spins > kLbSpinLimit) {
-                raise_status(status, MH_EHIP);
-                acc = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
+    uint32_t spins = 0;
+    for (;;) {
+        const uint64_t w = __hip_atomic_load(&state1[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((w & ~kLbValue) == kLbDone) break;
+        if (++spins > kLbSpinLimit) {
+            raise_status(status, MH_EHIP);
+            return 0;
         }
+        __builtin_amdgcn_s_sleep(1);
     }
-    for (int64_t j = u * kLbTile; j < J; ++j) acc += mass_q(sorted_rank_z(keys, vals, j, kb));
-    return acc;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return __hip_atomic_load(&P[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ __launch_bounds__(kLbThreads) void k_finish_plan_scan(
@@ -401,6 +395,8 @@ __global__ __launch_bounds__(kLbThreads) void k_finish_plan_scan(
             sh.items[lb_at(idx)] = m;
         }
         if (threadIdx.x == 0) s_zt[kLbTile] = base + kLbTile < n ? sorted_rank_z(keys, vals, base + kLbTile, kb) : 0.0;
+        // whether any row's dense part can reach this tile (then its P is read by other tiles)
+        const bool reached = tile > 0 && sorted_rank_z(keys, vals, 0, kb) * sorted_rank_z(keys, vals, base - 1, kb) >= 1.0;
         // 2. P, the exclusive prefix of the masses (look-back 1)
         const uint64_t end1 = lb_tile_scan(sh, tile, state1, status);
 #pragma unroll
@@ -410,18 +406,27 @@ __global__ __launch_bounds__(kLbThreads) void k_finish_plan_scan(
             const uint64_t v = sh.items[lb_at(idx)];
             s_pt[idx] = v;
             if (r < n) {
-                P[r] = v;
+                // a reached tile's P goes through to the coherence point: other
+                // tiles of this launch read it
+                if (reached) __hip_atomic_store(&P[r], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else P[r] = v;
                 if ((r & ((1 << kSampleShift) - 1)) == 0) Psamp[r >> kSampleShift] = v;
             }
         }
         if (threadIdx.x == 0) {
             s_pt[kLbTile] = end1;  // P at base + kLbTile
             if (base + kLbTile >= n) {
-                P[n] = end1;
+                __hip_atomic_store(&P[n], end1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if ((n & ((1 << kSampleShift) - 1)) == 0) Psamp[n >> kSampleShift] = end1;
             }
         }
+        // a reached tile's P out: every wave's stores complete, then the
+        // look-back word marked done with a release (reached is uniform over
+        // the block); the barrier also makes s_pt whole for the plan
+        if (reached) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
+        if (reached && threadIdx.x == 0)
+            __hip_atomic_store(&state1[tile], kLbDone | end1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         // 3. the row plan, and the records
         uint64_t cnt[kLbItems];
 #pragma unroll
@@ -440,9 +445,7 @@ __global__ __launch_bounds__(kLbThreads) void k_finish_plan_scan(
                     uint64_t PJ = s_pt[idx + 1];  // P[r + 1]
                     if (s * s_zt[idx + 1] >= cr) {
                         J = fused_dense_end(keys, vals, kb, n, base, s_zt, s, first);
-                        if (J < n)
-                            PJ = J <= base + kLbTile ? s_pt[J - base]
-                                                     : fused_prefix_beyond(keys, vals, kb, tile, end1, state1, J, status);
+                        if (J < n) PJ = J <= base + kLbTile ? s_pt[J - base] : fused_prefix_beyond(P, state1, J, status);
                     }
                     const int64_t nd = J > first ? (int64_t)((uint32_t)(J - first + T - 1) / (uint32_t)T) : 0;
                     int64_t ns = 0;
