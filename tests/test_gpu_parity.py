@@ -457,6 +457,20 @@ def test_full_size_fitted_unweighted_matches_oracle(mh):
         compare_edges((src, dst), ora, len(x), ora.tie_rows, label=f"fitted N=1M replica {replica}")
 
 
+@pytest.mark.parametrize("n", [1 << 20, (1 << 20) + 3_000])
+def test_sampler_at_the_exchange_limit_matches_oracle(mh, n):
+    # 256 tiles of 4096 nodes (every tile of the sort, and of the one-pass
+    # records-and-plan kernel, on a CU of its own) and one tile more (the
+    # look-back sort and the two-kernel plan)
+    rng = np.random.default_rng(n)
+    x = rng.lognormal(-7.2, 1.3, n)
+    x[rng.integers(0, n, 2000)] = rng.uniform(1.5, 4.0, 2000)  # a dense core
+    src, dst = mh.sample_unweighted(dev(x), seed=2, replica=5, seg_work=8)
+    ora = oracle.sample_mh(x, None, seed=2, replica=5, seg_work=8, capacity=4_000_000)
+    assert ora.n_edges > 100_000
+    compare_edges((src, dst), ora, n, ora.tie_rows, label=f"N={n}")
+
+
 def test_full_size_weighted_matches_oracle(mh):
     # N = 200,000 weighted targets (k power law 2.3 on [1, 5000], s = k (1 + Gamma(2, 3))),
     # in the configuration the benchmark times (seg_work 32, default grid)
