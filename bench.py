@@ -705,7 +705,48 @@ def batched_ensemble(args, dev) -> dict:
         runs.append(time.perf_counter() - t0)
     t_batch = min(runs)
     batch_edges = int(deg.sum().item()) // 2
-    del deg, g
+    del g
+
+    # the same degree sequences, columns counted through a slot buffer
+    # (MH_BATCH_DEGREES_STAGED): samples in consecutive groups whose columns
+    # fit the buffer with margin (a sample's region is sized from a bound on
+    # its proposals; what overflows a region is added by atomics), one graph per
+    # group, every group's degrees at its place in one array
+    slot_cap = args.batch_slot_buffer
+    sgroups, cur, need = [], [], 0
+    for s_i, c in enumerate(plain_counts):
+        w_ = 2 * c + 4096
+        if cur and need + w_ > slot_cap:
+            sgroups.append(cur)
+            cur, need = [], 0
+        cur.append(s_i)
+        need += w_
+    sgroups.append(cur)
+    slots = torch.empty(slot_cap, dtype=torch.int32, device=dev)
+    sdeg = torch.empty_like(deg)
+    graphs = []
+    for grp in sgroups:
+        gn = torch.tensor([net_ids[j] for j in grp], dtype=torch.int32, device=dev)
+        gr = torch.tensor([reps[j] for j in grp], dtype=torch.int32, device=dev)
+        goff = b.degree_offsets(gn.cpu())
+        base = int(off[grp[0]])
+        graphs.append(b.capture_degrees(gn, gr, args.seed, sdeg[base:base + int(goff[-1])], goff.to(dev),
+                                        grid_blocks=tuned["grid_blocks"], slots=slots))
+    for g_ in graphs:  # warm-up
+        g_.launch()
+    b.result(-1)
+    runs = []
+    for _ in range(2):
+        sdeg.fill_(-1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for g_ in graphs:
+            g_.launch()
+        b.result(-1)
+        runs.append(time.perf_counter() - t0)
+    t_staged = min(runs)
+    staged_equal = bool(torch.equal(sdeg, deg))
+    del deg, sdeg, slots, graphs
 
     # batched, edge output: the samples in consecutive groups whose edges fit
     # one output buffer (src, dst and the sample index, int32 each), one
@@ -774,6 +815,14 @@ def batched_ensemble(args, dev) -> dict:
                                                               "adds not counted)",
                                            "ceiling_source": "measured here (libmh_probe.so): 2048 x 256 lanes x "
                                                              "256 random int32 atomic adds into 2^22 counters"}},
+        # the same sequences through the slot buffer: the sweep writes each
+        # accepted column (4 B), a counting kernel reads it per 32768-column window
+        "degree_sink_staged": {"replicas_per_s": S / t_staged,
+                               "ms_graph_launches": t_staged * 1e3, "edges_per_s": batch_edges / t_staged,
+                               "launches": len(sgroups), "slot_buffer_int32": slot_cap,
+                               "degrees_equal_atomic_sink": staged_equal,
+                               "speedup_vs_atomic_sink": t_batch / t_staged,
+                               "speedup_vs_plain_edge_output": t_plain_async / t_staged},
         "tuned": tuned,
     }
 
@@ -806,6 +855,8 @@ def main():
                     help="replicas of the Chung-Lu bias statistics (0: skip the Chung-Lu measurement)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--batch-slot-buffer", type=int, default=1_500_000_000,
+                    help="int32 slots of the staged degree sink's buffer")
     ap.add_argument("--skip-small", action="store_true", help="skip the N=2,000 timings")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="copy a buffer of this many MiB once first (reference for HBM byte counters)")

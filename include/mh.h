@@ -255,6 +255,7 @@ typedef struct {
 
 #define MH_BATCH_EDGES 0   /* edges (src, dst[, w]) and optionally the sample index per edge (sid) */
 #define MH_BATCH_DEGREES 1 /* per-sample degree sequences: degrees[deg_off[s] + node id] */
+#define MH_BATCH_DEGREES_STAGED 2 /* the same sequences, columns counted through a slot buffer (src) */
 
 typedef struct {
     int32_t seg_work;    /* chosen plan parameter */
@@ -277,7 +278,20 @@ mh_status mh_batch_prepare(const mh_network* nets_host, int32_t n_networks, int3
  * src/dst (w for weighted networks; sid[k] = sample of edge k, may be NULL),
  * order unspecified.  MH_BATCH_DEGREES: degrees[deg_off[s] + v] (device int32,
  * offsets device int64; the caller's array must hold deg_off[s] + n of every
- * listed sample) is overwritten with node v's degree in sample s.
+ * listed sample) is overwritten with node v's degree in sample s, every
+ * accepted edge adding to its endpoints by a device atomic (the rate of random
+ * atomic adds bounds it).  MH_BATCH_DEGREES_STAGED: the same degrees, the same
+ * samples, counted through src (capacity int32 words, scratch owned by the
+ * caller, contents undefined afterwards): each sample's node ids fall in
+ * windows of 32768; the front of src holds 24 bytes of bookkeeping per
+ * (sample, window) key, the rest the keys' slot regions, sized from a bound on
+ * each window's expected column hits and cut at the capacity.  The sweep
+ * writes each accepted edge's column into its key's region (one device atomic
+ * per key and wave flush, not per edge) and a counting kernel adds every
+ * region up in LDS, one block per key.  Columns beyond their region's end are
+ * added by atomics; with less room than the bookkeeping, or a network of more
+ * than 256 windows (8,388,608 nodes), the call counts by atomics throughout:
+ * any capacity (0 included) gives the same degrees.
  * grid_blocks = 0 uses every resident block.  Asynchronous, kernels only: it
  * may be captured in a hipGraph.  mh_batch_result reads the edge count back. */
 mh_status mh_batch_sample_async(const mh_network* nets_host, int32_t n_networks, int32_t max_samples,

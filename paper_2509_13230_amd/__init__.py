@@ -542,7 +542,7 @@ class ExpectedDegree(torch.autograd.Function):
 
 
 # ---------------------------------------------------------------------------- batched ensembles
-MH_BATCH_EDGES, MH_BATCH_DEGREES = 0, 1
+MH_BATCH_EDGES, MH_BATCH_DEGREES, MH_BATCH_DEGREES_STAGED = 0, 1, 2
 
 
 class Network(ctypes.Structure):
@@ -657,27 +657,39 @@ class Batch:
             cap = -m
         raise MHError(MH_ECAPACITY, "mh_batch_sample_async")
 
-    def sample_degrees(self, sample_net, sample_rep, seed: int = 1, out=None, grid_blocks=0):
-        """Concatenated per-sample degree sequences and their offsets (int64, len n_samples + 1)."""
+    def sample_degrees(self, sample_net, sample_rep, seed: int = 1, out=None, grid_blocks=0, slots=None):
+        """Concatenated per-sample degree sequences and their offsets (int64, len n_samples + 1).
+        slots: an int32 CUDA tensor (scratch) to count the columns through
+        (MH_BATCH_DEGREES_STAGED), else every edge adds by a device atomic."""
         net, rep = self._refs(sample_net, sample_rep)
         off = self.degree_offsets(net.cpu())
         deg = out if out is not None else torch.empty(int(off[-1]), dtype=torch.int32, device=self.device)
         offd = off.to(self.device)
+        mode, cap = self._degree_mode(slots)
         _check(self.L.mh_batch_sample_async(self.nets, self.k, self.max_samples, _ptr(self.ws), self.ws.numel(),
-                                            _ptr(net), _ptr(rep), net.numel(), seed, MH_BATCH_DEGREES, None, None,
-                                            None, None, 0, _ptr(deg), _ptr(offd), grid_blocks, _stream(self.device)),
+                                            _ptr(net), _ptr(rep), net.numel(), seed, mode, _ptr(slots), None,
+                                            None, None, cap, _ptr(deg), _ptr(offd), grid_blocks, _stream(self.device)),
                "mh_batch_sample_async")
         self.result(-1)
         return deg, off
 
-    def capture_degrees(self, net, rep, seed, deg, offd, grid_blocks=0):
+    @staticmethod
+    def _degree_mode(slots):
+        if slots is None:
+            return MH_BATCH_DEGREES, 0
+        if slots.dtype != torch.int32 or not slots.is_cuda or not slots.is_contiguous():
+            raise ValueError("slots must be a contiguous int32 CUDA tensor")
+        return MH_BATCH_DEGREES_STAGED, slots.numel()
+
+    def capture_degrees(self, net, rep, seed, deg, offd, grid_blocks=0, slots=None):
         """hipGraph of one degree-sink batch launch; returns a BatchGraph (replay with .launch())."""
         exe = ctypes.c_void_p()
+        mode, cap = self._degree_mode(slots)
         _check(self.L.mh_batch_capture(self.nets, self.k, self.max_samples, _ptr(self.ws), self.ws.numel(), _ptr(net),
-                                       _ptr(rep), net.numel(), seed, MH_BATCH_DEGREES, None, None, None, None, 0,
+                                       _ptr(rep), net.numel(), seed, mode, _ptr(slots), None, None, None, cap,
                                        _ptr(deg), _ptr(offd), grid_blocks, _stream(self.device), ctypes.byref(exe)),
                "mh_batch_capture")
-        return BatchGraph(self.L, exe, self.device, keep=(net, rep, deg, offd, self.ws))
+        return BatchGraph(self.L, exe, self.device, keep=(net, rep, deg, offd, slots, self.ws))
 
     def capture_edges(self, net, rep, seed, src, dst, w, sid, capacity, grid_blocks=0):
         exe = ctypes.c_void_p()

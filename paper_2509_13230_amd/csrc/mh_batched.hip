@@ -53,6 +53,149 @@ __global__ __launch_bounds__(kThreads) void k_batch_zero_degrees(const NetDesc* 
     }
 }
 
+// ---- staged degree counts (MH_BATCH_DEGREES_STAGED) ----
+// The sweep writes each accepted column's node id into the slot region of its
+// key (sample, window of 2^15 ids); one counting block per key then adds the
+// region up in LDS.  A region is sized from a bound on the expected column
+// hits of its window's nodes; what does not fit is added by atomics.
+constexpr int64_t kWinCols = int64_t(1) << kSlotWinShift;
+
+__host__ __device__ inline int64_t windows_of(int64_t n) { return (n + kWinCols - 1) / kWinCols; }
+
+// Per network and window: the sum over the window's nodes of a bound on the
+// node's expected hits as a column.  Column rank j is proposed by the rows of
+// smaller rank at most once each and, from row r, with probability at most
+// z_r z_j (the skip's rate), so its hits are at most min(j, z_j Z_j), Z_j the
+// mass of the ranks before j (P[j]).  The weighted chain proposes with its
+// row bound as well, so there the bound is looser than the truth can be:
+// its regions overflow into atomics sooner.  Without a plan (no column
+// masses) the bound is 0.  Grid (chunks, networks); est zeroed beforehand.
+constexpr int kEstThreads = 1024;
+__global__ __launch_bounds__(kEstThreads) void k_net_estimate(const NetDesc* __restrict__ nets, int32_t n_networks,
+                                                              const uint64_t* __restrict__ net_win_off,
+                                                              double* __restrict__ est) {
+    __shared__ double s_w[kSlotBins];
+    for (int32_t k = blockIdx.y; k < n_networks; k += gridDim.y) {
+        const NetDesc D = nets[k];
+        const int64_t nwin = windows_of(D.n);
+        __syncthreads();
+        for (int i = threadIdx.x; i < kSlotBins; i += kEstThreads) s_w[i] = 0.0;
+        __syncthreads();
+        if (D.P && nwin <= kSlotBins) {
+            for (int64_t j = (int64_t)blockIdx.x * kEstThreads + threadIdx.x; j < D.n;
+                 j += (int64_t)gridDim.x * kEstThreads) {
+                const NodeRec rec = D.node[j];
+                const double mass = (double)D.P[j] * 0x1.0p-32 * rec.z;
+                atomicAdd(&s_w[rec.id >> kSlotWinShift], mass < (double)j ? mass : (double)j);
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nwin && i < kSlotBins; i += kEstThreads)
+            if (s_w[i] > 0.0) atomicAdd(&est[net_win_off[k] + i], s_w[i]);
+    }
+}
+
+__global__ void k_fill_f64(double* a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0.0;
+}
+
+// Per sample: its count of windows (0 for a bad network index: the call fails).
+__global__ __launch_bounds__(kThreads) void k_batch_wins(const NetDesc* __restrict__ nets, int32_t n_networks,
+                                                         const int32_t* __restrict__ sample_net, int32_t n_samples,
+                                                         uint64_t* __restrict__ wins) {
+    const int32_t s = blockIdx.x * kThreads + threadIdx.x;
+    if (s >= n_samples) return;
+    const int32_t k = sample_net[s];
+    wins[s] = (k >= 0 && k < n_networks) ? (uint64_t)windows_of(nets[k].n) : 0;
+}
+
+// Sample of key g: the last s with win_off[s] <= g (samples without windows
+// share their successor's offset and are skipped).
+__device__ __forceinline__ int32_t key_sample(const uint64_t* __restrict__ win_off, int32_t n_samples, uint64_t g) {
+    int32_t lo = 0, hi = n_samples;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (win_off[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Per key (grid: n_keys upper bound): its region's size (1.25 times its
+// window's bound, plus 512) and an empty cursor; keys past the last are empty.
+__global__ __launch_bounds__(kThreads) void k_batch_regions(const int32_t* __restrict__ sample_net, int32_t n_samples,
+                                                            const uint64_t* __restrict__ win_off,
+                                                            const uint64_t* __restrict__ net_win_off,
+                                                            const double* __restrict__ est, int64_t n_keys,
+                                                            uint64_t* __restrict__ cap,
+                                                            unsigned long long* __restrict__ cursor) {
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= n_keys) return;
+    cursor[g] = 0;
+    if ((uint64_t)g >= win_off[n_samples]) {
+        cap[g] = 0;
+        return;
+    }
+    const int32_t s = key_sample(win_off, n_samples, (uint64_t)g);
+    const double e = est[net_win_off[sample_net[s]] + ((uint64_t)g - win_off[s])];
+    cap[g] = (uint64_t)(1.25 * e) + 512;
+}
+
+// Regions end at the slot capacity: a region reaching past it is cut.
+__global__ __launch_bounds__(kThreads) void k_batch_clip(int64_t n_keys, const uint64_t* __restrict__ off,
+                                                         uint64_t* __restrict__ cap, int64_t capacity) {
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= n_keys) return;
+    const uint64_t room = off[g] < (uint64_t)capacity ? (uint64_t)capacity - off[g] : 0;
+    if (cap[g] > room) cap[g] = room;
+}
+
+// One block per key: counts its region's node ids in LDS and adds the counts
+// to its sample's degrees (the window's ids belong to this block alone).  The
+// region is read once, 8 values a thread in flight.
+constexpr int kCountThreads = 1024;
+constexpr int kCountPer = 8;
+__global__ __launch_bounds__(kCountThreads) void k_batch_count(const NetDesc* __restrict__ nets,
+                                                               const int32_t* __restrict__ sample_net, int32_t n_samples,
+                                                               const uint64_t* __restrict__ win_off,
+                                                               const uint64_t* __restrict__ region_off,
+                                                               const uint64_t* __restrict__ region_cap,
+                                                               const unsigned long long* __restrict__ cursor,
+                                                               const int32_t* __restrict__ slots,
+                                                               int32_t* __restrict__ degrees,
+                                                               const int64_t* __restrict__ deg_off,
+                                                               const int32_t* status) {
+    __shared__ uint32_t s_cnt[kWinCols];
+    if (*status != 0) return;
+    const uint64_t g = blockIdx.x;
+    if (g >= win_off[n_samples]) return;
+    const int32_t s = key_sample(win_off, n_samples, g);
+    const int64_t w0 = (int64_t)(g - win_off[s]) * kWinCols;
+    const int64_t n = nets[sample_net[s]].n;
+    const int64_t wn = n - w0 < kWinCols ? n - w0 : kWinCols;
+    for (int i = threadIdx.x; i < kWinCols; i += kCountThreads) s_cnt[i] = 0;
+    __syncthreads();
+    const uint64_t taken = cursor[g] < region_cap[g] ? cursor[g] : region_cap[g];
+    const int32_t* reg = slots + region_off[g];
+    for (uint64_t k0 = 0; k0 < taken; k0 += (uint64_t)kCountThreads * kCountPer) {
+        int32_t v[kCountPer];
+#pragma unroll
+        for (int u = 0; u < kCountPer; ++u) {
+            const uint64_t k = k0 + (uint64_t)u * kCountThreads + threadIdx.x;
+            v[u] = k < taken ? reg[k] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kCountPer; ++u) {
+            const int64_t c = (int64_t)v[u] - w0;
+            if (v[u] >= 0 && c >= 0 && c < wn) atomicAdd(&s_cnt[c], 1u);
+        }
+    }
+    __syncthreads();
+    int32_t* d = degrees + deg_off[s] + w0;
+    for (int64_t i = threadIdx.x; i < wn; i += kCountThreads)
+        if (s_cnt[i]) d[i] += (int32_t)s_cnt[i];
+}
+
 // Start of a sampling call: clears the edge count and statistics, and the
 // status of any earlier call; a preparation error (invalid networks) stays.
 __global__ void k_batch_init(Counters* c) {
@@ -72,6 +215,12 @@ struct BatchLayout {
     Counters* ctr;
     NetDesc* nets;
     uint64_t* item_off;
+    // staged degree counts (when every network has at most kSlotBins windows)
+    int64_t max_win;           // windows of the largest network
+    int64_t total_win;         // windows of all networks
+    uint64_t* net_win_off;     // per network (+1): its first window's bound
+    double* est;               // per network and window: the bound on its column hits
+    uint64_t* win_off;         // per sample (+1): its first key
     std::vector<NetBuffers> bufs;
     void* scratch;
     size_t scratch_bytes;
@@ -86,13 +235,24 @@ bool layout(const mh_network* nets, int32_t n_networks, int32_t max_samples, voi
         s.take<Counters>(1);
         s.take<NetDesc>(n_networks);
         s.take<uint64_t>((size_t)max_samples + 1);
+        int64_t tw = 0, mw = 0;
+        for (int32_t i = 0; i < n_networks; ++i) {
+            tw += windows_of(nets[i].n);
+            mw = windows_of(nets[i].n) > mw ? windows_of(nets[i].n) : mw;
+        }
+        s.take<uint64_t>((size_t)n_networks + 1);
+        s.take<double>((size_t)tw);
+        s.take<uint64_t>((size_t)max_samples + 1);
         bytes = s.used;
         for (int32_t i = 0; i < n_networks; ++i) {
             bytes = ((bytes + 255) & ~size_t(255)) + network_bytes(nets[i].n, nets[i].y != nullptr, nets[i].seg_work);
             if (nets[i].n > max_n) max_n = nets[i].n;
         }
         size_t scratch = prepare_scratch_bytes(max_n);
-        const size_t s2 = scan_workspace_bytes((int64_t)max_samples + 1);
+        size_t s2 = scan_workspace_bytes((int64_t)max_samples + 1);
+        if (s2 > scratch) scratch = s2;
+        // the scan over the keys of a staged call
+        if (mw <= kSlotBins) s2 = scan_workspace_bytes((int64_t)max_samples * mw + 1);
         if (s2 > scratch) scratch = s2;
         bytes = ((bytes + 255) & ~size_t(255)) + scratch + 512;
     }
@@ -103,6 +263,15 @@ bool layout(const mh_network* nets, int32_t n_networks, int32_t max_samples, voi
     L->ctr = ar.take<Counters>(1);
     L->nets = ar.take<NetDesc>(n_networks);
     L->item_off = ar.take<uint64_t>((size_t)max_samples + 1);
+    L->max_win = 0;
+    L->total_win = 0;
+    for (int32_t i = 0; i < n_networks; ++i) {
+        L->total_win += windows_of(nets[i].n);
+        L->max_win = windows_of(nets[i].n) > L->max_win ? windows_of(nets[i].n) : L->max_win;
+    }
+    L->net_win_off = ar.take<uint64_t>((size_t)n_networks + 1);
+    L->est = ar.take<double>((size_t)L->total_win);
+    L->win_off = ar.take<uint64_t>((size_t)max_samples + 1);
     L->bufs.resize(n_networks);
     for (int32_t i = 0; i < n_networks; ++i) {
         Arena sub(ar.base + ((ar.used + 255) & ~size_t(255)), ws_bytes - ((ar.used + 255) & ~size_t(255)));
@@ -168,6 +337,20 @@ mh_status mh_batch_prepare(const mh_network* nets, int32_t n_networks, int32_t m
         descs[i] = net_desc(L.bufs[i]);
     }
     MH_HIP_TRY(hipMemcpyAsync(L.nets, descs.data(), sizeof(NetDesc) * n_networks, hipMemcpyHostToDevice, stream));
+    // the column-hit bounds that size the regions of staged degree counts
+    std::vector<uint64_t> wo((size_t)n_networks + 1, 0);
+    for (int32_t i = 0; i < n_networks; ++i) wo[i + 1] = wo[i] + (uint64_t)windows_of(nets[i].n);
+    MH_HIP_TRY(hipMemcpyAsync(L.net_win_off, wo.data(), sizeof(uint64_t) * wo.size(), hipMemcpyHostToDevice, stream));
+    if (L.total_win > 0 && L.max_win <= kSlotBins) {
+        hipLaunchKernelGGL(k_fill_f64, dim3(64), dim3(256), 0, stream, L.est, L.total_win);
+        MH_HIP_TRY(hipGetLastError());
+        int64_t max_n = 0;
+        for (int32_t i = 0; i < n_networks; ++i) max_n = nets[i].n > max_n ? nets[i].n : max_n;
+        const int64_t gx = (max_n + kEstThreads - 1) / kEstThreads;
+        const dim3 eg((unsigned)(gx < 64 ? gx : 64), (unsigned)(n_networks < 4096 ? n_networks : 4096));
+        hipLaunchKernelGGL(k_net_estimate, eg, dim3(kEstThreads), 0, stream, L.nets, n_networks, L.net_win_off, L.est);
+        MH_HIP_TRY(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_batch_seal, dim3(1), dim3(64), 0, stream, L.ctr);
     MH_HIP_TRY(hipGetLastError());
     Counters hc;
@@ -187,13 +370,39 @@ mh_status mh_batch_sample_async(const mh_network* nets, int32_t n_networks, int3
     if (n_samples < 0 || n_samples > max_samples || (n_samples > 0 && (!sample_net || !sample_rep))) return MH_EINVAL;
     if (mode == MH_BATCH_EDGES) {
         if (capacity < 0 || (capacity > 0 && (!src || !dst || (weighted && !w)))) return MH_EINVAL;
-    } else if (mode == MH_BATCH_DEGREES) {
+    } else if (mode == MH_BATCH_DEGREES || mode == MH_BATCH_DEGREES_STAGED) {
         if (n_samples > 0 && (!degrees || !deg_off)) return MH_EINVAL;
+        if (mode == MH_BATCH_DEGREES_STAGED && (capacity < 0 || (capacity > 0 && !src))) return MH_EINVAL;
     } else {
         return MH_EINVAL;
     }
+    bool staged = mode == MH_BATCH_DEGREES_STAGED;
     BatchLayout L;
     if (!layout(nets, n_networks, max_samples, workspace, ws_bytes, &L, nullptr)) return MH_EWORKSPACE;
+    // staged counts: the keys' arrays at the front of src (8-byte aligned),
+    // then the slots; with too little room (or networks of more than
+    // kSlotBins windows) every column is added by atomics instead
+    int64_t n_keys = 0, slot_cap = 0;
+    uint64_t *region_cap = nullptr, *region_off = nullptr;
+    unsigned long long* cursor = nullptr;
+    int32_t* slot_base = nullptr;
+    if (staged) {
+        n_keys = L.max_win <= kSlotBins ? (int64_t)n_samples * L.max_win : 0;
+        const uintptr_t p0 = reinterpret_cast<uintptr_t>(src);
+        const uintptr_t p8 = (p0 + 7) & ~uintptr_t(7);
+        const int64_t skip = src ? (int64_t)((p8 - p0) / sizeof(int32_t)) : 0;
+        const int64_t words = 2 * (3 * n_keys + 1);
+        if (n_keys == 0 || n_keys > 0x7FFFFFFFll || !src || capacity < skip + words) {
+            staged = false;
+        } else {
+            uint64_t* k64 = reinterpret_cast<uint64_t*>(p8);
+            region_cap = k64;
+            region_off = k64 + n_keys;
+            cursor = reinterpret_cast<unsigned long long*>(k64 + 2 * n_keys + 1);
+            slot_base = src + skip + words;
+            slot_cap = capacity - skip - words;
+        }
+    }
     hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(64), 0, stream, L.ctr);
     MH_HIP_TRY(hipGetLastError());
     if (n_samples == 0) return MH_OK;
@@ -202,10 +411,28 @@ mh_status mh_batch_sample_async(const mh_network* nets, int32_t n_networks, int3
     MH_HIP_TRY(hipGetLastError());
     mh_status st = scan_exclusive_u64(L.item_off, L.item_off, n_samples, L.scratch, L.scratch_bytes, stream);
     if (st != MH_OK) return st;
-    if (mode == MH_BATCH_DEGREES) {
+    if (mode != MH_BATCH_EDGES) {
         const dim3 zg(64, (unsigned)(n_samples < 4096 ? n_samples : 4096));
         hipLaunchKernelGGL(k_batch_zero_degrees, zg, dim3(kThreads), 0, stream, L.nets, n_networks, sample_net, deg_off,
                            n_samples, degrees);
+        MH_HIP_TRY(hipGetLastError());
+    }
+    if (staged) {
+        // each key's (sample, window) slot region, cut at the slot capacity
+        const unsigned sgrid = (unsigned)((n_samples + kThreads - 1) / kThreads);
+        hipLaunchKernelGGL(k_batch_wins, dim3(sgrid), dim3(kThreads), 0, stream, L.nets, n_networks, sample_net,
+                           n_samples, L.win_off);
+        MH_HIP_TRY(hipGetLastError());
+        st = scan_exclusive_u64(L.win_off, L.win_off, n_samples, L.scratch, L.scratch_bytes, stream);
+        if (st != MH_OK) return st;
+        const unsigned kgrid = (unsigned)((n_keys + kThreads - 1) / kThreads);
+        hipLaunchKernelGGL(k_batch_regions, dim3(kgrid), dim3(kThreads), 0, stream, sample_net, n_samples, L.win_off,
+                           L.net_win_off, L.est, n_keys, region_cap, cursor);
+        MH_HIP_TRY(hipGetLastError());
+        st = scan_exclusive_u64(region_cap, region_off, n_keys, L.scratch, L.scratch_bytes, stream);
+        if (st != MH_OK) return st;
+        hipLaunchKernelGGL(k_batch_clip, dim3(kgrid), dim3(kThreads), 0, stream, n_keys, region_off, region_cap,
+                           slot_cap);
         MH_HIP_TRY(hipGetLastError());
     }
     SweepLaunch A{};
@@ -216,6 +443,12 @@ mh_status mh_batch_sample_async(const mh_network* nets, int32_t n_networks, int3
     A.batch.n_samples = n_samples;
     A.batch.degrees = degrees;
     A.batch.deg_off = deg_off;
+    A.batch.slots = slot_base;
+    A.batch.win_off = L.win_off;
+    A.batch.region_off = region_off;
+    A.batch.region_cap = region_cap;
+    A.batch.cursor = cursor;
+    A.batch.slot_wins = (int32_t)L.max_win;
     A.key0 = (uint32_t)seed;
     A.key1 = (uint32_t)(seed >> 32);
     A.out = EdgeOut{src, dst, w, mode == MH_BATCH_EDGES ? capacity : 0, &L.ctr->n_edges};
@@ -224,8 +457,18 @@ mh_status mh_batch_sample_async(const mh_network* nets, int32_t n_networks, int3
     if (mode == MH_BATCH_EDGES)
         return weighted ? launch_batch<true, OUT_EDGES>(A, grid_blocks, stream)
                         : launch_batch<false, OUT_EDGES>(A, grid_blocks, stream);
-    return weighted ? launch_batch<true, OUT_DEGREES>(A, grid_blocks, stream)
-                    : launch_batch<false, OUT_DEGREES>(A, grid_blocks, stream);
+    if (!staged)
+        return weighted ? launch_batch<true, OUT_DEGREES>(A, grid_blocks, stream)
+                        : launch_batch<false, OUT_DEGREES>(A, grid_blocks, stream);
+    st = weighted ? launch_batch<true, OUT_SLOTS>(A, grid_blocks, stream)
+                  : launch_batch<false, OUT_SLOTS>(A, grid_blocks, stream);
+    if (st != MH_OK) return st;
+    // the regions' counts, one block per key
+    hipLaunchKernelGGL(k_batch_count, dim3((unsigned)n_keys), dim3(kCountThreads), 0, stream, L.nets, sample_net,
+                       n_samples, L.win_off, region_off, region_cap, cursor, slot_base, degrees, deg_off,
+                       &L.ctr->status);
+    MH_HIP_TRY(hipGetLastError());
+    return MH_OK;
 }
 
 mh_status mh_batch_result(const mh_network* nets, int32_t n_networks, int32_t max_samples, void* workspace,

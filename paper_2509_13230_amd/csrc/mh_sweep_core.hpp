@@ -141,12 +141,101 @@ struct BatchRef {
     int32_t n_samples;
     int32_t* degrees;           // degree-sink output, or null
     const int64_t* deg_off;     // [n_samples] start of each sample's degree array
+    // OUT_SLOTS: the accepted columns of sample s in window w (node ids
+    // [w 2^15, (w + 1) 2^15)) go to the region of key g = win_off[s] + w:
+    // slots[region_off[g] + k] for k < region_cap[g] (k taken from cursor[g]);
+    // beyond, straight to the degrees.  slot_wins: windows of the batch's
+    // largest network (at most kSlotBins).
+    int32_t* slots;
+    const uint64_t* win_off;
+    const uint64_t* region_off;
+    const uint64_t* region_cap;
+    unsigned long long* cursor;
+    int32_t slot_wins;
 };
 
 // Output of a sweep: the edge list; per-node degrees (batched); or, for one
 // network, counts by rank: cnt[j] += 1 for every edge whose endpoint of larger
-// rank is j (the edges among the first K ranks number cnt[0] + ... + cnt[K-1]).
-enum SweepOut { OUT_EDGES = 0, OUT_DEGREES = 1, OUT_RANKS = 2 };
+// rank is j (the edges among the first K ranks number cnt[0] + ... + cnt[K-1]);
+// or (batched) per-node degrees with the rows' counts added as by OUT_DEGREES
+// and every accepted column written to its sample's slot region (counted later
+// in LDS) instead of added by a device atomic.
+enum SweepOut { OUT_EDGES = 0, OUT_DEGREES = 1, OUT_RANKS = 2, OUT_SLOTS = 3 };
+
+// Staged degree counts: a window holds 2^kSlotWinShift node ids; a wave bins
+// its staged columns into at most kSlotBins (sample, window) keys per flush.
+constexpr int kSlotWinShift = 15;
+constexpr int kSlotBins = 256;
+// LDS of one wave's flush: kSlotBins slot addresses (u64) and room counts (u32)
+constexpr int kSlotLdsWords = kSlotBins * 3;
+
+// A wave's staged (column, sample) pairs into their keys' slot regions.  The
+// keys of one flush are binned by (sample - lowest sample, window): an LDS
+// atomic gives each pair its rank in its bin, one device atomic per non-empty
+// bin reserves the bin's run in its region, and the pairs are written there.
+// Pairs of a sample too far from the lowest one to bin, and pairs past their
+// region's end, add to the degrees directly.  s_col holds node ids, s_smp
+// samples (overwritten); s_lds: kSlotLdsWords words of this wave.
+__device__ __forceinline__ void flush_slots(const int32_t* s_col, int32_t* s_smp, int32_t* s_lds, uint32_t fill,
+                                            const BatchRef& B) {
+    if (fill == 0) return;
+    __builtin_amdgcn_wave_barrier();
+    uint64_t* s_start = reinterpret_cast<uint64_t*>(s_lds);
+    uint32_t* s_room = reinterpret_cast<uint32_t*>(s_lds + 2 * kSlotBins);
+    const int lane = (int)(threadIdx.x & 63);
+    const int32_t nw = B.slot_wins;
+    const int32_t span = kSlotBins / nw;
+    int32_t lo = 0x7FFFFFFF;
+    for (uint32_t k = (uint32_t)lane; k < fill; k += kWave) lo = min(lo, s_smp[k]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lo = min(lo, __shfl_xor(lo, off, kWave));
+    for (int b = lane; b < kSlotBins; b += kWave) s_room[b] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    // 1. each pair's bin and rank in it (code >= 0), or -(sample + 1)
+    for (uint32_t k = (uint32_t)lane; k < fill; k += kWave) {
+        const int32_t smp = s_smp[k];
+        const int32_t d = smp - lo;
+        int32_t code = -(smp + 1);
+        if (d < span) {
+            const uint32_t bin = (uint32_t)(d * nw + (s_col[k] >> kSlotWinShift));
+            const uint32_t r = atomicAdd(&s_room[bin], 1u);
+            code = (int32_t)((bin << 16) | r);
+        }
+        s_smp[k] = code;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // 2. one reservation per non-empty bin: where its run starts, and how much
+    //    of it fits in the region
+    for (int b = lane; b < kSlotBins; b += kWave) {
+        const uint32_t c = s_room[b];
+        if (c == 0) continue;
+        const int32_t smp = lo + b / nw;
+        const uint64_t g = B.win_off[smp] + (uint64_t)(b % nw);
+        const uint64_t at = atomicAdd(&B.cursor[g], (unsigned long long)c);
+        const uint64_t cap = B.region_cap[g];
+        const uint64_t room = at < cap ? cap - at : 0;
+        s_start[b] = B.region_off[g] + at;
+        s_room[b] = room < c ? (uint32_t)room : c;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // 3. the writes
+    for (uint32_t k = (uint32_t)lane; k < fill; k += kWave) {
+        const int32_t code = s_smp[k];
+        const int32_t col = s_col[k];
+        if (code >= 0) {
+            const uint32_t bin = (uint32_t)code >> 16, r = (uint32_t)code & 0xFFFFu;
+            if (r < s_room[bin]) {
+                B.slots[s_start[bin] + r] = col;
+            } else {
+                const int32_t smp = lo + (int32_t)bin / nw;
+                atomicAdd(&B.degrees[B.deg_off[smp] + col], 1);
+            }
+        } else {
+            atomicAdd(&B.degrees[B.deg_off[-code - 1] + col], 1);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
 
 struct SweepLaunch {
     NetDesc net;        // single-sample network (unused in batch launches)
@@ -175,6 +264,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
     static_assert(!(BIP && BATCH), "two-set networks are sampled one at a time");
     static_assert(!(CL && (WEIGHTED || BIP || BATCH)), "the Chung-Lu chain is unweighted, one set, one sample");
     static_assert(OUT != OUT_RANKS || !(BATCH || BIP), "counts by rank are kept for one network");
+    static_assert(OUT != OUT_SLOTS || BATCH, "slot regions belong to batched samples");
     const int wave = threadIdx.x >> 6;
     const int64_t gwave = (int64_t)blockIdx.x * kSweepWaves + wave;
     const int64_t nwaves = (int64_t)gridDim.x * kSweepWaves;
@@ -323,6 +413,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
             ++row_deg;
             atomicAdd(&deg[dst_id], 1);
         }
+        if (OUT == OUT_SLOTS && acc) ++row_deg;
         if (OUT == OUT_RANKS && acc) atomicAdd(&A.rank_cnt[pos], 1);  // pos: the accepted column's rank
         // the accepted edge's sample: step 4 may move the lane to an item of the next sample
         const int32_t acc_sample = sample;
@@ -353,7 +444,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
             }
             if (ended) {
                 state = S_IDLE;
-                if (OUT == OUT_DEGREES && row_deg) atomicAdd(&deg[id], row_deg);
+                if ((OUT == OUT_DEGREES || OUT == OUT_SLOTS) && row_deg) atomicAdd(&deg[id], row_deg);
                 row_deg = 0;
             }
         }
@@ -380,7 +471,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
                         H = heavy_items(*Dp);
                         node = in_global(Dp->node);
                         ys = in_global(Dp->ys);
-                        if (OUT == OUT_DEGREES) deg = A.batch.degrees + A.batch.deg_off[lo];
+                        if (OUT == OUT_DEGREES || OUT == OUT_SLOTS) deg = A.batch.degrees + A.batch.deg_off[lo];
                     }
                     if (it < H) {
                         rec_direct = it >= Dp->rec_cap;
@@ -416,7 +507,26 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
             if (pc) rcc = *pc;
         }
         if (OUT == OUT_EDGES) stage.push_sid(acc, id, dst_id, wt, acc_sample, s_sid, A.out, A.sid);
+        if (OUT == OUT_SLOTS) {
+            const uint64_t am = __ballot(acc);
+            if (am) {
+                if (acc) {
+                    const uint32_t o = stage.fill + (uint32_t)__popcll(am & lt);
+                    s_dst[o] = dst_id;
+                    s_sid[o] = acc_sample;
+                }
+                stage.fill += (uint32_t)__popcll(am);
+                if (stage.fill > (uint32_t)kStageFlushAt) {
+                    flush_slots(s_dst, s_sid, s_src, stage.fill, A.batch);
+                    stage.fill = 0;
+                }
+            }
+        }
         if (__ballot(state != S_DONE) == 0) break;
+    }
+    if (OUT == OUT_SLOTS) {
+        flush_slots(s_dst, s_sid, s_src, stage.fill, A.batch);
+        stage.fill = 0;
     }
     if (STATS) {
         const unsigned long long v0 = wave_sum((unsigned long long)st_steps);
@@ -437,8 +547,10 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
 
 template <bool WEIGHTED, bool STATS, bool BATCH, int OUT, bool BIP = false, bool CL = false>
 __global__ __launch_bounds__(kSweepThreads) void k_sweep(SweepLaunch A) {
-    constexpr int kStage = OUT == OUT_EDGES ? kStageEdges : 1;
-    __shared__ int32_t s_src[kSweepWaves][kStage];
+    constexpr int kStage = (OUT == OUT_EDGES || OUT == OUT_SLOTS) ? kStageEdges : 1;
+    // OUT_SLOTS: s_src holds the flush's bins (8-byte aligned words)
+    __shared__ __attribute__((aligned(8))) int32_t
+        s_src[kSweepWaves][OUT == OUT_EDGES ? kStage : (OUT == OUT_SLOTS ? kSlotLdsWords : 1)];
     __shared__ int32_t s_dst[kSweepWaves][kStage];
     __shared__ int32_t s_w[WEIGHTED ? kSweepWaves : 1][WEIGHTED ? kStage : 1];
     __shared__ int32_t s_sid[BATCH ? kSweepWaves : 1][BATCH ? kStage : 1];

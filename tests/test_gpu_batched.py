@@ -154,6 +154,90 @@ def test_graph_replays_match_eager(mh):
         b.sample_degrees([1], [0], seed=1)
 
 
+def _staged_nets(seed, weighted):
+    # a network of three counting windows (70,000 columns), one of two, and
+    # small ones; weights kept sparse enough for the oracle
+    rng = np.random.default_rng(seed)
+    sizes = [70_000, 40_000, 3000, 150]
+    xs = [np.exp(rng.normal(-6.0, 1.5, n)) for n in sizes[:2]] + [np.exp(rng.normal(-3.0, 1.8, n)) for n in sizes[2:]]
+    ys = [rng.uniform(0.1, 0.95, n) for n in sizes] if weighted else None
+    return sizes, xs, ys
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_staged_degrees_equal_atomic_degrees(mh, weighted):
+    # the slot-buffer degree sink gives the atomic sink's degrees at any slot
+    # capacity: none (no room for the regions' bookkeeping: every column by
+    # atomics), a few thousand (regions cut, the rest by atomics) and ample;
+    # the atomic sink equals the oracle
+    sizes, xs, ys = _staged_nets(12, weighted)
+    b = mh.Batch([dev(x) for x in xs], [dev(y) for y in ys] if weighted else None, seg_work=16, max_samples=16)
+    net, rep = [0, 1, 2, 3, 0, 2, 1], [0, 0, 1, 2, 5, 3, 9]
+    ref, off = b.sample_degrees(net, rep, seed=7)
+    ref = ref.cpu().numpy()
+    for s in (0, 2):
+        i, r = net[s], rep[s]
+        ora = oracle.sample_mh(xs[i], ys[i] if weighted else None, seed=7, replica=r, seg_work=16)
+        _compare_degrees(ref[off[s]:off[s + 1]], ora, sizes[i], f"atomic sink sample {s}")
+    for cap in (0, 5000, 1 << 22):
+        slots = torch.empty(cap, dtype=torch.int32, device="cuda")
+        deg, off2 = b.sample_degrees(net, rep, seed=7, slots=slots)
+        assert np.array_equal(off2.numpy(), off.numpy())
+        assert np.array_equal(deg.cpu().numpy(), ref), f"staged sink, {cap} slots"
+    # a smaller batch after a larger one reuses the cursors and regions
+    slots = torch.empty(1 << 22, dtype=torch.int32, device="cuda")
+    deg, off3 = b.sample_degrees([3, 0], [2, 5], seed=7, slots=slots)
+    deg = deg.cpu().numpy()
+    assert np.array_equal(deg[off3[0]:off3[1]], ref[off[3]:off[4]])
+    assert np.array_equal(deg[off3[1]:off3[2]], ref[off[4]:off[5]])
+
+
+def test_staged_degrees_at_the_window_limits(mh):
+    # 256 windows of 2^15 ids (8,388,608 nodes): one bin per sample, so the
+    # flushes that hold several samples add all but the lowest by atomics;
+    # one node more (257 windows): the call counts by atomics throughout.
+    # Sparse x (about 1e5 edges a sample); the staged degrees must equal the
+    # atomic sink's exactly.
+    rng = np.random.default_rng(15)
+    for n_big in (256 << 15, (256 << 15) + 1):
+        xs = [np.exp(rng.normal(-9.0, 1.0, n_big)), np.exp(rng.normal(-3.0, 1.8, 2000))]
+        b = mh.Batch([dev(x) for x in xs], seg_work=16, max_samples=8)
+        net, rep = [0, 1, 0, 1, 1], [0, 0, 1, 1, 2]
+        ref, off = b.sample_degrees(net, rep, seed=3)
+        slots = torch.empty(1 << 24, dtype=torch.int32, device="cuda")
+        deg, _ = b.sample_degrees(net, rep, seed=3, slots=slots)
+        assert np.array_equal(deg.cpu().numpy(), ref.cpu().numpy()), f"{n_big} nodes"
+        assert int(ref.sum()) > 0
+        del b, slots, deg, ref
+
+
+def test_staged_degree_graph_replays_match_eager(mh):
+    sizes, xs, _ = _staged_nets(13, False)
+    b = mh.Batch([dev(x) for x in xs], seg_work=8, max_samples=8)
+    net = torch.tensor([0, 3, 1], dtype=torch.int32, device="cuda")
+    rep = torch.tensor([2, 2, 3], dtype=torch.int32, device="cuda")
+    eager, off = b.sample_degrees(net.cpu(), rep.cpu(), seed=9)
+    eager = eager.cpu().numpy()
+    slots = torch.empty(1 << 21, dtype=torch.int32, device="cuda")
+    deg = torch.empty(int(off[-1]), dtype=torch.int32, device="cuda")
+    g = b.capture_degrees(net, rep, 9, deg, off.cuda(), slots=slots)
+    for _ in range(3):
+        deg.fill_(-1)
+        slots.fill_(-1)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(deg.cpu().numpy(), eager)
+        b.sample_degrees([2], [0], seed=1, slots=slots)
+
+
+def test_staged_degrees_reject_bad_slots(mh):
+    _, xs, _ = _staged_nets(14, False)
+    b = mh.Batch([dev(xs[3])], seg_work=8, max_samples=4)
+    with pytest.raises(ValueError):
+        b.sample_degrees([0], [0], slots=torch.empty(10, dtype=torch.int64, device="cuda"))
+
+
 def test_graph_edge_replays_match_eager(mh):
     xs, _ = _nets(5, [2000])
     b = mh.Batch([dev(xs[0])], seg_work=16, max_samples=4)
