@@ -715,7 +715,7 @@ def batched_ensemble(args, dev) -> dict:
     slot_cap = args.batch_slot_buffer
     sgroups, cur, need = [], [], 0
     for s_i, c in enumerate(plain_counts):
-        w_ = 2 * c + 4096
+        w_ = (9 * c) // 5 + 4096
         if cur and need + w_ > slot_cap:
             sgroups.append(cur)
             cur, need = [], 0
@@ -855,7 +855,7 @@ def main():
                     help="replicas of the Chung-Lu bias statistics (0: skip the Chung-Lu measurement)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
-    ap.add_argument("--batch-slot-buffer", type=int, default=1_500_000_000,
+    ap.add_argument("--batch-slot-buffer", type=int, default=4_000_000_000,
                     help="int32 slots of the staged degree sink's buffer")
     ap.add_argument("--skip-small", action="store_true", help="skip the N=2,000 timings")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,

@@ -283,14 +283,14 @@ mh_status mh_batch_prepare(const mh_network* nets_host, int32_t n_networks, int3
  * atomic adds bounds it).  MH_BATCH_DEGREES_STAGED: the same degrees, the same
  * samples, counted through src (capacity int32 words, scratch owned by the
  * caller, contents undefined afterwards): each sample's node ids fall in
- * windows of 32768; the front of src holds 24 bytes of bookkeeping per
+ * windows of 32768; the front of src holds 144 bytes of bookkeeping per
  * (sample, window) key, the rest the keys' slot regions, sized from a bound on
  * each window's expected column hits and cut at the capacity.  The sweep
  * writes each accepted edge's column into its key's region (one device atomic
  * per key and wave flush, not per edge) and a counting kernel adds every
  * region up in LDS, one block per key.  Columns beyond their region's end are
  * added by atomics; with less room than the bookkeeping, or a network of more
- * than 256 windows (8,388,608 nodes), the call counts by atomics throughout:
+ * than 128 windows (4,194,304 nodes), the call counts by atomics throughout:
  * any capacity (0 included) gives the same degrees.
  * grid_blocks = 0 uses every resident block.  Asynchronous, kernels only: it
  * may be captured in a hipGraph.  mh_batch_result reads the edge count back. */

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_regions(const int32_t* __res
                                                             unsigned long long* __restrict__ cursor) {
     const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (g >= n_keys) return;
-    cursor[g] = 0;
+    cursor[g * kCursorStride] = 0;
     if ((uint64_t)g >= win_off[n_samples]) {
         cap[g] = 0;
         return;
@@ -175,7 +175,8 @@ __global__ __launch_bounds__(kCountThreads) void k_batch_count(const NetDesc* __
     const int64_t wn = n - w0 < kWinCols ? n - w0 : kWinCols;
     for (int i = threadIdx.x; i < kWinCols; i += kCountThreads) s_cnt[i] = 0;
     __syncthreads();
-    const uint64_t taken = cursor[g] < region_cap[g] ? cursor[g] : region_cap[g];
+    const uint64_t used = cursor[g * kCursorStride];
+    const uint64_t taken = used < region_cap[g] ? used : region_cap[g];
     const int32_t* reg = slots + region_off[g];
     for (uint64_t k0 = 0; k0 < taken; k0 += (uint64_t)kCountThreads * kCountPer) {
         int32_t v[kCountPer];
@@ -379,9 +380,10 @@ mh_status mh_batch_sample_async(const mh_network* nets, int32_t n_networks, int3
     bool staged = mode == MH_BATCH_DEGREES_STAGED;
     BatchLayout L;
     if (!layout(nets, n_networks, max_samples, workspace, ws_bytes, &L, nullptr)) return MH_EWORKSPACE;
-    // staged counts: the keys' arrays at the front of src (8-byte aligned),
-    // then the slots; with too little room (or networks of more than
-    // kSlotBins windows) every column is added by atomics instead
+    // staged counts: the keys' arrays at the front of src (128-byte aligned:
+    // cursors, one line each, then sizes and offsets), then the slots; with
+    // too little room (or networks of more than kSlotBins windows) every
+    // column is added by atomics instead
     int64_t n_keys = 0, slot_cap = 0;
     uint64_t *region_cap = nullptr, *region_off = nullptr;
     unsigned long long* cursor = nullptr;
@@ -389,16 +391,16 @@ mh_status mh_batch_sample_async(const mh_network* nets, int32_t n_networks, int3
     if (staged) {
         n_keys = L.max_win <= kSlotBins ? (int64_t)n_samples * L.max_win : 0;
         const uintptr_t p0 = reinterpret_cast<uintptr_t>(src);
-        const uintptr_t p8 = (p0 + 7) & ~uintptr_t(7);
+        const uintptr_t p8 = (p0 + 127) & ~uintptr_t(127);
         const int64_t skip = src ? (int64_t)((p8 - p0) / sizeof(int32_t)) : 0;
-        const int64_t words = 2 * (3 * n_keys + 1);
+        const int64_t words = 2 * ((kCursorStride + 2) * n_keys + 1);
         if (n_keys == 0 || n_keys > 0x7FFFFFFFll || !src || capacity < skip + words) {
             staged = false;
         } else {
             uint64_t* k64 = reinterpret_cast<uint64_t*>(p8);
-            region_cap = k64;
-            region_off = k64 + n_keys;
-            cursor = reinterpret_cast<unsigned long long*>(k64 + 2 * n_keys + 1);
+            cursor = reinterpret_cast<unsigned long long*>(k64);
+            region_cap = k64 + kCursorStride * n_keys;
+            region_off = region_cap + n_keys;
             slot_base = src + skip + words;
             slot_cap = capacity - skip - words;
         }

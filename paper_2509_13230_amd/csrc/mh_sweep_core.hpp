@@ -143,7 +143,8 @@ struct BatchRef {
     const int64_t* deg_off;     // [n_samples] start of each sample's degree array
     // OUT_SLOTS: the accepted columns of sample s in window w (node ids
     // [w 2^15, (w + 1) 2^15)) go to the region of key g = win_off[s] + w:
-    // slots[region_off[g] + k] for k < region_cap[g] (k taken from cursor[g]);
+    // slots[region_off[g] + k] for k < region_cap[g] (k taken from
+    // cursor[g * kCursorStride], one cache line per key);
     // beyond, straight to the degrees.  slot_wins: windows of the batch's
     // largest network (at most kSlotBins).
     int32_t* slots;
@@ -165,7 +166,10 @@ enum SweepOut { OUT_EDGES = 0, OUT_DEGREES = 1, OUT_RANKS = 2, OUT_SLOTS = 3 };
 // Staged degree counts: a window holds 2^kSlotWinShift node ids; a wave bins
 // its staged columns into at most kSlotBins (sample, window) keys per flush.
 constexpr int kSlotWinShift = 15;
-constexpr int kSlotBins = 256;
+constexpr int kSlotBins = 128;
+// keys' cursors one 128-byte line apart: the reservations of the keys in
+// flight (a few samples' windows) do not queue on one line
+constexpr int kCursorStride = 16;
 // LDS of one wave's flush: kSlotBins slot addresses (u64) and room counts (u32)
 constexpr int kSlotLdsWords = kSlotBins * 3;
 
@@ -211,7 +215,7 @@ __device__ __forceinline__ void flush_slots(const int32_t* s_col, int32_t* s_smp
         if (c == 0) continue;
         const int32_t smp = lo + b / nw;
         const uint64_t g = B.win_off[smp] + (uint64_t)(b % nw);
-        const uint64_t at = atomicAdd(&B.cursor[g], (unsigned long long)c);
+        const uint64_t at = atomicAdd(&B.cursor[g * kCursorStride], (unsigned long long)c);
         const uint64_t cap = B.region_cap[g];
         const uint64_t room = at < cap ? cap - at : 0;
         s_start[b] = B.region_off[g] + at;

@@ -193,13 +193,13 @@ def test_staged_degrees_equal_atomic_degrees(mh, weighted):
 
 
 def test_staged_degrees_at_the_window_limits(mh):
-    # 256 windows of 2^15 ids (8,388,608 nodes): one bin per sample, so the
+    # 128 windows of 2^15 ids (4,194,304 nodes): one bin per sample, so the
     # flushes that hold several samples add all but the lowest by atomics;
-    # one node more (257 windows): the call counts by atomics throughout.
+    # one node more (129 windows): the call counts by atomics throughout.
     # Sparse x (about 1e5 edges a sample); the staged degrees must equal the
     # atomic sink's exactly.
     rng = np.random.default_rng(15)
-    for n_big in (256 << 15, (256 << 15) + 1):
+    for n_big in (128 << 15, (128 << 15) + 1):
         xs = [np.exp(rng.normal(-9.0, 1.0, n_big)), np.exp(rng.normal(-3.0, 1.8, 2000))]
         b = mh.Batch([dev(x) for x in xs], seg_work=16, max_samples=8)
         net, rep = [0, 1, 0, 1, 1], [0, 0, 1, 1, 2]
