@@ -51,8 +51,8 @@ SWEEP_VALU_PER_STEP = 176
 # counters read for a 256 MiB copy (fetched bytes = 2 x FETCH_SIZE, written =
 # 1 x WRITE_SIZE).  They hold for the sweep built from the sources hashed in
 # SWEEP_SOURCES only; for any other build or input the bench reports null.
-SWEEP_COUNTERS = {"fetch_kib": 107035, "write_kib": 16367, "fetch_scale": 2.0, "write_scale": 1.0,
-                  "sources_sha256": "e9757c709c165cc0d04891981cfc1840a6e16bac3547f3bab2b5d03fee783711",
+SWEEP_COUNTERS = {"fetch_kib": 106972, "write_kib": 16365, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sources_sha256": "32fa9aa49f3997ca38aaa44b3efcfb60d0d8304d069ac97709703f618cd55ad7",
                   "input_sha256": "bc9851eaa93191638377524467d37dbbae5a37d6523e29d9c327d955e13c3ef6",
                   "seg_work": 8}
 SWEEP_SOURCES = ["paper_2509_13230_amd/csrc/" + f for f in
@@ -685,6 +685,13 @@ def batched_ensemble(args, dev) -> dict:
         mh.sample_async(xs[i], None, (src, dst), ws, seed=args.seed, replica=r, seg_work=sw)
     torch.cuda.synchronize()
     t_plain_async = time.perf_counter() - t0
+    # the chains' steps (untimed, the statistics variant of the sweep): a
+    # batched sample takes the same steps as its plain twin
+    steps_total = 0
+    for i, r in zip(net_ids, reps):
+        _, _, st_ = mh.sample_unweighted(xs[i], seed=args.seed, replica=r, seg_work=sw, out=(src, dst),
+                                         workspace=ws, stats=True)
+        steps_total += st_["steps"]
     del src, dst, ws
 
     # batched: one graph launch per ensemble (prepared and tuned above)
@@ -782,6 +789,13 @@ def batched_ensemble(args, dev) -> dict:
     # The degree sink adds 1 to a column's counter per sampled edge (and each
     # row's count once per row): bound by the GPU's rate of random atomic adds.
     ceiling = atomic_add_rate(dev)
+
+    def valu(t):
+        ops = steps_total * SWEEP_VALU_PER_STEP / t
+        return {"bound": "alu", "achieved": ops / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
+                "frac": ops / PEAK_LANE_OPS,
+                "work": f"{steps_total} steps x {SWEEP_VALU_PER_STEP} VALU lane-ops over the whole call"}
+
     return {
         "workload": f"{len(xs)} networks x {R} replicas = {S} samples, N log-uniform in [1e3, 2e5], "
                     "x = exp(Normal(-5, 2)), unweighted",
@@ -798,6 +812,7 @@ def batched_ensemble(args, dev) -> dict:
                   f"{len(groups)} launches of up to {group_cap} edges)",
         "batched_edges_equal": edge_total == plain_edges,
         "edges_per_s_batched": edge_total / t_batch_edges,
+        "valu_batched": valu(t_batch_edges),
         "ms_batched_edges_total": t_batch_edges * 1e3,
         "replicas_per_s_plain_sync": S / t_plain,
         "ms_prepare": t_prepare * 1e3,
@@ -805,7 +820,7 @@ def batched_ensemble(args, dev) -> dict:
         "ms_plain_sync_total": t_plain * 1e3,
         "replicas_per_s_batched_incl_prepare": S / (t_batch_edges + t_prepare),
         # a different output: per-sample degree sequences, no edge list
-        "degree_sink": {"replicas_per_s": S / t_batch, "ms_graph_launch": t_batch * 1e3,
+        "degree_sink": {"replicas_per_s": S / t_batch, "ms_graph_launch": t_batch * 1e3, "valu": valu(t_batch),
                         "edges_per_s": batch_edges / t_batch,
                         "speedup_vs_plain_edge_output": t_plain_async / t_batch,
                         # no published figure exists for this rate: the ceiling is measured
@@ -822,7 +837,8 @@ def batched_ensemble(args, dev) -> dict:
                                "launches": len(sgroups), "slot_buffer_int32": slot_cap,
                                "degrees_equal_atomic_sink": staged_equal,
                                "speedup_vs_atomic_sink": t_batch / t_staged,
-                               "speedup_vs_plain_edge_output": t_plain_async / t_staged},
+                               "speedup_vs_plain_edge_output": t_plain_async / t_staged,
+                               "valu": valu(t_staged)},
         "tuned": tuned,
     }
 
