@@ -211,6 +211,23 @@ def test_staged_degrees_at_the_window_limits(mh):
         del b, slots, deg, ref
 
 
+@pytest.mark.parametrize("grid", [1, 3, 0])
+def test_staged_degrees_many_samples_per_flush(mh, grid):
+    # 120 samples, the largest network of three windows (42 samples a flush
+    # can bin): on one block a wave's flushes hold pairs of samples far apart
+    # (added by atomics) as well as near ones (binned); staged and atomic
+    # sinks must agree exactly at every grid
+    sizes, xs, _ = _staged_nets(16, False)
+    b = mh.Batch([dev(x) for x in xs], seg_work=8, max_samples=128)
+    rng = np.random.default_rng(17)
+    net = rng.integers(0, len(xs), 120).tolist()
+    rep = rng.integers(0, 1000, 120).tolist()
+    ref, off = b.sample_degrees(net, rep, seed=4, grid_blocks=grid)
+    slots = torch.empty(1 << 24, dtype=torch.int32, device="cuda")
+    deg, _ = b.sample_degrees(net, rep, seed=4, grid_blocks=grid, slots=slots)
+    assert np.array_equal(deg.cpu().numpy(), ref.cpu().numpy()), f"grid {grid}"
+
+
 def test_staged_degree_graph_replays_match_eager(mh):
     sizes, xs, _ = _staged_nets(13, False)
     b = mh.Batch([dev(x) for x in xs], seg_work=8, max_samples=8)
@@ -281,6 +298,13 @@ def test_bad_network_index(mh):
     deg, off = b.sample_degrees([0], [0], seed=2)
     ora = oracle.sample_mh(xs[0], None, seed=2, replica=0, seg_work=mh.DEFAULT_SEG_WORK)
     _compare_degrees(deg.cpu().numpy(), ora, 100, "after a failed call")
+    # the same through the slot buffer: a bad index among good ones fails the
+    # call, and the next staged call counts as the atomic one did
+    slots = torch.empty(1 << 16, dtype=torch.int32, device="cuda")
+    with pytest.raises(mh.MHError):
+        b.sample_degrees([0, 3, 0], [0, 0, 1], slots=slots)
+    deg2, _ = b.sample_degrees([0], [0], seed=2, slots=slots)
+    assert np.array_equal(deg2.cpu().numpy(), deg.cpu().numpy())
 
 
 def test_batch_largest_ensemble_networks_match_oracle(mh):
