@@ -871,14 +871,14 @@ def main():
                     help="replicas of the Chung-Lu bias statistics (0: skip the Chung-Lu measurement)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
-    ap.add_argument("--batch-slot-buffer", type=int, default=1_000_000_000,
+    ap.add_argument("--batch-slot-buffer", type=int, default=4_000_000_000,
                     help="int32 slots of the staged degree sink's buffer")
     ap.add_argument("--skip-small", action="store_true", help="skip the N=2,000 timings")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="copy a buffer of this many MiB once first (reference for HBM byte counters)")
     ap.add_argument("--batch-networks", type=int, default=256)
     ap.add_argument("--batch-replicas", type=int, default=16)
-    ap.add_argument("--batch-edge-buffer", type=int, default=100_000_000,
+    ap.add_argument("--batch-edge-buffer", type=int, default=1_500_000_000,
                     help="edges per launch of the batched edge-output measurement")
     args = ap.parse_args()
 

@@ -53,6 +53,28 @@ __global__ __launch_bounds__(kThreads) void k_batch_zero_degrees(const NetDesc* 
     }
 }
 
+// The item table: item_tab[c] = the sample holding item c 2^shift, with the
+// least shift that keeps ceil(items / 2^shift) within kItemTab entries (one
+// thread per entry, a search among the samples each).
+constexpr int64_t kItemTab = int64_t(1) << 18;
+__global__ __launch_bounds__(kThreads) void k_batch_item_table(const uint64_t* __restrict__ item_off,
+                                                               int32_t n_samples, int32_t* __restrict__ tab,
+                                                               int32_t* __restrict__ shift_out) {
+    const uint64_t total = item_off[n_samples];
+    int32_t sh = 0;
+    while ((total + (uint64_t(1) << sh) - 1) >> sh > (uint64_t)kItemTab) ++sh;
+    const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (c == 0) *shift_out = sh;
+    if ((uint64_t)c >= (total + (uint64_t(1) << sh) - 1) >> sh) return;
+    const uint64_t it = (uint64_t)c << sh;
+    int32_t lo = 0, hi = n_samples;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (item_off[mid] <= it) lo = mid; else hi = mid;
+    }
+    tab[c] = lo;
+}
+
 // ---- staged degree counts (MH_BATCH_DEGREES_STAGED) ----
 // The sweep writes each accepted column's node id into the slot region of its
 // key (sample, window of 2^15 ids); one counting block per key then adds the
@@ -222,6 +244,8 @@ struct BatchLayout {
     uint64_t* net_win_off;     // per network (+1): its first window's bound
     double* est;               // per network and window: the bound on its column hits
     uint64_t* win_off;         // per sample (+1): its first key
+    int32_t* item_tab;         // kItemTab entries: the sample of every 2^item_shift-th item
+    int32_t* item_shift;
     std::vector<NetBuffers> bufs;
     void* scratch;
     size_t scratch_bytes;
@@ -244,6 +268,8 @@ bool layout(const mh_network* nets, int32_t n_networks, int32_t max_samples, voi
         s.take<uint64_t>((size_t)n_networks + 1);
         s.take<double>((size_t)tw);
         s.take<uint64_t>((size_t)max_samples + 1);
+        s.take<int32_t>((size_t)kItemTab);
+        s.take<int32_t>(1);
         bytes = s.used;
         for (int32_t i = 0; i < n_networks; ++i) {
             bytes = ((bytes + 255) & ~size_t(255)) + network_bytes(nets[i].n, nets[i].y != nullptr, nets[i].seg_work);
@@ -273,6 +299,8 @@ bool layout(const mh_network* nets, int32_t n_networks, int32_t max_samples, voi
     L->net_win_off = ar.take<uint64_t>((size_t)n_networks + 1);
     L->est = ar.take<double>((size_t)L->total_win);
     L->win_off = ar.take<uint64_t>((size_t)max_samples + 1);
+    L->item_tab = ar.take<int32_t>((size_t)kItemTab);
+    L->item_shift = ar.take<int32_t>(1);
     L->bufs.resize(n_networks);
     for (int32_t i = 0; i < n_networks; ++i) {
         Arena sub(ar.base + ((ar.used + 255) & ~size_t(255)), ws_bytes - ((ar.used + 255) & ~size_t(255)));
@@ -413,6 +441,9 @@ mh_status mh_batch_sample_async(const mh_network* nets, int32_t n_networks, int3
     MH_HIP_TRY(hipGetLastError());
     mh_status st = scan_exclusive_u64(L.item_off, L.item_off, n_samples, L.scratch, L.scratch_bytes, stream);
     if (st != MH_OK) return st;
+    hipLaunchKernelGGL(k_batch_item_table, dim3((unsigned)(kItemTab / kThreads)), dim3(kThreads), 0, stream,
+                       L.item_off, n_samples, L.item_tab, L.item_shift);
+    MH_HIP_TRY(hipGetLastError());
     if (mode != MH_BATCH_EDGES) {
         const dim3 zg(64, (unsigned)(n_samples < 4096 ? n_samples : 4096));
         hipLaunchKernelGGL(k_batch_zero_degrees, zg, dim3(kThreads), 0, stream, L.nets, n_networks, sample_net, deg_off,
@@ -442,6 +473,8 @@ mh_status mh_batch_sample_async(const mh_network* nets, int32_t n_networks, int3
     A.batch.sample_net = sample_net;
     A.batch.sample_rep = sample_rep;
     A.batch.item_off = L.item_off;
+    A.batch.item_tab = L.item_tab;
+    A.batch.item_shift = L.item_shift;
     A.batch.n_samples = n_samples;
     A.batch.degrees = degrees;
     A.batch.deg_off = deg_off;

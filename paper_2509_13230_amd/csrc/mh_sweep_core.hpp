@@ -138,6 +138,11 @@ struct BatchRef {
     const int32_t* sample_net;  // [n_samples]
     const uint32_t* sample_rep; // [n_samples]
     const uint64_t* item_off;   // [n_samples + 1] exclusive prefix of items
+    // item_tab[c]: the sample holding item c 2^item_shift[0] (c below
+    // ceil(items / 2^shift)), so that a lane finds an item's sample between
+    // two table entries instead of among all samples
+    const int32_t* item_tab;
+    const int32_t* item_shift;
     int32_t n_samples;
     int32_t* degrees;           // degree-sink output, or null
     const int64_t* deg_off;     // [n_samples] start of each sample's degree array
@@ -275,8 +280,12 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
     const uint64_t lt = lanemask_lt();
     int64_t total;
     int64_t H_single = 0;
+    int32_t ishift = 0;
+    int64_t nchunks = 0;
     if (BATCH) {
         total = (int64_t)A.batch.item_off[A.batch.n_samples];
+        ishift = *A.batch.item_shift;
+        nchunks = (total + (int64_t(1) << ishift) - 1) >> ishift;
     } else {
         H_single = heavy_items(A.net);
         total = H_single + light_rows(A.net);
@@ -463,7 +472,11 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
                     int64_t H = H_single;
                     const NetDesc* Dp = &A.net;
                     if (BATCH) {
-                        int32_t lo = 0, hi = A.batch.n_samples;  // sample with item_off <= it < next
+                        // sample with item_off <= it < next: between the samples of
+                        // the table's chunk starts around it
+                        const int64_t c = it >> ishift;
+                        int32_t lo = A.batch.item_tab[c];
+                        int32_t hi = c + 1 < nchunks ? A.batch.item_tab[c + 1] + 1 : A.batch.n_samples;
                         while (hi - lo > 1) {
                             const int32_t mid = (lo + hi) >> 1;
                             if (A.batch.item_off[mid] <= (uint64_t)it) lo = mid; else hi = mid;
