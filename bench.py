@@ -623,13 +623,16 @@ def atomic_add_rate(dev, slots: int = 1 << 22, blocks: int = 2048, iters: int = 
 
 def batched_ensemble(args, dev) -> dict:
     """The ensemble workload: 256 networks (N log-uniform in [1e3, 2e5],
-    x = exp(Normal(-5, 2))) x 16 replicas = 4,096 samples.  Times one
-    hipGraph-captured persistent launch over all samples (degree-sink output,
-    preparation of every network done once beforehand and timed separately)
-    against 4,096 plain single-sample samples (order + plan + sweep + edge
-    output each), issued back to back through the asynchronous entry point
-    (and, as a second figure, through the synchronous call, which reads each
-    sample's edge count back)."""
+    x = exp(Normal(-5, 2))) x 16 replicas = 4,096 samples, every network
+    prepared once beforehand (timed separately).  Times the batched sampler
+    writing edge lists (persistent launches over groups of samples whose edges
+    fit one buffer) against the same 4,096 samples through the plain
+    single-sample path (order + plan + sweep + edge output each), issued back
+    to back through the asynchronous entry point (and, as a second figure,
+    through the synchronous call, which reads each sample's edge count back);
+    and the two degree-sink modes: one hipGraph launch adding degrees by
+    atomics, and graphs over groups of samples counting columns through a slot
+    buffer."""
     import torch
 
     import paper_2509_13230_amd as mh
