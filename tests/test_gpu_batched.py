@@ -332,3 +332,7 @@ def test_batch_largest_ensemble_networks_match_oracle(mh):
     deg = deg.cpu().numpy()
     for s, (i, r) in enumerate(zip(net, rep)):
         _compare_degrees(deg[off[s]:off[s + 1]], ora[s], len(xs[i]), f"ensemble degrees {big[i]} replica {r}")
+    # the staged sink on the same samples (seven windows each): the atomic sink's degrees
+    slots = torch.empty(200_000_000, dtype=torch.int32, device="cuda")
+    sdeg, _ = b.sample_degrees(net, rep, seed=1, slots=slots)
+    assert np.array_equal(sdeg.cpu().numpy(), deg)
