@@ -762,9 +762,11 @@ def batched_ensemble(args, dev) -> dict:
     # one output buffer (src, dst and the sample index, int32 each), one
     # persistent launch per group, the buffer reused like the plain samples'
     group_cap = args.batch_edge_buffer
+    # room beyond a group's edges for the waves' output chunks (MH_BATCH_EDGE_SLACK)
+    group_edges = group_cap - mh.BATCH_EDGE_SLACK
     groups, cur, cur_edges = [], [], 0
     for s_i, c in enumerate(plain_counts):
-        if cur and cur_edges + c > group_cap:
+        if cur and cur_edges + c > group_edges:
             groups.append(cur)
             cur, cur_edges = [], 0
         cur.append(s_i)
@@ -812,7 +814,7 @@ def batched_ensemble(args, dev) -> dict:
         "replicas_per_s_plain": S / t_plain_async,
         "speedup_vs_plain": t_plain_async / t_batch_edges,
         "output": "edge lists (plain: src, dst; batched: src, dst and the sample index, in "
-                  f"{len(groups)} launches of up to {group_cap} edges)",
+                  f"{len(groups)} launches of up to {group_edges} edges)",
         "batched_edges_equal": edge_total == plain_edges,
         "edges_per_s_batched": edge_total / t_batch_edges,
         "valu_batched": valu(t_batch_edges),

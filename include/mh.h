@@ -255,7 +255,9 @@ typedef struct {
 
 #define MH_BATCH_EDGES 0   /* edges (src, dst[, w]) and optionally the sample index per edge (sid) */
 #define MH_BATCH_DEGREES 1 /* per-sample degree sequences: degrees[deg_off[s] + node id] */
-#define MH_BATCH_DEGREES_STAGED 2 /* the same sequences, columns counted through a slot buffer (src) */
+#define MH_BATCH_DEGREES_STAGED 2
+#define MH_BATCH_OUT_CHUNK 4096                /* edge output: slots a wave reserves at a time */
+#define MH_BATCH_EDGE_SLACK (4096ll * 4096ll)  /* edge output: room beyond the edges that always suffices */ /* the same sequences, columns counted through a slot buffer (src) */
 
 typedef struct {
     int32_t seg_work;    /* chosen plan parameter */
@@ -276,7 +278,12 @@ mh_status mh_batch_prepare(const mh_network* nets_host, int32_t n_networks, int3
  * (device int32/uint32 arrays; a network index outside [0, n_networks) fails
  * the call with MH_EINVAL, reported by mh_batch_result).  MH_BATCH_EDGES: up to `capacity` edges into
  * src/dst (w for weighted networks; sid[k] = sample of edge k, may be NULL),
- * order unspecified.  MH_BATCH_DEGREES: degrees[deg_off[s] + v] (device int32,
+ * order unspecified.  Each wave of the launch reserves output slots
+ * MH_BATCH_OUT_CHUNK at a time and the unused tails of the waves' last chunks
+ * are filled afterwards, so the call needs room for the edges plus one chunk
+ * per wave (4 waves per block, at most 4096 waves: MH_BATCH_EDGE_SLACK slots
+ * always suffice); otherwise mh_batch_result returns MH_ECAPACITY with a
+ * capacity that suffices (the edge count plus a chunk per wave).  MH_BATCH_DEGREES: degrees[deg_off[s] + v] (device int32,
  * offsets device int64; the caller's array must hold deg_off[s] + n of every
  * listed sample) is overwritten with node v's degree in sample s, every
  * accepted edge adding to its endpoints by a device atomic (the rate of random

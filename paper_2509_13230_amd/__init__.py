@@ -543,6 +543,7 @@ class ExpectedDegree(torch.autograd.Function):
 
 # ---------------------------------------------------------------------------- batched ensembles
 MH_BATCH_EDGES, MH_BATCH_DEGREES, MH_BATCH_DEGREES_STAGED = 0, 1, 2
+BATCH_EDGE_SLACK = 4096 * 4096  # MH_BATCH_EDGE_SLACK: room beyond the edges for the waves' output chunks
 
 
 class Network(ctypes.Structure):
@@ -644,7 +645,7 @@ class Batch:
         """(src, dst, w|None, sid) of every listed sample, order unspecified."""
         net, rep = self._refs(sample_net, sample_rep)
         cap = int(capacity) if capacity is not None else max(
-            4096, 4 * sum(self.sizes[i] for i in net.tolist() if 0 <= i < self.k))
+            4096, 4 * sum(self.sizes[i] for i in net.tolist() if 0 <= i < self.k)) + BATCH_EDGE_SLACK
         for _ in range(2):
             src = torch.empty(cap, dtype=torch.int32, device=self.device)
             dst = torch.empty(cap, dtype=torch.int32, device=self.device)

@@ -75,6 +75,165 @@ __global__ __launch_bounds__(kThreads) void k_batch_item_table(const uint64_t* _
     tab[c] = lo;
 }
 
+// ---- batched edge output: filling the chunks' unused tails ----
+// Each wave of the sweep reserved output slots kOutChunk at a time; every
+// chunk but a wave's last is full.  With G slots reserved and T unused in the
+// waves' last chunks, the list has n = G - T edges; the unused slots below n
+// (holes) take the edges found at n and beyond, so the list ends up in
+// [0, n).  The order of a batch's edges is unspecified, so any one-to-one
+// matching of holes and those edges does.
+constexpr int kMaxChunkWaves = 4096;  // waves of a launch with edge output (grid capped to match)
+constexpr int kGapThreads = 1024;
+constexpr int kGapPer = (kMaxChunkWaves + 2 + kGapThreads - 1) / kGapThreads;
+
+struct GapLists {
+    uint64_t* hole_pos;  // [kMaxChunkWaves]: first hole slot of wave w's last chunk below n
+    uint64_t* hole_off;  // [kMaxChunkWaves]: exclusive prefix of the holes' lengths
+    uint64_t* src_pos;   // [kMaxChunkWaves + 2]: first edge at or beyond n of chunk c0 + i
+    uint64_t* src_off;   // [kMaxChunkWaves + 2]: exclusive prefix of those edge counts
+    uint64_t* meta;      // [4]: holes H, waves W, chunks m
+};
+
+// Block-wide exclusive scan of v[0..count) (count <= kGapThreads * kGapPer),
+// each thread taking a run of kGapPer entries; returns the total.
+__device__ uint64_t gap_scan(const uint64_t* v, uint64_t* out, int count, uint64_t* s_part) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int b = t * kGapPer;
+    uint64_t run = 0;
+    for (int i = 0; i < kGapPer; ++i)
+        if (b + i < count) run += v[b + i];
+    uint64_t inc = run;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t u = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += u;
+    }
+    if (lane == 63) s_part[wave] = inc;
+    __syncthreads();
+    if (t == 0) {
+        uint64_t acc = 0;
+        for (int w = 0; w < kGapThreads / kWave; ++w) {
+            const uint64_t x = s_part[w];
+            s_part[w] = acc;
+            acc += x;
+        }
+        s_part[kGapThreads / kWave] = acc;
+    }
+    __syncthreads();
+    uint64_t pre = s_part[wave] + inc - run;
+    for (int i = 0; i < kGapPer; ++i)
+        if (b + i < count) {
+            out[b + i] = pre;
+            pre += v[b + i];
+        }
+    const uint64_t total = s_part[kGapThreads / kWave];
+    __syncthreads();
+    return total;
+}
+
+// One block: n, the holes below n and the edges at or beyond n, as lists with
+// prefixes; the call's edge count becomes n.  Reserved slots beyond the
+// capacity were not written: then the count reported is n plus a chunk per
+// wave, a capacity that suffices, and nothing moves.
+__global__ __launch_bounds__(kGapThreads) void k_gap_plan(Counters* ctr, const unsigned long long* __restrict__ rec,
+                                                         int32_t W, int64_t capacity, GapLists g) {
+    __shared__ uint64_t s_v[kGapThreads * kGapPer];
+    __shared__ uint32_t s_len[kGapThreads * kGapPer];
+    __shared__ uint64_t s_part[kGapThreads / kWave + 1];
+    __shared__ uint64_t s_sum[kGapThreads / kWave];
+    const int t = threadIdx.x;
+    if (ctr->status != 0) {
+        if (t == 0) g.meta[0] = 0;
+        return;
+    }
+    const uint64_t G = ctr->n_edges;
+    const uint64_t C = kOutChunk;
+    uint64_t tail = 0;
+    for (int w = t; w < W; w += kGapThreads)
+        if (rec[2 * w] != ~0ull) tail += C - rec[2 * w + 1];
+    tail = wave_sum(tail);
+    if ((t & 63) == 0) s_sum[t >> 6] = tail;
+    __syncthreads();
+    uint64_t T = 0;
+    for (int w = 0; w < kGapThreads / kWave; ++w) T += s_sum[w];
+    const uint64_t n = G - T;
+    if (G > (uint64_t)capacity) {
+        if (t == 0) {
+            g.meta[0] = 0;
+            ctr->n_edges = n + (uint64_t)W * C;
+        }
+        return;
+    }
+    // holes below n, one per wave's last chunk
+    for (int w = t; w < kGapThreads * kGapPer; w += kGapThreads) {
+        uint64_t h = 0, pos = 0;
+        if (w < W && rec[2 * w] != ~0ull) {
+            pos = rec[2 * w] + rec[2 * w + 1];
+            const uint64_t end = rec[2 * w] + C < n ? rec[2 * w] + C : n;
+            h = pos < end ? end - pos : 0;
+        }
+        s_v[w] = h;
+        if (w < W) g.hole_pos[w] = pos;
+    }
+    __syncthreads();
+    const uint64_t H = gap_scan(s_v, g.hole_off, W, s_part);
+    // edges at or beyond n: chunks c0 .. c1 - 1, full but for the waves' last ones
+    const uint64_t c0 = n / C, c1 = G / C;
+    const int m = (int)(c1 - c0);
+    for (int i = t; i < kGapThreads * kGapPer; i += kGapThreads) s_len[i] = (uint32_t)C;
+    __syncthreads();
+    for (int w = t; w < W; w += kGapThreads) {
+        const uint64_t st = rec[2 * w];
+        if (st != ~0ull && st / C >= c0 && st / C < c1) s_len[st / C - c0] = (uint32_t)rec[2 * w + 1];
+    }
+    __syncthreads();
+    for (int i = t; i < kGapThreads * kGapPer; i += kGapThreads) {
+        uint64_t len = 0, lo = 0;
+        if (i < m) {
+            const uint64_t start = (c0 + (uint64_t)i) * C;
+            lo = start > n ? start : n;
+            const uint64_t e = start + s_len[i];
+            len = e > lo ? e - lo : 0;
+            g.src_pos[i] = lo;
+        }
+        s_v[i] = len;
+    }
+    __syncthreads();
+    const uint64_t S = gap_scan(s_v, g.src_off, m, s_part);
+    if (t == 0) {
+        if (S != H) raise_status(&ctr->status, MH_EHIP);  // the two counts always agree
+        g.meta[0] = S == H ? H : 0;
+        g.meta[1] = (uint64_t)W;
+        g.meta[2] = (uint64_t)m;
+        ctr->n_edges = n;
+    }
+}
+
+// The moves: the k-th hole slot takes the k-th edge at or beyond n.
+__global__ __launch_bounds__(kThreads) void k_gap_move(GapLists g, int32_t* __restrict__ src, int32_t* __restrict__ dst,
+                                                      int32_t* __restrict__ w, int32_t* __restrict__ sid) {
+    const uint64_t H = g.meta[0];
+    const int32_t W = (int32_t)g.meta[1], m = (int32_t)g.meta[2];
+    for (uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x; k < H; k += (uint64_t)gridDim.x * kThreads) {
+        int32_t lo = 0, hi = W;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (g.hole_off[mid] <= k) lo = mid; else hi = mid;
+        }
+        const uint64_t p = g.hole_pos[lo] + (k - g.hole_off[lo]);
+        int32_t a = 0, b = m;
+        while (b - a > 1) {
+            const int32_t mid = (a + b) >> 1;
+            if (g.src_off[mid] <= k) a = mid; else b = mid;
+        }
+        const uint64_t q = g.src_pos[a] + (k - g.src_off[a]);
+        src[p] = src[q];
+        dst[p] = dst[q];
+        if (w) w[p] = w[q];
+        if (sid) sid[p] = sid[q];
+    }
+}
+
 // ---- staged degree counts (MH_BATCH_DEGREES_STAGED) ----
 // The sweep writes each accepted column's node id into the slot region of its
 // key (sample, window of 2^15 ids); one counting block per key then adds the
@@ -246,6 +405,8 @@ struct BatchLayout {
     uint64_t* win_off;         // per sample (+1): its first key
     int32_t* item_tab;         // kItemTab entries: the sample of every 2^item_shift-th item
     int32_t* item_shift;
+    unsigned long long* chunk_rec;  // edge output: per wave, its last chunk (start, used)
+    GapLists gap;
     std::vector<NetBuffers> bufs;
     void* scratch;
     size_t scratch_bytes;
@@ -270,6 +431,12 @@ bool layout(const mh_network* nets, int32_t n_networks, int32_t max_samples, voi
         s.take<uint64_t>((size_t)max_samples + 1);
         s.take<int32_t>((size_t)kItemTab);
         s.take<int32_t>(1);
+        s.take<unsigned long long>(2 * (size_t)kMaxChunkWaves);
+        s.take<uint64_t>((size_t)kMaxChunkWaves);
+        s.take<uint64_t>((size_t)kMaxChunkWaves);
+        s.take<uint64_t>((size_t)kMaxChunkWaves + 2);
+        s.take<uint64_t>((size_t)kMaxChunkWaves + 2);
+        s.take<uint64_t>(4);
         bytes = s.used;
         for (int32_t i = 0; i < n_networks; ++i) {
             bytes = ((bytes + 255) & ~size_t(255)) + network_bytes(nets[i].n, nets[i].y != nullptr, nets[i].seg_work);
@@ -301,6 +468,12 @@ bool layout(const mh_network* nets, int32_t n_networks, int32_t max_samples, voi
     L->win_off = ar.take<uint64_t>((size_t)max_samples + 1);
     L->item_tab = ar.take<int32_t>((size_t)kItemTab);
     L->item_shift = ar.take<int32_t>(1);
+    L->chunk_rec = ar.take<unsigned long long>(2 * (size_t)kMaxChunkWaves);
+    L->gap.hole_pos = ar.take<uint64_t>((size_t)kMaxChunkWaves);
+    L->gap.hole_off = ar.take<uint64_t>((size_t)kMaxChunkWaves);
+    L->gap.src_pos = ar.take<uint64_t>((size_t)kMaxChunkWaves + 2);
+    L->gap.src_off = ar.take<uint64_t>((size_t)kMaxChunkWaves + 2);
+    L->gap.meta = ar.take<uint64_t>(4);
     L->bufs.resize(n_networks);
     for (int32_t i = 0; i < n_networks; ++i) {
         Arena sub(ar.base + ((ar.used + 255) & ~size_t(255)), ws_bytes - ((ar.used + 255) & ~size_t(255)));
@@ -326,12 +499,15 @@ bool check_networks(const mh_network* nets, int32_t n_networks, bool* weighted) 
 }
 
 template <bool W, int OUT>
-mh_status launch_batch(const SweepLaunch& A, int32_t grid_blocks, hipStream_t stream) {
+mh_status launch_batch(const SweepLaunch& A, int32_t grid_blocks, hipStream_t stream, int64_t* grid_out = nullptr) {
     auto kern = k_sweep<W, false, true, OUT>;
-    const int64_t cap = resident_blocks(kern, kThreads);
+    int64_t cap = resident_blocks(kern, kThreads);
+    // edge output keeps one chunk record per wave
+    if (OUT == OUT_EDGES && cap > kMaxChunkWaves / kSweepWaves) cap = kMaxChunkWaves / kSweepWaves;
     const int64_t g = (grid_blocks > 0 && grid_blocks < cap) ? grid_blocks : cap;
     hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(kThreads), 0, stream, A);
     MH_HIP_TRY(hipGetLastError());
+    if (grid_out) *grid_out = g;
     return MH_OK;
 }
 
@@ -475,6 +651,7 @@ mh_status mh_batch_sample_async(const mh_network* nets, int32_t n_networks, int3
     A.batch.item_off = L.item_off;
     A.batch.item_tab = L.item_tab;
     A.batch.item_shift = L.item_shift;
+    A.batch.chunk_rec = L.chunk_rec;
     A.batch.n_samples = n_samples;
     A.batch.degrees = degrees;
     A.batch.deg_off = deg_off;
@@ -489,9 +666,20 @@ mh_status mh_batch_sample_async(const mh_network* nets, int32_t n_networks, int3
     A.out = EdgeOut{src, dst, w, mode == MH_BATCH_EDGES ? capacity : 0, &L.ctr->n_edges};
     A.sid = sid;
     A.ctr = L.ctr;
-    if (mode == MH_BATCH_EDGES)
-        return weighted ? launch_batch<true, OUT_EDGES>(A, grid_blocks, stream)
-                        : launch_batch<false, OUT_EDGES>(A, grid_blocks, stream);
+    if (mode == MH_BATCH_EDGES) {
+        int64_t g = 0;
+        st = weighted ? launch_batch<true, OUT_EDGES>(A, grid_blocks, stream, &g)
+                      : launch_batch<false, OUT_EDGES>(A, grid_blocks, stream, &g);
+        if (st != MH_OK) return st;
+        // the waves' unused chunk tails filled from the end of the list
+        hipLaunchKernelGGL(k_gap_plan, dim3(1), dim3(kGapThreads), 0, stream, L.ctr, L.chunk_rec,
+                           (int32_t)(g * kSweepWaves), capacity, L.gap);
+        MH_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_gap_move, dim3(1024), dim3(kThreads), 0, stream, L.gap, src, dst, weighted ? w : nullptr,
+                           sid);
+        MH_HIP_TRY(hipGetLastError());
+        return MH_OK;
+    }
     if (!staged)
         return weighted ? launch_batch<true, OUT_DEGREES>(A, grid_blocks, stream)
                         : launch_batch<false, OUT_DEGREES>(A, grid_blocks, stream);

@@ -13,6 +13,12 @@ namespace mh {
 
 constexpr int kStageEdges = 1024;              // per wave
 constexpr int kStageFlushAt = kStageEdges - kWave;
+// Batched edge output: a wave reserves output slots kOutChunk at a time
+// (flush_chunked), so that the one output counter sees an atomic per
+// kOutChunk edges; each wave's last chunk keeps an unused tail that a later
+// pass fills from the end of the list.
+constexpr uint32_t kOutChunk = 4096;
+static_assert(kStageEdges < (int)kOutChunk, "a staged run spans at most two chunks");
 
 struct EdgeOut {
     int32_t* src;
@@ -28,6 +34,7 @@ struct WaveStage {
     int32_t* s_dst;
     int32_t* s_w;
     uint32_t fill;  // wave-uniform
+    unsigned long long cpos = 0, cend = 0;  // flush_chunked: the wave's chunk [cend - kOutChunk, cend), next slot cpos
 
     __device__ __forceinline__ void push(bool acc, int32_t a, int32_t b, int32_t wt, const EdgeOut& out) {
         const uint64_t am = __ballot(acc);
@@ -42,7 +49,9 @@ struct WaveStage {
         if (fill > (uint32_t)kStageFlushAt) flush(out);
     }
 
-    // Variants that also stage a sample id per edge (s_sid, sid_out may be null).
+    // Variants that also stage a sample id per edge (s_sid, sid_out may be null);
+    // CHUNKED: runs go out through flush_chunked.
+    template <bool CHUNKED = false>
     __device__ __forceinline__ void push_sid(bool acc, int32_t a, int32_t b, int32_t wt, int32_t sample,
                                              int32_t* s_sid, const EdgeOut& out, int32_t* sid_out) {
         const uint64_t am = __ballot(acc);
@@ -55,7 +64,44 @@ struct WaveStage {
             if (s_sid) s_sid[o] = sample;
         }
         fill += (uint32_t)__popcll(am);
-        if (fill > (uint32_t)kStageFlushAt) flush_sid(s_sid, out, sid_out);
+        if (fill > (uint32_t)kStageFlushAt) {
+            if (CHUNKED) flush_chunked(s_sid, out, sid_out);
+            else flush_sid(s_sid, out, sid_out);
+        }
+    }
+
+    // The staged run into the wave's chunk, reserving the next chunk when the
+    // current one is full (a run fills at most one chunk and starts the next:
+    // kStageEdges < kOutChunk).  Slots at or beyond out.capacity are not written.
+    __device__ __forceinline__ void flush_chunked(const int32_t* s_sid, const EdgeOut& out, int32_t* sid_out) {
+        if (fill == 0) return;
+        __builtin_amdgcn_wave_barrier();
+        const int lane = (int)__lane_id();
+        uint32_t done = 0;
+        while (done < fill) {
+            if (cpos == cend) {
+                unsigned long long b = 0;
+                if (lane == 0) b = atomicAdd(out.count, (unsigned long long)kOutChunk);
+                b = __shfl(b, 0, kWave);
+                cpos = b;
+                cend = b + kOutChunk;
+            }
+            const uint32_t room = (uint32_t)(cend - cpos);
+            const uint32_t take = fill - done < room ? fill - done : room;
+            for (uint32_t k = (uint32_t)lane; k < take; k += kWave) {
+                const unsigned long long idx = cpos + k;
+                if (idx < (unsigned long long)out.capacity) {
+                    out.src[idx] = s_src[done + k];
+                    out.dst[idx] = s_dst[done + k];
+                    if (WEIGHTED) out.w[idx] = s_w[done + k];
+                    if (s_sid && sid_out) sid_out[idx] = s_sid[done + k];
+                }
+            }
+            cpos += take;
+            done += take;
+        }
+        __builtin_amdgcn_wave_barrier();
+        fill = 0;
     }
 
     __device__ __forceinline__ void flush_sid(const int32_t* s_sid, const EdgeOut& out, int32_t* sid_out) {

@@ -153,6 +153,9 @@ struct BatchRef {
     // beyond, straight to the degrees.  slot_wins: windows of the batch's
     // largest network (at most kSlotBins).
     int32_t* slots;
+    // OUT_EDGES: per wave of the launch, its last output chunk's start (or
+    // ~0 when it reserved none) and the slots of it used
+    unsigned long long* chunk_rec;
     const uint64_t* win_off;
     const uint64_t* region_off;
     const uint64_t* region_cap;
@@ -535,7 +538,7 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
             if (py) ry = *py;
             if (pc) rcc = *pc;
         }
-        if (OUT == OUT_EDGES) stage.push_sid(acc, id, dst_id, wt, acc_sample, s_sid, A.out, A.sid);
+        if (OUT == OUT_EDGES) stage.template push_sid<BATCH>(acc, id, dst_id, wt, acc_sample, s_sid, A.out, A.sid);
         if (OUT == OUT_SLOTS) {
             const uint64_t am = __ballot(acc);
             if (am) {
@@ -556,6 +559,14 @@ __device__ __forceinline__ uint32_t sweep_body(const SweepLaunch& A, int32_t* s_
     if (OUT == OUT_SLOTS) {
         flush_slots(s_dst, s_sid, s_src, stage.fill, A.batch);
         stage.fill = 0;
+    }
+    if (BATCH && OUT == OUT_EDGES) {
+        stage.flush_chunked(s_sid, A.out, A.sid);
+        if ((threadIdx.x & 63) == 0) {
+            const bool any = stage.cend != 0;
+            A.batch.chunk_rec[2 * gwave] = any ? stage.cend - kOutChunk : ~0ull;
+            A.batch.chunk_rec[2 * gwave + 1] = any ? stage.cpos - (stage.cend - kOutChunk) : 0ull;
+        }
     }
     if (STATS) {
         const unsigned long long v0 = wave_sum((unsigned long long)st_steps);

@@ -263,7 +263,7 @@ def test_graph_edge_replays_match_eager(mh):
     s0, d0, _, sid0 = b.sample_edges(net.cpu(), rep.cpu(), seed=2)
     k0 = np.sort(sid0.cpu().numpy().astype(np.int64) * 2**40 + s0.cpu().numpy().astype(np.int64) * 2000 +
                  d0.cpu().numpy())
-    cap = len(s0) + 1000
+    cap = len(s0) + mh.BATCH_EDGE_SLACK
     src = torch.empty(cap, dtype=torch.int32, device="cuda")
     dst = torch.empty(cap, dtype=torch.int32, device="cuda")
     sid = torch.empty(cap, dtype=torch.int32, device="cuda")
@@ -275,6 +275,37 @@ def test_graph_edge_replays_match_eager(mh):
         k = np.sort(sid[:m].cpu().numpy().astype(np.int64) * 2**40 + src[:m].cpu().numpy().astype(np.int64) * 2000 +
                     dst[:m].cpu().numpy())
         assert np.array_equal(k, k0)
+
+
+def test_edge_output_room_for_chunks(mh):
+    # each wave reserves its output 4096 slots at a time: at the exact edge
+    # count the call reports a capacity that suffices; the retry (the
+    # binding's) gives the same edges, and so do grids of one and three blocks
+    xs, _ = _nets(9, [3000, 1500, 700])
+    b = mh.Batch([dev(x) for x in xs], seg_work=8, max_samples=8)
+    net, rep = [0, 1, 2, 0], [0, 0, 1, 1]
+    s0, d0, _, sid0 = b.sample_edges(net, rep, seed=3)
+    n = len(s0)
+
+    def key(s, d, sid):
+        return np.sort(sid.cpu().numpy().astype(np.int64) * 2**40 + s.cpu().numpy().astype(np.int64) * 4096 +
+                       d.cpu().numpy())
+
+    k0 = key(s0, d0, sid0)
+    bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(3)]
+    b.sample_edges_async(torch.tensor(net, dtype=torch.int32, device="cuda"),
+                         torch.tensor(rep, dtype=torch.int32, device="cuda"), 3, bufs[0], bufs[1], None, bufs[2], n)
+    m = b.result(n)
+    assert m == n or -m > n  # not enough room for the chunks: a larger capacity is reported
+    s1, d1, _, sid1 = b.sample_edges(net, rep, seed=3, capacity=n)
+    assert np.array_equal(key(s1, d1, sid1), k0)
+    for grid in (1, 3):
+        s2, d2, _, sid2 = b.sample_edges(net, rep, seed=3, grid_blocks=grid)
+        assert np.array_equal(key(s2, d2, sid2), k0)
+    for i, (nn, r) in enumerate(zip(net, rep)):
+        ora = oracle.sample_mh(xs[nn], None, seed=3, replica=r, seg_work=8)
+        sel = sid0.cpu().numpy() == i
+        _compare_sample(s0.cpu().numpy(), d0.cpu().numpy(), None, sel, ora, len(xs[nn]), f"chunked sample {i}")
 
 
 def test_autotune_then_parity(mh):
