@@ -51,8 +51,8 @@ SWEEP_VALU_PER_STEP = 176
 # counters read for a 256 MiB copy (fetched bytes = 2 x FETCH_SIZE, written =
 # 1 x WRITE_SIZE).  They hold for the sweep built from the sources hashed in
 # SWEEP_SOURCES only; for any other build or input the bench reports null.
-SWEEP_COUNTERS = {"fetch_kib": 107059, "write_kib": 16365, "fetch_scale": 2.0, "write_scale": 1.0,
-                  "sources_sha256": "19774baa2f3abe1f9aa1cab6e8d8a9e41ab02f015ce2c461ab225b5d5df302a6",
+SWEEP_COUNTERS = {"fetch_kib": 107118, "write_kib": 16365, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sources_sha256": "c9d7b355f93c24aa5bf738ff85b732d26a132230fa0b6bd42f208f78cf3bd664",
                   "input_sha256": "bc9851eaa93191638377524467d37dbbae5a37d6523e29d9c327d955e13c3ef6",
                   "seg_work": 8}
 SWEEP_SOURCES = ["paper_2509_13230_amd/csrc/" + f for f in
