@@ -642,7 +642,10 @@ class Batch:
         return int(m.value) if st == MH_OK else -int(m.value)
 
     def sample_edges(self, sample_net, sample_rep, seed: int = 1, capacity: int | None = None, grid_blocks=0):
-        """(src, dst, w|None, sid) of every listed sample, order unspecified."""
+        """(src, dst, w|None, sid) of every listed sample, order unspecified.
+        capacity: output slots; the call needs the edges plus a chunk of
+        MH_BATCH_OUT_CHUNK slots per wave of the launch (BATCH_EDGE_SLACK always
+        suffices), and retries once with the capacity the library reports."""
         net, rep = self._refs(sample_net, sample_rep)
         cap = int(capacity) if capacity is not None else max(
             4096, 4 * sum(self.sizes[i] for i in net.tolist() if 0 <= i < self.k)) + BATCH_EDGE_SLACK
