@@ -165,3 +165,25 @@ def test_probe_library_exports_and_checks_arguments(L):
     assert f(fake, 1 << 31, 1, 1, None) == -1
     assert f(fake, 1024, 0, 1, None) == -1
     assert f(fake, 1024, 1, -1, None) == -1
+
+
+def test_binding_constants_match_header():
+    # the binding restates a few of the header's values; they must agree
+    import re
+
+    import paper_2509_13230_amd as mh
+
+    hdr = open(os.path.join(ROOT, "include", "mh.h")).read()
+
+    def define(name):
+        m = re.search(r"#define\s+" + name + r"\s+\(?([0-9]+)(?:ll)?(?:\s*\*\s*([0-9]+)(?:ll)?)?\)?", hdr)
+        assert m, name
+        return int(m.group(1)) * (int(m.group(2)) if m.group(2) else 1)
+
+    assert define("MH_BATCH_EDGES") == mh.MH_BATCH_EDGES
+    assert define("MH_BATCH_DEGREES") == mh.MH_BATCH_DEGREES
+    assert define("MH_BATCH_DEGREES_STAGED") == mh.MH_BATCH_DEGREES_STAGED
+    assert define("MH_BATCH_EDGE_SLACK") == mh.BATCH_EDGE_SLACK
+    # a chunk per wave, at most 4096 waves a launch
+    assert define("MH_BATCH_EDGE_SLACK") == define("MH_BATCH_OUT_CHUNK") * 4096
+    assert define("MH_NOALLOC_MAX_NODES") == mh.NOALLOC_MAX_NODES
