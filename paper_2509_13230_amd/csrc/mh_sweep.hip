@@ -597,10 +597,15 @@ __global__ __launch_bounds__(kHrThreads) void k_heavy_records(NetDesc D, HeavyRe
                 b_next = kk + 1 < ns && threadIdx.x + 1 < kHrThreads && it + 1 < lim;
                 int64_t lo[2], hi[2];
                 uint64_t v[2];
+                // interpolation points: P is xp[0] -> yp[0], xp[1] -> yp[1] (sample
+                // positions and values around the cut, then probed ones)
+                double xl[2], xr[2], yl[2], yr[2];
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int64_t k2 = kk + e;
                     v[e] = pb + (uint64_t)k2 * m;
+                    xl[e] = xr[e] = 0.0;
+                    yl[e] = yr[e] = 0.0;
                     if ((e == 0 && k2 == 0) || (e == 1 && (k2 == ns || b_next))) {
                         lo[e] = hi[e] = (e == 0) ? J : nc;
                         continue;
@@ -617,16 +622,52 @@ __global__ __launch_bounds__(kHrThreads) void k_heavy_records(NetDesc D, HeavyRe
                     if (chi < clo) chi = clo;
                     lo[e] = clo;
                     hi[e] = chi;
+                    if (ql > 0 && ql < (int)np) {
+                        xl[e] = (double)((int64_t)(ql - 1) * ps);
+                        yl[e] = (double)s_p[ql - 1];
+                        xr[e] = (double)((int64_t)ql * ps);
+                        yr[e] = (double)s_p[ql];
+                    }
                 }
-                while (lo[0] < hi[0] || lo[1] < hi[1]) {
-                    const int64_t m0 = lo[0] + (hi[0] - lo[0]) / 2, m1 = lo[1] + (hi[1] - lo[1]) / 2;
+                // The first two probes of each search where the line through the
+                // known points of P meets v (the masses within a bracket change
+                // slowly, so the cut is close), then bisection; each probe keeps
+                // the bracket exact, so the cut found is the same.
+                for (int step = 0; lo[0] < hi[0] || lo[1] < hi[1]; ++step) {
+                    int64_t mid[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        mid[e] = lo[e] + (hi[e] - lo[e]) / 2;
+                        if (step < 2 && lo[e] < hi[e] && yr[e] > yl[e]) {
+                            const double f = ((double)v[e] - yl[e]) / (yr[e] - yl[e]);
+                            const double x = xl[e] + f * (xr[e] - xl[e]);
+                            int64_t g = x < (double)lo[e] ? lo[e] : (x > (double)(hi[e] - 1) ? hi[e] - 1 : (int64_t)x);
+                            mid[e] = g;
+                        }
+                    }
                     const bool a0 = lo[0] < hi[0], a1 = lo[1] < hi[1];
-                    const uint64_t p0 = a0 ? D.P[m0] : 0, p1 = a1 ? D.P[m1] : 0;
+                    const uint64_t p0 = a0 ? D.P[mid[0]] : 0, p1 = a1 ? D.P[mid[1]] : 0;
                     if (a0) {
-                        if (p0 >= v[0]) hi[0] = m0; else lo[0] = m0 + 1;
+                        if (p0 >= v[0]) {
+                            hi[0] = mid[0];
+                            xr[0] = (double)mid[0];
+                            yr[0] = (double)p0;
+                        } else {
+                            lo[0] = mid[0] + 1;
+                            xl[0] = (double)mid[0];
+                            yl[0] = (double)p0;
+                        }
                     }
                     if (a1) {
-                        if (p1 >= v[1]) hi[1] = m1; else lo[1] = m1 + 1;
+                        if (p1 >= v[1]) {
+                            hi[1] = mid[1];
+                            xr[1] = (double)mid[1];
+                            yr[1] = (double)p1;
+                        } else {
+                            lo[1] = mid[1] + 1;
+                            xl[1] = (double)mid[1];
+                            yl[1] = (double)p1;
+                        }
                     }
                 }
                 a = lo[0];
