@@ -51,8 +51,8 @@ SWEEP_VALU_PER_STEP = 176
 # counters read for a 256 MiB copy (fetched bytes = 2 x FETCH_SIZE, written =
 # 1 x WRITE_SIZE).  They hold for the sweep built from the sources hashed in
 # SWEEP_SOURCES only; for any other build or input the bench reports null.
-SWEEP_COUNTERS = {"fetch_kib": 107118, "write_kib": 16365, "fetch_scale": 2.0, "write_scale": 1.0,
-                  "sources_sha256": "c9d7b355f93c24aa5bf738ff85b732d26a132230fa0b6bd42f208f78cf3bd664",
+SWEEP_COUNTERS = {"fetch_kib": 107300, "write_kib": 16366, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sources_sha256": "369d7138187e68df5636896cbf79f7f604a5aefa97c62fa74cf18adb8134a247",
                   "input_sha256": "bc9851eaa93191638377524467d37dbbae5a37d6523e29d9c327d955e13c3ef6",
                   "seg_work": 8}
 SWEEP_SOURCES = ["paper_2509_13230_amd/csrc/" + f for f in
