@@ -109,9 +109,17 @@ def fit_uecm(k_target, s_target, tol: float = 1e-8, max_newton: int = 200, cg_it
         h2 = torch.where(free_y, gy * y, torch.zeros_like(gy))
         return h1, h2
 
+    # The model needs y_i y_j < 1 for every pair of distinct nodes: the two
+    # largest y multiply below 1, and a class of several nodes (paired with
+    # itself) keeps y < 1; a class of one node may have y > 1.  (Its own pair
+    # has weight zero; the kernels still evaluate it, with b = y^2 > 1, and its
+    # terms stay finite unless 1 - b + ab is exactly 0.)
+    multi = mult >= 2
+
     def feasible(et_n):
         top = torch.topk(et_n, 2).values if et_n.numel() >= 2 else et_n
-        return et_n.numel() < 2 or float(top[0] + top[1]) < 0
+        ok = et_n.numel() < 2 or float(top[0] + top[1]) < 0
+        return ok and not bool((et_n[multi] >= 0).any())
 
     res_k = res_s = np.inf
     it = 0
@@ -154,7 +162,7 @@ def fit_uecm(k_target, s_target, tol: float = 1e-8, max_newton: int = 200, cg_it
         # line search on the directional derivative phi'(t) = d . grad(theta + t d) (convex):
         # keep t = 1 while phi' < 0 there, else bisect for phi' = 0 on [0, 1]
         def dphi(t):
-            et_n = torch.clamp(et + t * d2, max=-1e-12)
+            et_n = torch.where(multi, torch.clamp(et + t * d2, max=-1e-12), et + t * d2)
             if not feasible(et_n):
                 return None, None, None
             n1, n2, _, _ = grad(th + t * d1, et_n)

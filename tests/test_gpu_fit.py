@@ -127,3 +127,25 @@ def test_fit_uecm_then_sample_4sigma(mh):
         sd = M.std(0).cpu().numpy()
         z = (mean - target) / np.maximum(sd / np.sqrt(R), 1e-12)
         assert np.mean(np.abs(z) > 4) < 2e-3
+
+
+def test_fit_uecm_weighted_workload_reaches_targets(mh):
+    # the N = 200,000 weighted workload (degrees 2.3 on [1, 5000], strengths
+    # k (1 + Gamma(2, 3))): its largest strength-to-degree ratios need one
+    # node with y slightly above 1 (allowed: every pair of distinct nodes keeps
+    # y_i y_j < 1); the fit reaches the targets within 1e-8, and the sampler
+    # takes the fitted parameters, its mean degrees near the targets
+    from paper_2509_13230_amd.fit import fit_uecm
+
+    k, st = workloads.cfg3_targets(seed=3, n=200_000)
+    fit = fit_uecm(k, st, tol=1e-8, max_newton=100)
+    assert fit.residual <= 1e-8 and fit.residual_s <= 1e-8
+    ys = np.sort(fit.y)
+    assert ys[-1] * ys[-2] < 1.0
+    x, y = dev(fit.x), dev(fit.y)
+    kk, ss = mh.expected_degree(x, y)
+    assert np.max(np.abs(kk.cpu().numpy() - k) / k) <= 1e-8
+    src, dst, w = mh.sample_weighted(x, y, seed=2, seg_work=32)
+    deg = np.bincount(src.cpu().numpy(), minlength=len(k)) + np.bincount(dst.cpu().numpy(), minlength=len(k))
+    # one sample: the total degree within 4 sigma of the expected total
+    assert abs(deg.sum() - k.sum()) <= 4 * np.sqrt(k.sum()) + 1
